@@ -1,0 +1,216 @@
+"""Benchmark of the fused D2Q9 interface-capturing step on one MI355X.
+
+Workload (default): single vortex on an 8192 x 8192 periodic lattice, disk
+R = 0.15 N at (0.5 N, 0.75 N), eps = 1, tau = 0.8, delta = 1e-10, U = 0.02,
+period T = 4096 steps; FP32 collide with FP32 population storage.  W warm-up
+steps run first on a separate context; the timed run then starts from the
+initial field and covers K steps, so with K = T the L2 shape error is taken
+at the return time t = T.
+
+Prints ONE JSON line: MLUPS (whole job), the step kernel's achieved HBM
+bandwidth against the 8 TB/s peak (algorithmic bytes: every stored value
+read and written once per step), the L2 shape error, the same run with the
+16-bit shifted storage forms, and the CPU oracle timed on a bounded sample.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_f32_8192_hbm_counters.txt")
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lbac_kernels.hpp", "lbac.hip"):
+        with open(os.path.join(ROOT, "paper_2203_05230_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(bytes_per_launch_alg):
+    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    try:
+        kv = {}
+        with open(COUNTERS_FILE) as fh:
+            for line in fh:
+                if ":" in line:
+                    k, v = line.split(":", 1)
+                    kv[k.strip()] = v.strip()
+        if kv.get("kernel_source_sha") != kernel_source_hash():
+            return None
+        return float(kv["hbm_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False):
+    # a stream of our own: the library works on it and the events are recorded
+    # on it (torch's default stream has handle 0, which the library would
+    # replace by a private stream)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    assert stream.cuda_stream != 0
+    c = {**case, "precision": precision}
+    sim = lbac.Simulation(c, phi0, stream=stream.cuda_stream)
+    if launch:
+        sim.set_launch(*launch)
+    if autotune:
+        sim.autotune(4)
+    launch = sim.get_launch()
+    if warmup:
+        sim.step(warmup)
+    torch.cuda.synchronize()
+    sim.close()
+    # timed run from the initial field
+    sim = lbac.Simulation(c, phi0, stream=stream.cuda_stream)
+    sim.set_launch(*launch)
+    m0 = sim.mass()
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1)
+    e1, e2 = sim.shape_error(phi0)
+    m1 = sim.mass()
+    assert sim.stream() == stream.cuda_stream
+    out = dict(ms_total=ms, wall_s=wall, launch=list(launch), e1=e1, e2=e2, mass_drift=abs(m1 - m0) / m0,
+               bytes_per_node=sim.bytes_per_node(), t_end=sim.time())
+    sim.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    return out
+
+
+def cpu_baseline(phi0, case, steps):
+    """The FP64 oracle as it stands, on the host cores, for `steps` steps of the
+    same grid (a bounded sample of the workload)."""
+    from oracle import lib as O
+
+    p = O.Params(case["nx"], case["ny"], eps=case["eps"], tau=case["tau"], delta=case["delta"],
+                 vel_kind=O.VEL_VORTEX, U=case["U"], period_T=case["period_T"])
+    O.lib()
+    t0 = time.perf_counter()
+    O.run(p, phi0, 0)  # set-up alone (allocation, initial populations)
+    t1 = time.perf_counter()
+    O.run(p, phi0, steps)
+    t2 = time.perf_counter()
+    dt = (t2 - t1) - (t1 - t0)
+    threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+    return dict(value=case["nx"] * case["ny"] * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+                sample="%d steps of the %dx%d single vortex (FP64 oracle, OpenMP over rows); %.1f s of "
+                "stepping, set-up time subtracted" % (steps, case["nx"], case["ny"], dt))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=4096)
+    ap.add_argument("--warmup", type=int, default=256)
+    ap.add_argument("--n", type=int, default=8192)
+    ap.add_argument("--eps", type=float, default=1.0)
+    ap.add_argument("--period", type=float, default=4096.0)
+    ap.add_argument("--precision", default="f32")
+    ap.add_argument("--forms", default="f32_f16store,f32_bf16store",
+                    help="extra storage forms timed on the same workload ('' for none)")
+    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--launch", default="", help="bx,strip_h (default: autotune)")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
+                         "scaling HBM byte counters) and exit")
+    args = ap.parse_args()
+    if args.copy_calibration:
+        import torch
+
+        n = args.copy_calibration * (1 << 20) // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "launches": 3}), flush=True)
+        return
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on exactly one GPU: this build has no multi-GPU path (see the sharding notes "
+              "in DESIGN.md); rerun with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2203_05230_amd import lbac, workloads as W
+
+    lbac.load()
+    torch.cuda.set_device(0)
+    n = args.n
+    case = W.single_vortex_case(n, eps=args.eps, tau=0.8, U=0.02, period_T=args.period)
+    phi0 = W.circle(n, args.eps)
+    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    print("bench: %dx%d %s, warmup %d, steps %d" % (n, n, args.precision, args.warmup, args.steps),
+          file=sys.stderr, flush=True)
+    main_run = run_form(lbac, torch, case, phi0, args.precision, args.steps, args.warmup, launch=launch,
+                        autotune=launch is None)
+    nodes = n * n
+    ms_per_step = main_run["ms_total"] / args.steps
+    mlups = nodes * args.steps / (main_run["ms_total"] * 1e-3) / 1e6
+    alg_bytes = main_run["bytes_per_node"] * nodes
+    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    traffic = measured_traffic(alg_bytes)
+    forms = {}
+    for f in [s for s in args.forms.split(",") if s]:
+        print("bench: form %s" % f, file=sys.stderr, flush=True)
+        r = run_form(lbac, torch, case, phi0, f, args.steps, args.warmup, autotune=True)
+        fm = nodes * args.steps / (r["ms_total"] * 1e-3) / 1e6
+        forms[f] = dict(mlups=round(fm, 1), ms_per_step=round(r["ms_total"] / args.steps, 4),
+                        hbm_gbs=round(r["bytes_per_node"] * nodes / (r["ms_total"] / args.steps * 1e-3) / 1e9, 1),
+                        bytes_per_node=r["bytes_per_node"], e2=r["e2"], e1=r["e1"], mass_drift=r["mass_drift"],
+                        e2_vs_plain=r["e2"] / main_run["e2"] if main_run["e2"] > 0 else None,
+                        launch=r["launch"])
+    cpu = None
+    if args.cpu_steps > 0:
+        print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
+        cpu = cpu_baseline(phi0, case, args.cpu_steps)
+    line = {
+        "metric": "MLUPS + HBM GB/s (% peak), D2Q9 phase-field step; L2 shape error at t=T",
+        "value": round(mlups, 1),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"f64": "f64", "f32": "f32"}.get(args.precision, "f32"),
+        "data": "synthetic",
+        "config": {"workload": "single vortex %dx%d, eps=%g, tau=0.8, U=0.02, period T=%g steps, %s storage"
+                               % (n, n, args.eps, args.period, args.precision),
+                   "grid": n, "precision": args.precision, "launch": main_run["launch"]},
+        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(achieved / HBM_PEAK_GBS, 4),
+                     "traffic": None if traffic is None else round(traffic, 0),
+                     "algorithmic_bytes_per_launch": alg_bytes},
+        "shape_error": {"t": main_run["t_end"], "e2": main_run["e2"], "e1": main_run["e1"],
+                        "mass_drift": main_run["mass_drift"]},
+        "wall_s": round(main_run["wall_s"], 3),
+        "forms": forms,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

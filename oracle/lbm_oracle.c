@@ -65,7 +65,23 @@ typedef struct {
     double theta;      /* closure band: applied where theta < phi_clip < 1 - theta */
     int32_t mutation;  /* 0 in every real use; nonzero plants one known mistake
                           (MUT_*) so tests can show that the pins catch it */
+    double noise;      /* 0 in every real use; > 0 multiplies every post-collision
+                          population by (1 + noise xi), xi uniform in [-1, 1), to
+                          measure how the iteration amplifies rounding-sized errors */
+    uint64_t noise_seed;
 } orc_params;
+
+/* splitmix64 (Steele, Lea, Flood 2014): counter-based stream for the noise option */
+static uint64_t splitmix64(uint64_t z) {
+    z += 0x9e3779b97f4a7c15ull;
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+static double unit_noise(uint64_t seed, uint64_t counter) {
+    return (double)(splitmix64(seed ^ splitmix64(counter)) >> 11) * (2.0 / 9007199254740992.0) - 1.0;
+}
 
 enum {
     MUT_NONE = 0,
@@ -235,6 +251,7 @@ void orc_flux(const orc_params* p, const double* phi, int nx, int ny, double* fx
         for (size_t k = 0; k < n; ++k) fx[k] = fy[k] = NAN;
         return;
     }
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
         if (p->model == MODEL_CONVENTIONAL)
             src[k] = phi[k];
@@ -249,6 +266,7 @@ void orc_flux(const orc_params* p, const double* phi, int nx, int ny, double* fx
         gx = gy;
         gy = t;
     }
+#pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
         double mag = sqrt(gx[k] * gx[k] + gy[k] * gy[k]);
         double nxv = gx[k] / (mag + p->delta), nyv = gy[k] / (mag + p->delta);
@@ -311,6 +329,7 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
     for (int j = 0; j < lny; ++j) Yg[j] = wrap(oy + j, p->ny) + 0.5;
 
     /* initial state: equilibrium populations, (phi u) at t = 0 */
+#pragma omp parallel for schedule(static)
     for (int j = 0; j < lny; ++j)
         for (int i = 0; i < lnx; ++i) {
             size_t k = (size_t)j * lnx + i;
@@ -324,6 +343,7 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
 
     for (long step = 0; step <= nsteps; ++step) {
         /* Eq. (12) */
+#pragma omp parallel for schedule(static)
         for (size_t k = 0; k < n; ++k) {
             double s = 0.0;
             for (int q = 0; q < 9; ++q) s += f[q * n + k];
@@ -373,6 +393,8 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
                     double fi = f[q * n + k];
                     /* Eq. (9): collision, then push to x + c_q */
                     double post = fi - (fi - fe[q]) / tau + kf * F[q];
+                    if (p->noise > 0.0)
+                        post *= 1.0 + p->noise * unit_noise(p->noise_seed, ((uint64_t)step * n + k) * 9u + (uint64_t)q);
                     int ti = wrap(i + sdir * CX[q], lnx), tj = wrap(j + sdir * CY[q], lny);
                     fn[q * n + (size_t)tj * lnx + ti] = post;
                 }

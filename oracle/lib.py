@@ -30,6 +30,7 @@ class OrcParams(C.Structure):
         ("reading", C.c_int32), ("model", C.c_int32),
         ("mlp", C.POINTER(C.c_double)), ("theta", C.c_double),
         ("mutation", C.c_int32),
+        ("noise", C.c_double), ("noise_seed", C.c_uint64),
     ]
 
 
@@ -75,7 +76,8 @@ class Params:
 
     def __init__(self, nx, ny, eps=1.0, tau=0.8, delta=1e-10, vel_kind=VEL_VORTEX, U=0.02,
                  period_T=2000.0, omega=0.0, cx=None, cy=None, ux=0.0, uy=0.0,
-                 reading=READ_JAIN, model=MODEL_IMPROVED, mlp=None, theta=0.0, mutation=0):
+                 reading=READ_JAIN, model=MODEL_IMPROVED, mlp=None, theta=0.0, mutation=0, noise=0.0,
+                 noise_seed=0):
         self.nx, self.ny = int(nx), int(ny)
         self.eps, self.tau, self.delta = float(eps), float(tau), float(delta)
         self.vel_kind, self.U, self.period_T = int(vel_kind), float(U), float(period_T)
@@ -87,11 +89,13 @@ class Params:
         self.mlp = None if mlp is None else np.ascontiguousarray(mlp, dtype=np.float64)
         self.theta = float(theta)
         self.mutation = int(mutation)
+        self.noise, self.noise_seed = float(noise), int(noise_seed)
 
     def c(self):
         s = OrcParams(self.nx, self.ny, self.eps, self.tau, self.delta, self.vel_kind, self.U, self.period_T,
                       self.omega, self.cx, self.cy, self.ux, self.uy, self.reading, self.model,
-                      None if self.mlp is None else _dp(self.mlp), self.theta, self.mutation)
+                      None if self.mlp is None else _dp(self.mlp), self.theta, self.mutation, self.noise,
+                      self.noise_seed)
         return s
 
 

@@ -1,0 +1,695 @@
+// Host side of the lbac library: context, memory layout, launches, graph
+// replay, autotuning, reductions and the C ABI declared in include/lbac.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "lbac.h"
+#include "lbac_kernels.hpp"
+
+using namespace lbac;
+
+namespace {
+
+constexpr int kPlanePadBytes = 4096 + 256;  // staggers plane bases across HBM channels
+constexpr uint64_t kStateMagic = 0x4c42414353543031ull;  // "LBACST01"
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace
+
+struct lbac_ctx {
+    lbac_params p{};
+    lbac_allocator alloc{};
+    bool has_alloc = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int storage = ST_PLAIN;
+    int elem_bytes = 8;
+    int nplanes = 9;
+    int32_t pitch = 0;
+    int64_t plane_stride = 0;
+    void* pop[2] = {nullptr, nullptr};
+    float* phis[2] = {nullptr, nullptr};
+    double* vtab = nullptr;
+    int64_t* t_dev = nullptr;
+    double* rows = nullptr;
+    double* red5 = nullptr;
+    double* dtmp = nullptr;  // ny*nx doubles (phi0 upload, phi output, reference field)
+    double* host5 = nullptr; // pinned
+    int cur = 0;
+    int64_t t = 0;
+    int bx = 256, strip_h = 64;
+    int graph_chunk = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gexec_chunk[2] = {0, 0};
+    std::string err;
+};
+
+namespace {
+
+int fail(lbac_ctx* h, int code, const std::string& msg) {
+    if (h) h->err = msg;
+    return code;
+}
+
+#define HIPCHK(h, call)                                                                         \
+    do {                                                                                        \
+        hipError_t e_ = (call);                                                                 \
+        if (e_ != hipSuccess) return fail(h, LBAC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+void* dev_alloc(lbac_ctx* h, size_t bytes) {
+    if (h->has_alloc) return h->alloc.alloc(bytes, h->alloc.user);
+    void* ptr = nullptr;
+    if (hipMalloc(&ptr, bytes) != hipSuccess) return nullptr;
+    return ptr;
+}
+
+void dev_free(lbac_ctx* h, void* ptr) {
+    if (!ptr) return;
+    if (h->has_alloc)
+        h->alloc.free(ptr, h->alloc.user);
+    else
+        (void)hipFree(ptr);
+}
+
+void drop_graphs(lbac_ctx* h) {
+    for (int i = 0; i < 2; ++i) {
+        if (h->gexec[i]) (void)hipGraphExecDestroy(h->gexec[i]);
+        h->gexec[i] = nullptr;
+        h->gexec_chunk[i] = 0;
+    }
+}
+
+void release(lbac_ctx* h) {
+    if (h->stream) (void)hipStreamSynchronize(h->stream);
+    drop_graphs(h);
+    for (int i = 0; i < 2; ++i) {
+        dev_free(h, h->pop[i]);
+        dev_free(h, h->phis[i]);
+    }
+    dev_free(h, h->vtab);
+    dev_free(h, h->t_dev);
+    dev_free(h, h->rows);
+    dev_free(h, h->red5);
+    dev_free(h, h->dtmp);
+    if (h->host5) (void)hipHostFree(h->host5);
+    if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+}
+
+// Separable velocity tables: u = s(t) Ax[x] Ay[y], v = s(t) Bx[x] By[y].
+void build_velocity(const lbac_params& p, std::vector<double>& tab) {
+    const int nx = p.nx, ny = p.ny;
+    tab.assign(2 * (size_t)nx + 2 * (size_t)ny, 0.0);
+    double* Ax = tab.data();
+    double* Bx = Ax + nx;
+    double* Ay = Bx + nx;
+    double* By = Ay + ny;
+    const double PI = 3.14159265358979323846;
+    for (int i = 0; i < nx; ++i) {
+        const double X = i + 0.5, x = X / nx;
+        const double sx = std::sin(PI * x);
+        switch (p.vel_kind) {
+        case LBAC_VEL_VORTEX:
+            Ax[i] = -p.U * sx * sx;
+            Bx[i] = p.U * std::sin(2.0 * PI * x);
+            break;
+        case LBAC_VEL_VORTEX_PAPER:
+            Ax[i] = p.U * sx * sx;
+            Bx[i] = -p.U * std::sin(2.0 * PI * x);
+            break;
+        case LBAC_VEL_ROTATION:
+            Ax[i] = -p.omega;
+            Bx[i] = p.omega * (X - p.cx);
+            break;
+        case LBAC_VEL_UNIFORM:
+            Ax[i] = p.ux;
+            Bx[i] = p.uy;
+            break;
+        default:
+            break;
+        }
+    }
+    for (int j = 0; j < ny; ++j) {
+        const double Y = j + 0.5, y = Y / ny;
+        const double sy = std::sin(PI * y);
+        switch (p.vel_kind) {
+        case LBAC_VEL_VORTEX:
+        case LBAC_VEL_VORTEX_PAPER:
+            Ay[j] = std::sin(2.0 * PI * y);
+            By[j] = sy * sy;
+            break;
+        case LBAC_VEL_ROTATION:
+            Ay[j] = Y - p.cy;
+            By[j] = 1.0;
+            break;
+        case LBAC_VEL_UNIFORM:
+            Ay[j] = 1.0;
+            By[j] = 1.0;
+            break;
+        default:
+            break;
+        }
+    }
+}
+
+double time_period(const lbac_params& p) {
+    return (p.vel_kind == LBAC_VEL_VORTEX || p.vel_kind == LBAC_VEL_VORTEX_PAPER) ? p.period_T : 0.0;
+}
+
+StepArgs make_args(const lbac_ctx* h, int src, int32_t k) {
+    StepArgs a{};
+    a.src = h->pop[src];
+    a.dst = h->pop[1 - src];
+    a.src_phi = h->phis[src];
+    a.dst_phi = h->phis[1 - src];
+    a.plane_stride = h->plane_stride;
+    a.pitch = h->pitch;
+    a.nx = h->p.nx;
+    a.ny = h->p.ny;
+    a.strip_h = h->strip_h;
+    a.vtab = h->vtab;
+    a.t_dev = h->t_dev;
+    a.k = k;
+    a.period_T = time_period(h->p);
+    a.eps = h->p.eps;
+    a.tau = h->p.tau;
+    a.delta = h->p.delta;
+    return a;
+}
+
+template <typename R, int ST, int MODEL>
+hipError_t launch_step_bx(const StepArgs& a, int bx, hipStream_t s) {
+    dim3 grid((a.nx + bx - 1) / bx, (a.ny + a.strip_h - 1) / a.strip_h);
+    switch (bx) {
+    case 64:
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 64>), grid, dim3(64), 0, s, a);
+        break;
+    case 128:
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 128>), grid, dim3(128), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 256>), grid, dim3(256), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+template <typename R, int ST>
+hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a) {
+    if (h->p.model == LBAC_MODEL_CONVENTIONAL) return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, h->bx, h->stream);
+    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, h->bx, h->stream);
+}
+
+hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
+    const StepArgs a = make_args(h, src, k);
+    switch (h->p.precision) {
+    case LBAC_F64:
+        return launch_step_m<double, ST_PLAIN>(h, a);
+    case LBAC_F32:
+        return launch_step_m<float, ST_PLAIN>(h, a);
+    case LBAC_F32_F16STORE:
+        return launch_step_m<float, ST_F16>(h, a);
+    default:
+        return launch_step_m<float, ST_BF16>(h, a);
+    }
+}
+
+template <typename R, int ST>
+hipError_t launch_aux_t(const lbac_ctx* h, int which, const StepArgs& a, double* out, const double* ref,
+                        const double* phi0) {
+    dim3 g2((a.nx + 255) / 256, a.ny);
+    switch (which) {
+    case 0:
+        hipLaunchKernelGGL((init_kernel<R, ST>), g2, dim3(256), 0, h->stream, a, phi0);
+        break;
+    case 1:
+        hipLaunchKernelGGL((phi_kernel<R, ST>), g2, dim3(256), 0, h->stream, a, out);
+        break;
+    default:
+        hipLaunchKernelGGL((row_sums_kernel<R, ST>), dim3(a.ny), dim3(kRedThreads), 0, h->stream, a, ref, h->rows);
+        break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_aux(const lbac_ctx* h, int which, const StepArgs& a, double* out, const double* ref,
+                      const double* phi0) {
+    switch (h->p.precision) {
+    case LBAC_F64:
+        return launch_aux_t<double, ST_PLAIN>(h, which, a, out, ref, phi0);
+    case LBAC_F32:
+        return launch_aux_t<float, ST_PLAIN>(h, which, a, out, ref, phi0);
+    case LBAC_F32_F16STORE:
+        return launch_aux_t<float, ST_F16>(h, which, a, out, ref, phi0);
+    default:
+        return launch_aux_t<float, ST_BF16>(h, which, a, out, ref, phi0);
+    }
+}
+
+int validate(const lbac_params* p, std::string& why) {
+    if (!p) return why = "params is NULL", LBAC_EINVAL;
+    if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536 || (int64_t)p->nx * p->ny > (1ll << 31))
+        return why = "grid size out of range", LBAC_EINVAL;
+    if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return why = "tau must exceed 1/2", LBAC_EINVAL;
+    if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return why = "eps must be positive", LBAC_EINVAL;
+    if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return why = "delta must be >= 0", LBAC_EINVAL;
+    if (p->vel_kind < LBAC_VEL_ZERO || p->vel_kind > LBAC_VEL_VORTEX_PAPER) return why = "bad vel_kind", LBAC_EINVAL;
+    if ((p->vel_kind == LBAC_VEL_VORTEX || p->vel_kind == LBAC_VEL_VORTEX_PAPER) && !(p->period_T > 0.0))
+        return why = "vortex needs period_T > 0", LBAC_EINVAL;
+    if (p->precision < LBAC_F64 || p->precision > LBAC_F32_BF16STORE) return why = "bad precision", LBAC_EINVAL;
+    if (p->model != LBAC_MODEL_IMPROVED && p->model != LBAC_MODEL_CONVENTIONAL) return why = "bad model", LBAC_EINVAL;
+    if (p->alloc && (!p->alloc->alloc || !p->alloc->free)) return why = "allocator without alloc/free", LBAC_EINVAL;
+    std::vector<double> tab;
+    build_velocity(*p, tab);
+    double ma = 0, mb = 0, mc = 0, md = 0;
+    for (int i = 0; i < p->nx; ++i) {
+        ma = std::max(ma, std::fabs(tab[i]));
+        mb = std::max(mb, std::fabs(tab[p->nx + i]));
+    }
+    for (int j = 0; j < p->ny; ++j) {
+        mc = std::max(mc, std::fabs(tab[2 * (size_t)p->nx + j]));
+        md = std::max(md, std::fabs(tab[2 * (size_t)p->nx + p->ny + j]));
+    }
+    if (!std::isfinite(ma * mc + mb * md) || ma * mc + mb * md >= 1.0 / 3.0)
+        return why = "velocity too large: max |u| + |v| must stay below 1/3", LBAC_EINVAL;
+    return LBAC_OK;
+}
+
+int create(const lbac_params* p, const double* phi0, bool phi0_on_device, lbac_ctx** out) {
+    if (!out) return LBAC_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate(p, why);
+    if (rc != LBAC_OK) return rc;
+    if (!phi0) return LBAC_EINVAL;
+    const size_t n = (size_t)p->nx * p->ny;
+    if (!phi0_on_device)
+        for (size_t i = 0; i < n; ++i)
+            if (!std::isfinite(phi0[i])) return LBAC_EINVAL;
+
+    lbac_ctx* h = new (std::nothrow) lbac_ctx();
+    if (!h) return LBAC_ENOMEM;
+    h->p = *p;
+    if (p->alloc) {
+        h->alloc = *p->alloc;
+        h->has_alloc = true;
+    }
+    h->p.alloc = nullptr;
+    if (hipGetDevice(&h->device) != hipSuccess) {
+        delete h;
+        return LBAC_EDEVICE;
+    }
+    auto bail = [&](int code) {
+        release(h);
+        delete h;
+        return code;
+    };
+    if (p->stream) {
+        h->stream = (hipStream_t)p->stream;
+    } else {
+        if (hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking) != hipSuccess) return bail(LBAC_EDEVICE);
+        h->own_stream = true;
+    }
+    h->storage = p->precision == LBAC_F64 || p->precision == LBAC_F32 ? ST_PLAIN
+                 : (p->precision == LBAC_F32_F16STORE ? ST_F16 : ST_BF16);
+    h->elem_bytes = p->precision == LBAC_F64 ? 8 : (p->precision == LBAC_F32 ? 4 : 2);
+    h->nplanes = h->storage == ST_PLAIN ? 9 : 8;
+    h->pitch = (p->nx + 63) / 64 * 64;
+    h->plane_stride = (int64_t)h->pitch * p->ny + kPlanePadBytes / h->elem_bytes;
+    // default launch shape: full-width blocks when the grid allows, strips of 64 rows
+    h->bx = p->nx >= 256 ? 256 : (p->nx >= 128 ? 128 : 64);
+    h->strip_h = std::min(64, p->ny);
+    const size_t pop_bytes = (size_t)h->plane_stride * h->nplanes * h->elem_bytes;
+    const size_t phis_bytes = ((size_t)h->pitch * p->ny + 64) * sizeof(float);
+    for (int i = 0; i < 2; ++i) {
+        h->pop[i] = dev_alloc(h, pop_bytes);
+        if (!h->pop[i]) return bail(LBAC_ENOMEM);
+        if (h->storage != ST_PLAIN) {
+            h->phis[i] = (float*)dev_alloc(h, phis_bytes);
+            if (!h->phis[i]) return bail(LBAC_ENOMEM);
+        }
+    }
+    std::vector<double> tab;
+    build_velocity(h->p, tab);
+    h->vtab = (double*)dev_alloc(h, tab.size() * sizeof(double));
+    h->t_dev = (int64_t*)dev_alloc(h, 64);
+    h->rows = (double*)dev_alloc(h, 5 * sizeof(double) * (size_t)p->ny);
+    h->red5 = (double*)dev_alloc(h, 64);
+    h->dtmp = (double*)dev_alloc(h, n * sizeof(double));
+    if (!h->vtab || !h->t_dev || !h->rows || !h->red5 || !h->dtmp) return bail(LBAC_ENOMEM);
+    if (hipHostMalloc((void**)&h->host5, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        h->host5 = nullptr;
+        return bail(LBAC_ENOMEM);
+    }
+    if (hipMemcpyAsync(h->vtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
+        hipSuccess)
+        return bail(LBAC_EDEVICE);
+    const double* src0 = phi0;
+    if (!phi0_on_device) {
+        if (hipMemcpyAsync(h->dtmp, phi0, n * sizeof(double), hipMemcpyHostToDevice, h->stream) != hipSuccess)
+            return bail(LBAC_EDEVICE);
+        src0 = h->dtmp;
+    }
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, (int64_t)0);
+    StepArgs a = make_args(h, 1, 0);  // dst = pop[0]
+    if (launch_aux(h, 0, a, nullptr, nullptr, src0) != hipSuccess) return bail(LBAC_EDEVICE);
+    if (hipStreamSynchronize(h->stream) != hipSuccess) return bail(LBAC_EDEVICE);
+    h->cur = 0;
+    h->t = 0;
+    *out = h;
+    return LBAC_OK;
+}
+
+int capture_graph(lbac_ctx* h, int parity) {
+    if (h->gexec[parity] && h->gexec_chunk[parity] == h->graph_chunk) return LBAC_OK;
+    if (h->gexec[parity]) {
+        (void)hipGraphExecDestroy(h->gexec[parity]);
+        h->gexec[parity] = nullptr;
+    }
+    HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = hipSuccess;
+    for (int k = 0; k < h->graph_chunk && e == hipSuccess; ++k) e = launch_step(h, parity ^ (k & 1), k);
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, (int64_t)h->graph_chunk);
+        e = hipGetLastError();
+    }
+    hipGraph_t g = nullptr;
+    hipError_t e2 = hipStreamEndCapture(h->stream, &g);
+    if (e != hipSuccess || e2 != hipSuccess) {
+        if (g) (void)hipGraphDestroy(g);
+        return fail(h, LBAC_EDEVICE, std::string("graph capture: ") + hipGetErrorString(e != hipSuccess ? e : e2));
+    }
+    hipGraphExec_t ge = nullptr;
+    e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return fail(h, LBAC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+    h->gexec[parity] = ge;
+    h->gexec_chunk[parity] = h->graph_chunk;
+    return LBAC_OK;
+}
+
+// Runs the row-sum and row-reduce kernels; results land in host5[0..4].
+int reduce5(lbac_ctx* h, const double* ref_dev) {
+    StepArgs a = make_args(h, h->cur, 0);
+    HIPCHK(h, launch_aux(h, 2, a, nullptr, ref_dev, nullptr));
+    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedThreads), 0, h->stream, h->rows, h->p.ny, h->red5);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipMemcpyAsync(h->host5, h->red5, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LBAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void lbac_default_params(lbac_params* p, int32_t nx, int32_t ny) {
+    if (!p) return;
+    std::memset(p, 0, sizeof(*p));
+    p->nx = nx;
+    p->ny = ny;
+    p->eps = 1.0;
+    p->tau = 0.8;
+    p->delta = 1e-10;
+    p->vel_kind = LBAC_VEL_VORTEX;
+    p->U = 0.02;
+    p->period_T = 2000.0;
+    p->cx = 0.5 * nx;
+    p->cy = 0.5 * ny;
+    p->precision = LBAC_F64;
+    p->model = LBAC_MODEL_IMPROVED;
+}
+
+int lbac_init(const lbac_params* p, const double* phi0, lbac_ctx** out) { return create(p, phi0, false, out); }
+
+int lbac_init_device(const lbac_params* p, const double* phi0_device, lbac_ctx** out) {
+    return create(p, phi0_device, true, out);
+}
+
+int lbac_free(lbac_ctx* h) {
+    if (!h) return LBAC_OK;
+    DeviceGuard g(h->device);
+    release(h);
+    delete h;
+    return LBAC_OK;
+}
+
+int lbac_step(lbac_ctx* h, int64_t n) {
+    if (!h) return LBAC_EINVAL;
+    if (n < 0) return fail(h, LBAC_EINVAL, "negative step count");
+    DeviceGuard g(h->device);
+    if (!g.ok) return fail(h, LBAC_EDEVICE, "hipSetDevice failed");
+    int64_t done = 0;
+    if (h->graph_chunk > 0) {
+        while (n - done >= h->graph_chunk) {
+            int rc = capture_graph(h, h->cur);
+            if (rc != LBAC_OK) return rc;
+            HIPCHK(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
+            done += h->graph_chunk;  // chunk is even: the state is back in pop[cur]
+            h->t += h->graph_chunk;
+        }
+    }
+    const int64_t r = n - done;
+    for (int64_t k = 0; k < r; ++k) HIPCHK(h, launch_step(h, h->cur ^ (int)(k & 1), (int32_t)k));
+    if (r > 0) {
+        hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, r);
+        HIPCHK(h, hipGetLastError());
+        h->cur ^= (int)(r & 1);
+        h->t += r;
+    }
+    return LBAC_OK;
+}
+
+int lbac_phi_device(lbac_ctx* h, double* out_device) {
+    if (!h || !out_device) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    StepArgs a = make_args(h, h->cur, 0);
+    HIPCHK(h, launch_aux(h, 1, a, out_device, nullptr, nullptr));
+    return LBAC_OK;
+}
+
+int lbac_phi(lbac_ctx* h, double* out) {
+    if (!h || !out) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    int rc = lbac_phi_device(h, h->dtmp);
+    if (rc != LBAC_OK) return rc;
+    HIPCHK(h, hipMemcpyAsync(out, h->dtmp, sizeof(double) * (size_t)h->p.nx * h->p.ny, hipMemcpyDeviceToHost,
+                             h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    return LBAC_OK;
+}
+
+int lbac_mass(lbac_ctx* h, double* out) {
+    if (!h || !out) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    int rc = reduce5(h, nullptr);
+    if (rc != LBAC_OK) return rc;
+    *out = h->host5[0];
+    if (!std::isfinite(*out)) return fail(h, LBAC_ENONFINITE, "mass is not finite");
+    return LBAC_OK;
+}
+
+int lbac_shape_error(lbac_ctx* h, const double* ref, double* e1, double* e2) {
+    if (!h || !ref) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    const size_t n = (size_t)h->p.nx * h->p.ny;
+    HIPCHK(h, hipMemcpyAsync(h->dtmp, ref, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
+    int rc = reduce5(h, h->dtmp);
+    if (rc != LBAC_OK) return rc;
+    const double* r = h->host5;
+    const double v1 = r[1] / r[2], v2 = std::sqrt(r[3] / r[4]);
+    if (e1) *e1 = v1;
+    if (e2) *e2 = v2;
+    if (!std::isfinite(v1) || !std::isfinite(v2)) return fail(h, LBAC_ENONFINITE, "shape error is not finite");
+    return LBAC_OK;
+}
+
+int lbac_time(lbac_ctx* h, int64_t* t) {
+    if (!h || !t) return LBAC_EINVAL;
+    *t = h->t;
+    return LBAC_OK;
+}
+
+int lbac_get_state(lbac_ctx* h, void* buf, size_t* bytes) {
+    if (!h || !bytes) return LBAC_EINVAL;
+    const size_t plane = (size_t)h->pitch * h->p.ny * h->elem_bytes;
+    const size_t phib = h->storage == ST_PLAIN ? 0 : (size_t)h->pitch * h->p.ny * sizeof(float);
+    const size_t need = 64 + plane * h->nplanes + phib;
+    if (!buf) {
+        *bytes = need;
+        return LBAC_OK;
+    }
+    if (*bytes < need) return fail(h, LBAC_EINVAL, "state buffer too small");
+    DeviceGuard g(h->device);
+    unsigned char* b = (unsigned char*)buf;
+    std::memset(b, 0, 64);
+    uint64_t magic = kStateMagic;
+    int32_t hdr[4] = {h->p.nx, h->p.ny, h->p.precision, h->nplanes};
+    std::memcpy(b, &magic, 8);
+    std::memcpy(b + 8, hdr, 16);
+    std::memcpy(b + 24, &h->t, 8);
+    unsigned char* d = b + 64;
+    for (int q = 0; q < h->nplanes; ++q) {
+        HIPCHK(h, hipMemcpyAsync(d + q * plane, (char*)h->pop[h->cur] + (size_t)q * h->plane_stride * h->elem_bytes,
+                                 plane, hipMemcpyDeviceToHost, h->stream));
+    }
+    if (phib) HIPCHK(h, hipMemcpyAsync(d + h->nplanes * plane, h->phis[h->cur], phib, hipMemcpyDeviceToHost, h->stream));
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    *bytes = need;
+    return LBAC_OK;
+}
+
+int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
+    if (!h || !buf) return LBAC_EINVAL;
+    const size_t plane = (size_t)h->pitch * h->p.ny * h->elem_bytes;
+    const size_t phib = h->storage == ST_PLAIN ? 0 : (size_t)h->pitch * h->p.ny * sizeof(float);
+    const size_t need = 64 + plane * h->nplanes + phib;
+    if (bytes < need) return fail(h, LBAC_EINVAL, "state blob too small");
+    const unsigned char* b = (const unsigned char*)buf;
+    uint64_t magic;
+    int32_t hdr[4];
+    int64_t t;
+    std::memcpy(&magic, b, 8);
+    std::memcpy(hdr, b + 8, 16);
+    std::memcpy(&t, b + 24, 8);
+    if (magic != kStateMagic || hdr[0] != h->p.nx || hdr[1] != h->p.ny || hdr[2] != h->p.precision ||
+        hdr[3] != h->nplanes || t < 0)
+        return fail(h, LBAC_EINVAL, "state blob does not match this context");
+    DeviceGuard g(h->device);
+    const unsigned char* d = b + 64;
+    for (int q = 0; q < h->nplanes; ++q)
+        HIPCHK(h, hipMemcpyAsync((char*)h->pop[h->cur] + (size_t)q * h->plane_stride * h->elem_bytes, d + q * plane,
+                                 plane, hipMemcpyHostToDevice, h->stream));
+    if (phib) HIPCHK(h, hipMemcpyAsync(h->phis[h->cur], d + h->nplanes * plane, phib, hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(set_time_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, t);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->t = t;
+    return LBAC_OK;
+}
+
+int lbac_set_launch(lbac_ctx* h, int32_t bx, int32_t strip_h) {
+    if (!h) return LBAC_EINVAL;
+    if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
+    if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
+    h->bx = bx;
+    h->strip_h = std::min(strip_h, h->p.ny);
+    drop_graphs(h);
+    return LBAC_OK;
+}
+
+int lbac_get_launch(lbac_ctx* h, int32_t* bx, int32_t* strip_h) {
+    if (!h) return LBAC_EINVAL;
+    if (bx) *bx = h->bx;
+    if (strip_h) *strip_h = h->strip_h;
+    return LBAC_OK;
+}
+
+int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
+    if (!h || steps < 1) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    const int bxs[3] = {64, 128, 256};
+    const int hs[7] = {8, 16, 32, 64, 128, 256, 512};
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    const int keep_bx = h->bx, keep_h = h->strip_h;
+    int best_bx = keep_bx, best_h = keep_h;
+    float best = 1e30f;
+    hipError_t e = hipSuccess;
+    for (int bx : bxs) {
+        if (bx > 64 && bx / 2 >= h->p.nx) continue;
+        for (int sh : hs) {
+            if (sh > h->p.ny && sh != hs[0]) continue;
+            h->bx = bx;
+            h->strip_h = std::min(sh, h->p.ny);
+            // repeated step from pop[cur] into the scratch buffer: the state is untouched
+            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(h, h->cur, 0);
+            if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+            for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step(h, h->cur, 0);
+            if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) break;
+            if (ms < best) {
+                best = ms;
+                best_bx = bx;
+                best_h = h->strip_h;
+            }
+        }
+        if (e != hipSuccess) break;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->bx = best_bx;
+    h->strip_h = best_h;
+    drop_graphs(h);
+    if (e != hipSuccess) {
+        h->bx = keep_bx;
+        h->strip_h = keep_h;
+        return fail(h, LBAC_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
+    }
+    if (us_per_step) *us_per_step = 1000.0 * best / steps;
+    return LBAC_OK;
+}
+
+int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk) {
+    if (!h) return LBAC_EINVAL;
+    if (chunk < 0 || (chunk & 1)) return fail(h, LBAC_EINVAL, "graph chunk must be an even number >= 0");
+    h->graph_chunk = chunk;
+    drop_graphs(h);
+    return LBAC_OK;
+}
+
+int lbac_bytes_per_node(lbac_ctx* h, double* bytes) {
+    if (!h || !bytes) return LBAC_EINVAL;
+    // read and write of every stored value once per step
+    *bytes = 2.0 * (h->nplanes * h->elem_bytes + (h->storage == ST_PLAIN ? 0 : 4));
+    return LBAC_OK;
+}
+
+void* lbac_stream(lbac_ctx* h) { return h ? (void*)h->stream : nullptr; }
+
+const char* lbac_strerror(int code) {
+    switch (code) {
+    case LBAC_OK:
+        return "ok";
+    case LBAC_EINVAL:
+        return "invalid argument";
+    case LBAC_ENOMEM:
+        return "out of memory";
+    case LBAC_EDEVICE:
+        return "device error";
+    case LBAC_ENONFINITE:
+        return "non-finite result";
+    case LBAC_ESTATE:
+        return "invalid state";
+    default:
+        return "unknown status";
+    }
+}
+
+const char* lbac_last_error(lbac_ctx* h) { return h ? h->err.c_str() : "no context"; }
+
+}  // extern "C"

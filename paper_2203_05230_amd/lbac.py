@@ -1,0 +1,247 @@
+"""Python binding of liblbac.so (the C ABI in include/lbac.h).
+
+Argument marshalling only: every step of the scheme runs in the HIP kernels
+of the library.  The functions keep the C names (lbac_init, lbac_step,
+lbac_phi, lbac_mass, ...); `Simulation` wraps a context for convenience.
+PyTorch supplies the stream (its current stream) and, optionally, device
+memory through its caching allocator.
+
+There is no fallback: if the library cannot be loaded, `load()` raises.
+"""
+import ctypes as C
+import os
+
+import numpy as np
+
+from . import build as _build
+
+LBAC_OK, LBAC_EINVAL, LBAC_ENOMEM, LBAC_EDEVICE, LBAC_ENONFINITE, LBAC_ESTATE = 0, -1, -2, -3, -4, -5
+VEL = {"zero": 0, "vortex": 1, "rotation": 2, "uniform": 3, "vortex_paper": 4}
+PRECISION = {"f64": 0, "f32": 1, "f32_f16store": 2, "f32_bf16store": 3}
+MODEL = {"improved": 0, "conventional": 1}
+
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class lbac_allocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("user", C.c_void_p)]
+
+
+class lbac_params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32),
+        ("eps", C.c_double), ("tau", C.c_double), ("delta", C.c_double),
+        ("vel_kind", C.c_int32),
+        ("U", C.c_double), ("period_T", C.c_double),
+        ("omega", C.c_double), ("cx", C.c_double), ("cy", C.c_double),
+        ("ux", C.c_double), ("uy", C.c_double),
+        ("precision", C.c_int32), ("model", C.c_int32),
+        ("stream", C.c_void_p),
+        ("alloc", C.POINTER(lbac_allocator)),
+    ]
+
+
+EXPORTS = [
+    "lbac_default_params", "lbac_init", "lbac_init_device", "lbac_free", "lbac_step", "lbac_phi",
+    "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
+    "lbac_set_launch", "lbac_get_launch", "lbac_autotune", "lbac_set_graph_chunk", "lbac_bytes_per_node",
+    "lbac_stream", "lbac_strerror", "lbac_last_error",
+]
+
+_lib = None
+
+
+def lib_path():
+    return _build.LIB
+
+
+def load():
+    """Loads liblbac.so (building it first only if no built library exists)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    path = lib_path()
+    if not os.path.exists(path):
+        _build.build()
+    L = C.CDLL(path)
+    P = C.POINTER
+    ctx_pp = P(C.c_void_p)
+    dp = P(C.c_double)
+    L.lbac_default_params.argtypes = [P(lbac_params), C.c_int32, C.c_int32]
+    L.lbac_default_params.restype = None
+    L.lbac_init.argtypes = [P(lbac_params), dp, ctx_pp]
+    L.lbac_init_device.argtypes = [P(lbac_params), C.c_void_p, ctx_pp]
+    L.lbac_free.argtypes = [C.c_void_p]
+    L.lbac_step.argtypes = [C.c_void_p, C.c_int64]
+    L.lbac_phi.argtypes = [C.c_void_p, dp]
+    L.lbac_phi_device.argtypes = [C.c_void_p, C.c_void_p]
+    L.lbac_mass.argtypes = [C.c_void_p, dp]
+    L.lbac_shape_error.argtypes = [C.c_void_p, dp, dp, dp]
+    L.lbac_time.argtypes = [C.c_void_p, P(C.c_int64)]
+    L.lbac_get_state.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
+    L.lbac_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
+    L.lbac_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.lbac_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+    L.lbac_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
+    L.lbac_set_graph_chunk.argtypes = [C.c_void_p, C.c_int32]
+    L.lbac_bytes_per_node.argtypes = [C.c_void_p, dp]
+    L.lbac_stream.argtypes = [C.c_void_p]
+    L.lbac_stream.restype = C.c_void_p
+    L.lbac_strerror.argtypes = [C.c_int]
+    L.lbac_strerror.restype = C.c_char_p
+    L.lbac_last_error.argtypes = [C.c_void_p]
+    L.lbac_last_error.restype = C.c_char_p
+    for name in EXPORTS:
+        if name not in ("lbac_default_params", "lbac_stream", "lbac_strerror", "lbac_last_error"):
+            getattr(L, name).restype = C.c_int
+    _lib = L
+    return L
+
+
+class LbacError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("lbac error %d (%s): %s" % (code, load().lbac_strerror(code).decode(), msg))
+        self.code = code
+
+
+def _check(rc, ctx=None, what=""):
+    if rc != LBAC_OK:
+        msg = load().lbac_last_error(ctx).decode() if ctx else what
+        raise LbacError(rc, msg or what)
+
+
+def _dp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_double))
+
+
+def make_params(nx, ny, eps=1.0, tau=0.8, delta=1e-10, vel="vortex", U=0.02, period_T=2000.0, omega=0.0,
+                cx=None, cy=None, ux=0.0, uy=0.0, precision="f64", model="improved", stream=None, **_ignored):
+    p = lbac_params()
+    load().lbac_default_params(C.byref(p), int(nx), int(ny))
+    p.eps, p.tau, p.delta = float(eps), float(tau), float(delta)
+    p.vel_kind = VEL[vel] if isinstance(vel, str) else int(vel)
+    p.U, p.period_T, p.omega = float(U), float(period_T), float(omega)
+    p.cx = 0.5 * nx if cx is None else float(cx)
+    p.cy = 0.5 * ny if cy is None else float(cy)
+    p.ux, p.uy = float(ux), float(uy)
+    p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.model = MODEL[model] if isinstance(model, str) else int(model)
+    p.stream = stream
+    return p
+
+
+class TorchAllocator:
+    """Routes the library's device allocations through torch's caching allocator."""
+
+    def __init__(self, device=None):
+        import torch
+
+        self.torch = torch
+        self.device = torch.cuda.current_device() if device is None else device
+        self._alloc = _ALLOC_FN(self._do_alloc)
+        self._free = _FREE_FN(self._do_free)
+        self.struct = lbac_allocator(self._alloc, self._free, None)
+
+    def _do_alloc(self, nbytes, user):
+        try:
+            s = self.torch.cuda.current_stream(self.device)
+            return self.torch.cuda.caching_allocator_alloc(int(nbytes), self.device, s)
+        except Exception:
+            return None
+
+    def _do_free(self, ptr, user):
+        if ptr:
+            self.torch.cuda.caching_allocator_delete(ptr)
+
+
+class Simulation:
+    """One lattice run on the current GPU.  `case` keys mirror lbac_params."""
+
+    def __init__(self, case, phi0, stream=None, torch_alloc=False):
+        L = load()
+        self._keep = []
+        p = make_params(**{**case, "stream": stream})
+        if torch_alloc:
+            ta = TorchAllocator()
+            self._keep.append(ta)
+            p.alloc = C.pointer(ta.struct)
+        self.nx, self.ny = p.nx, p.ny
+        self.params = p
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(p.ny, p.nx)
+        h = C.c_void_p()
+        _check(L.lbac_init(C.byref(p), _dp(phi0), C.byref(h)), what="lbac_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbac_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n):
+        _check(load().lbac_step(self.h, int(n)), self.h)
+
+    def phi(self):
+        out = np.empty((self.ny, self.nx))
+        _check(load().lbac_phi(self.h, _dp(out)), self.h)
+        return out
+
+    def phi_device(self, out_ptr):
+        _check(load().lbac_phi_device(self.h, C.c_void_p(out_ptr)), self.h)
+
+    def mass(self):
+        m = C.c_double()
+        _check(load().lbac_mass(self.h, C.byref(m)), self.h)
+        return m.value
+
+    def shape_error(self, ref):
+        ref = np.ascontiguousarray(ref, dtype=np.float64)
+        e1, e2 = C.c_double(), C.c_double()
+        _check(load().lbac_shape_error(self.h, _dp(ref), C.byref(e1), C.byref(e2)), self.h)
+        return e1.value, e2.value
+
+    def time(self):
+        t = C.c_int64()
+        _check(load().lbac_time(self.h, C.byref(t)), self.h)
+        return t.value
+
+    def get_state(self):
+        n = C.c_size_t()
+        _check(load().lbac_get_state(self.h, None, C.byref(n)), self.h)
+        buf = np.empty(n.value, dtype=np.uint8)
+        _check(load().lbac_get_state(self.h, buf.ctypes.data_as(C.c_void_p), C.byref(n)), self.h)
+        return buf
+
+    def set_state(self, buf):
+        buf = np.ascontiguousarray(buf, dtype=np.uint8)
+        _check(load().lbac_set_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), self.h)
+
+    def set_launch(self, bx, strip_h):
+        _check(load().lbac_set_launch(self.h, int(bx), int(strip_h)), self.h)
+
+    def get_launch(self):
+        bx, sh = C.c_int32(), C.c_int32()
+        _check(load().lbac_get_launch(self.h, C.byref(bx), C.byref(sh)), self.h)
+        return bx.value, sh.value
+
+    def autotune(self, steps=10):
+        us = C.c_double()
+        _check(load().lbac_autotune(self.h, int(steps), C.byref(us)), self.h)
+        return us.value
+
+    def set_graph_chunk(self, chunk):
+        _check(load().lbac_set_graph_chunk(self.h, int(chunk)), self.h)
+
+    def bytes_per_node(self):
+        b = C.c_double()
+        _check(load().lbac_bytes_per_node(self.h, C.byref(b)), self.h)
+        return b.value
+
+    def stream(self):
+        return load().lbac_stream(self.h)
