@@ -163,6 +163,53 @@ int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
 /* hipStream_t of the context. */
 void* lbac_stream(lbac_ctx* h);
 
+/* ---- batched form --------------------------------------------------------
+ * Many independent lattices (instances) of uneven sizes and parameters
+ * advanced together by ONE persistent kernel launch, replayed from a captured
+ * HIP graph.  Work is split into (instance, 60-column block, strip) items
+ * assigned to resident workgroups longest-first; an item waits for its eight
+ * neighbours of the previous step through per-item progress counters (no
+ * grid-wide barrier), so instances retire independently.  Every instance uses
+ * FP32 collide and storage and the improved model; results are bitwise those
+ * of lbac_step on the same instance.  Requires the GPU to itself (all
+ * workgroups resident); a wait that exceeds the time-out makes every
+ * workgroup exit and the run return LBAC_EDEVICE. */
+typedef struct lbac_batch lbac_batch;
+
+/* params[k], phi0[k] (host, ny*nx doubles): instance k, k < count.  The stream
+ * of params[0] (or a private one) is used for the whole batch; allocators are
+ * honoured per instance.  Errors as lbac_init, plus LBAC_EINVAL for a
+ * precision other than LBAC_F32 or a model other than LBAC_MODEL_IMPROVED. */
+int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_t count, lbac_batch** out);
+int lbac_batch_free(lbac_batch* b);
+
+/* Advances instance k by nsteps[k] >= 0 steps (host array of count values) in
+ * one persistent launch.  Synchronous.  LBAC_EDEVICE if a dependency wait
+ * timed out (state then undefined). */
+int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
+
+/* Context of instance k, owned by the batch: use it with lbac_phi, lbac_mass,
+ * lbac_shape_error, lbac_time, lbac_get_state / lbac_set_state (lbac_free on
+ * it returns LBAC_ESTATE). */
+int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
+int lbac_batch_count(lbac_batch* b, int32_t* count);
+
+/* Strip height (rows per item, >= 2) and workgroup count (0: the occupancy
+ * limit, which is also the maximum). */
+int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups);
+int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, int32_t* max_workgroups);
+
+/* Times strip heights and workgroup counts on `steps` steps of every instance
+ * (reading the current state, writing only scratch: state and time unchanged)
+ * and keeps the fastest; *ms (may be NULL) gets its time. */
+int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms);
+
+/* Time-out of one dependency wait (default 20 s).  test_stall != 0 makes
+ * every wait ask for a step that never completes, so that the time-out path
+ * can be tested: each workgroup exits after `seconds`. */
+int lbac_batch_set_timeout(lbac_batch* b, double seconds, int32_t test_stall);
+const char* lbac_batch_last_error(lbac_batch* b);
+
 /* Text of a status code, and of the last failure of a context. */
 const char* lbac_strerror(int code);
 const char* lbac_last_error(lbac_ctx* h);

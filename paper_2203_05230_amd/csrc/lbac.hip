@@ -11,71 +11,17 @@
 #include <string>
 #include <vector>
 
-#include "lbac.h"
-#include "lbac_kernels.hpp"
+#include "lbac_internal.hpp"
 
 using namespace lbac;
+using namespace lbac_host;
 
-namespace {
-
-constexpr int kPlanePadBytes = 4096 + 256;  // staggers plane bases across HBM channels
-constexpr uint64_t kStateMagic = 0x4c42414353543031ull;  // "LBACST01"
-
-struct DeviceGuard {
-    int prev = -1;
-    bool ok = true;
-    explicit DeviceGuard(int dev) {
-        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
-        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
-    }
-    ~DeviceGuard() {
-        if (prev >= 0) (void)hipSetDevice(prev);
-    }
-};
-
-}  // namespace
-
-struct lbac_ctx {
-    lbac_params p{};
-    lbac_allocator alloc{};
-    bool has_alloc = false;
-    int device = 0;
-    hipStream_t stream = nullptr;
-    bool own_stream = false;
-    int storage = ST_PLAIN;
-    int elem_bytes = 8;
-    int nplanes = 9;
-    int32_t pitch = 0;
-    int64_t plane_stride = 0;
-    void* pop[2] = {nullptr, nullptr};
-    float* phis[2] = {nullptr, nullptr};
-    double* vtab = nullptr;
-    int64_t* t_dev = nullptr;
-    double* rows = nullptr;
-    double* red5 = nullptr;
-    double* dtmp = nullptr;  // ny*nx doubles (phi0 upload, phi output, reference field)
-    double* host5 = nullptr; // pinned
-    int cur = 0;
-    int64_t t = 0;
-    int bx = 256, strip_h = 64;
-    int graph_chunk = 0;
-    hipGraphExec_t gexec[2] = {nullptr, nullptr};
-    int gexec_chunk[2] = {0, 0};
-    std::string err;
-};
-
-namespace {
+namespace lbac_host {
 
 int fail(lbac_ctx* h, int code, const std::string& msg) {
     if (h) h->err = msg;
     return code;
 }
-
-#define HIPCHK(h, call)                                                                         \
-    do {                                                                                        \
-        hipError_t e_ = (call);                                                                 \
-        if (e_ != hipSuccess) return fail(h, LBAC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
-    } while (0)
 
 void* dev_alloc(lbac_ctx* h, size_t bytes) {
     if (h->has_alloc) return h->alloc.alloc(bytes, h->alloc.user);
@@ -91,6 +37,10 @@ void dev_free(lbac_ctx* h, void* ptr) {
     else
         (void)hipFree(ptr);
 }
+
+}  // namespace lbac_host
+
+namespace {
 
 void drop_graphs(lbac_ctx* h) {
     for (int i = 0; i < 2; ++i) {
@@ -176,7 +126,9 @@ double time_period(const lbac_params& p) {
     return (p.vel_kind == LBAC_VEL_VORTEX || p.vel_kind == LBAC_VEL_VORTEX_PAPER) ? p.period_T : 0.0;
 }
 
-StepArgs make_args(const lbac_ctx* h, int src, int32_t k) {
+}  // namespace
+
+StepArgs lbac_host::make_args(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a{};
     a.src = h->pop[src];
     a.dst = h->pop[1 - src];
@@ -197,9 +149,14 @@ StepArgs make_args(const lbac_ctx* h, int src, int32_t k) {
     return a;
 }
 
+namespace {
+
 template <typename R, int ST, int MODEL>
-hipError_t launch_step_bx(const StepArgs& a, int bx, hipStream_t s) {
-    dim3 grid((a.nx + bx - 1) / bx, (a.ny + a.strip_h - 1) / a.strip_h);
+hipError_t launch_step_bx(StepArgs a, int bx, hipStream_t s) {
+    a.nbx = (a.nx + bx - 5) / (bx - 4);  // tiles of bx - 4 output columns
+    a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
+    a.n_xcd = kXcds;
+    dim3 grid(a.nbx * a.nby);
     switch (bx) {
     case 64:
         hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 64>), grid, dim3(64), 0, s, a);
@@ -295,7 +252,9 @@ int validate(const lbac_params* p, std::string& why) {
     return LBAC_OK;
 }
 
-int create(const lbac_params* p, const double* phi0, bool phi0_on_device, lbac_ctx** out) {
+}  // namespace
+
+int lbac_host::create(const lbac_params* p, const double* phi0, bool phi0_on_device, lbac_ctx** out) {
     if (!out) return LBAC_EINVAL;
     *out = nullptr;
     std::string why;
@@ -380,6 +339,15 @@ int create(const lbac_params* p, const double* phi0, bool phi0_on_device, lbac_c
     return LBAC_OK;
 }
 
+void lbac_host::destroy(lbac_ctx* h) {
+    if (!h) return;
+    DeviceGuard g(h->device);
+    release(h);
+    delete h;
+}
+
+namespace {
+
 int capture_graph(lbac_ctx* h, int parity) {
     if (h->gexec[parity] && h->gexec_chunk[parity] == h->graph_chunk) return LBAC_OK;
     if (h->gexec[parity]) {
@@ -448,9 +416,8 @@ int lbac_init_device(const lbac_params* p, const double* phi0_device, lbac_ctx**
 
 int lbac_free(lbac_ctx* h) {
     if (!h) return LBAC_OK;
-    DeviceGuard g(h->device);
-    release(h);
-    delete h;
+    if (h->in_batch) return fail(h, LBAC_ESTATE, "context belongs to a batch; free the batch");
+    destroy(h);
     return LBAC_OK;
 }
 

@@ -1,0 +1,78 @@
+// Internal declarations shared by the translation units of the library
+// (not part of the C ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <string>
+
+#include "lbac.h"
+#include "lbac_kernels.hpp"
+
+namespace lbac_host {
+
+constexpr int kPlanePadBytes = 4096 + 256;  // staggers plane bases across HBM channels
+constexpr int kXcds = 8;                    // MI355X: workgroups go round-robin over 8 XCDs
+constexpr uint64_t kStateMagic = 0x4c42414353543031ull;  // "LBACST01"
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        if (prev != dev) ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+}  // namespace lbac_host
+
+struct lbac_ctx {
+    lbac_params p{};
+    lbac_allocator alloc{};
+    bool has_alloc = false;
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int storage = lbac::ST_PLAIN;
+    int elem_bytes = 8;
+    int nplanes = 9;
+    int32_t pitch = 0;
+    int64_t plane_stride = 0;
+    void* pop[2] = {nullptr, nullptr};
+    float* phis[2] = {nullptr, nullptr};
+    double* vtab = nullptr;
+    int64_t* t_dev = nullptr;
+    double* rows = nullptr;
+    double* red5 = nullptr;
+    double* dtmp = nullptr;  // ny*nx doubles (phi0 upload, phi output, reference field)
+    double* host5 = nullptr; // pinned
+    int cur = 0;
+    int64_t t = 0;
+    int bx = 256, strip_h = 64;
+    int graph_chunk = 0;
+    hipGraphExec_t gexec[2] = {nullptr, nullptr};
+    int gexec_chunk[2] = {0, 0};
+    bool in_batch = false;   // owned by a batch: lbac_free refuses it
+    std::string err;
+};
+
+namespace lbac_host {
+
+int fail(lbac_ctx* h, int code, const std::string& msg);
+void* dev_alloc(lbac_ctx* h, size_t bytes);
+void dev_free(lbac_ctx* h, void* ptr);
+lbac::StepArgs make_args(const lbac_ctx* h, int src, int32_t k);
+int create(const lbac_params* p, const double* phi0, bool phi0_on_device, lbac_ctx** out);
+void destroy(lbac_ctx* h);
+
+}  // namespace lbac_host
+
+#define HIPCHK(h, call)                                                                                      \
+    do {                                                                                                     \
+        hipError_t e_ = (call);                                                                              \
+        if (e_ != hipSuccess)                                                                                \
+            return ::lbac_host::fail(h, LBAC_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));   \
+    } while (0)

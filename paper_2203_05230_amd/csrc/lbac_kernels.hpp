@@ -61,6 +61,8 @@ struct StepArgs {
     int32_t k;              // this launch is step t_dev[0] + k
     double period_T;        // s(t) = cos(pi t / period_T) when > 0, else 1
     double eps, tau, delta;
+    int32_t nbx, nby;       // tiles of the step launch (columns blocks x strips)
+    int32_t n_xcd;          // XCDs the workgroups are dispatched over
 };
 
 __device__ __forceinline__ int wrap_idx(int a, int n) {
@@ -172,166 +174,263 @@ __device__ __forceinline__ R sharpening(R phi, R eps, R delta) {
 }
 
 // ---------------------------------------------------------------------------
-// The step kernel.  BX threads = BX lattice columns; one strip of strip_h rows.
-template <typename R, int BX>
-struct TileLds {
-    R ring[3][9][BX + 4];  // rows r-2..r of every plane; index j <-> column x0 - 2 + j
-    R sring[3][BX + 2];    // psi on rows r-3..r-1; index j <-> column x0 - 1 + j
+// Fast elementary functions for the FP32 path (hardware log2, reciprocal and
+// square root, about 1 ulp); the FP64 path keeps the correctly rounded ones.
+template <typename R>
+struct Math;
+template <>
+struct Math<float> {
+    __device__ __forceinline__ static float log2(float x) { return __builtin_amdgcn_logf(x); }
+    __device__ __forceinline__ static float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+    __device__ __forceinline__ static float sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+};
+template <>
+struct Math<double> {
+    __device__ __forceinline__ static double log2(double x) { return ::log2(x); }
+    __device__ __forceinline__ static double rcp(double x) { return 1.0 / x; }
+    __device__ __forceinline__ static double sqrt(double x) { return ::sqrt(x); }
 };
 
-// One step on the tile of column block `bxi` (BX columns) and strip `syi`
-// (a.strip_h rows) at time t.  All BX threads of the block take part.
+// Uniform per-plane base pointers and 32-bit byte offsets (a plane is far
+// below 4 GiB), so a load or store is one instruction on a scalar base.
+template <typename R, int ST>
+struct Io;
+
+template <typename R>
+struct Io<R, ST_PLAIN> {
+    static constexpr bool kShifted = false;
+    const char* s[9];
+    char* d[9];
+    __device__ __forceinline__ explicit Io(const StepArgs& a) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            s[q] = static_cast<const char*>(a.src) + (size_t)q * a.plane_stride * sizeof(R);
+            d[q] = static_cast<char*>(a.dst) + (size_t)q * a.plane_stride * sizeof(R);
+        }
+    }
+    __device__ __forceinline__ void load(uint32_t off, R (&v)[9]) const {
+        const uint32_t b = off * (uint32_t)sizeof(R);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) v[q] = *reinterpret_cast<const R*>(s[q] + b);
+    }
+    __device__ __forceinline__ void store(uint32_t off, const R (&v)[9], R /*phi*/) const {
+        const uint32_t b = off * (uint32_t)sizeof(R);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) *reinterpret_cast<R*>(d[q] + b) = v[q];
+    }
+};
+
+template <typename H>
+struct IoShifted {
+    static constexpr bool kShifted = true;
+    const char* s[9];  // s[0]: phi* plane (FP32); s[1..8]: g planes (16-bit)
+    char* d[9];
+    __device__ __forceinline__ explicit IoShifted(const StepArgs& a) {
+        s[0] = reinterpret_cast<const char*>(a.src_phi);
+        d[0] = reinterpret_cast<char*>(a.dst_phi);
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            s[q] = static_cast<const char*>(a.src) + (size_t)(q - 1) * a.plane_stride * sizeof(H);
+            d[q] = static_cast<char*>(a.dst) + (size_t)(q - 1) * a.plane_stride * sizeof(H);
+        }
+    }
+    // v[0] = phi*, v[i] = w_i phi* + g_i
+    __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
+        const float ph = *reinterpret_cast<const float*>(s[0] + off * 4u);
+        v[0] = ph;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) v[q] = wq<float>(q) * ph + h2f<H>(*reinterpret_cast<const H*>(s[q] + off * 2u));
+    }
+    __device__ __forceinline__ void store(uint32_t off, const float (&v)[9], float phi) const {
+#pragma unroll
+        for (int q = 1; q < 9; ++q) *reinterpret_cast<H*>(d[q] + off * 2u) = f2h<H>(v[q] - wq<float>(q) * phi);
+        *reinterpret_cast<float*>(d[0] + off * 4u) = phi;
+    }
+};
+template <>
+struct Io<float, ST_F16> : IoShifted<__half> {
+    using IoShifted<__half>::IoShifted;
+};
+template <>
+struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
+    using IoShifted<__hip_bfloat16>::IoShifted;
+};
+
+// ---------------------------------------------------------------------------
+// The step on one tile.  A block of BX threads owns BX - 4 output columns
+// (tiles overlap by two columns on each side): lane l loads lattice column
+// x0 - 2 + l of every plane, lanes 1..BX-2 form phi and psi, lanes 2..BX-3
+// update, so every lane runs the same instruction stream (no halo passes).
+template <typename R, int BX>
+struct TileLds {
+    R ring[3][9][BX];  // rows r-2..r of every plane; index j <-> column x0 - 2 + j
+    R sring[3][BX];    // psi on the last three centre rows, same column index
+};
+
+template <int BX>
+__host__ __device__ constexpr int tile_width() {
+    return BX - 4;
+}
+
+// One step on the tile of column block `bxi` and strip `syi` (a.strip_h rows)
+// at time t.  The strip is marched upward, or downward when `down` is set
+// (odd strips are flipped so that two strips sharing a boundary read its halo
+// rows at about the same time, while they are still in cache).
 template <typename R, int ST, int MODEL, int BX>
-__device__ __forceinline__ void step_tile(const StepArgs& a, int bxi, int syi, int64_t t, TileLds<R, BX>& lds) {
+__device__ __forceinline__ void step_tile(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
+                                          TileLds<R, BX>& lds) {
+    constexpr int W = tile_width<BX>();
     auto& ring = lds.ring;
     auto& sring = lds.sring;
     const int l = threadIdx.x;
-    const int x0 = bxi * BX;
-    const int w = min(BX, a.nx - x0);
+    const int x0 = bxi * W;
+    const int w = min(W, a.nx - x0);
     const int ys = syi * a.strip_h;
     const int hh = min(a.strip_h, a.ny - ys);
-    const bool act = l < w;
-    const int x = x0 + l;
-    // lanes 0..3 also load the halo columns x0-2, x0-1, x0+w, x0+w+1
-    const int hj = l < 2 ? l : w + l;
-    const int hx = wrap_idx(x0 - 2 + hj, a.nx);
+    const bool ld_lane = l < w + 4;
+    const bool psi_lane = l >= 1 && l <= w + 2;
+    const bool upd_lane = l >= 2 && l <= w + 1;
+    const int col = wrap_idx(x0 - 2 + l, a.nx);  // column this lane loads
+    const int x = x0 - 2 + l;                    // column this lane updates (upd_lane)
+    const Io<R, ST> io(a);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
     const bool first = (t == 0);
     const R s_now = R(time_factor(a.period_T, t));
     const R s_old = first ? s_now : R(time_factor(a.period_T, t - 1));
-    const R Axl = act ? R(a.vtab[x]) : R(0);
-    const R Bxl = act ? R(a.vtab[a.nx + x]) : R(0);
+    const R Axl = upd_lane ? R(a.vtab[x]) : R(0);
+    const R Bxl = upd_lane ? R(a.vtab[a.nx + x]) : R(0);
     const R eps = R(a.eps), delta = R(a.delta);
-    const R omega = R(1) / R(a.tau);
-    const R kforce = R(1) - R(0.5) / R(a.tau);
+    const R psi_scale = R(a.eps * 0.69314718055994530942);  // eps ln 2: psi = eps ln2 (log2 a - log2 b)
+    const R s_scale = R(1.0 / (a.eps * (1.0 + 2.0 * a.delta) * (1.0 + 2.0 * a.delta)));
+    const R omega = R(1.0 / a.tau);
+    const R kforce = R(1.0 - 0.5 / a.tau);
+    const R keep = R(1.0 - 1.0 / a.tau);
 
     R fprev[9], fcur[9];
     R phiprev = R(0), phicur = R(0);
-    R P2 = R(0), P1 = R(0), P0 = R(0);  // own-column sums of stored values, rows r-2, r-1, r
+    R P2 = R(0), P1 = R(0), P0 = R(0);  // own-column phi at t-1, rows r-2, r-1, r
 
-    // prefetch registers for the next row
-    R nv[9], hv[9];
-    {
-        const int ry = wrap_idx(ys - 2, a.ny);
-        if (act) Store<R, ST>::load(a, (int64_t)ry * a.pitch + x, nv);
-        if (l < 4) Store<R, ST>::load(a, (int64_t)ry * a.pitch + hx, hv);
-    }
+    R nv[9];  // prefetch registers for the next row
+    if (ld_lane) io.load((uint32_t)wrap_idx(down ? ys + hh + 1 : ys - 2, a.ny) * (uint32_t)a.pitch + col, nv);
 
     const int iters = hh + 4;
     for (int it = 0; it < iters; ++it) {
-        const int slot = it % 3;            // ring slot of row r = ys - 2 + it
-        const int slot1 = (it + 2) % 3;     // row r - 1
-        const int slot2 = (it + 1) % 3;     // row r - 2
+        // row r = start + dir * it enters the ring; phi and psi are formed on the
+        // centre row c = r - dir; row c - dir is updated
+        const int slot = it % 3;         // ring slot of row r
+        const int slot1 = (it + 2) % 3;  // centre row c
+        const int slot2 = (it + 1) % 3;  // row r - 2 dir
+        const int slot_n = down ? slot2 : slot;  // row c + 1
+        const int slot_s = down ? slot : slot2;  // row c - 1
         // ---- row r into the ring
-        if (act) {
+        if (ld_lane) {
             R s = R(0);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                ring[slot][q][l + 2] = nv[q];
+                ring[slot][q][l] = nv[q];
                 s += nv[q];
             }
             // phi at t-1 on this row: the stored sum (plain) or phi* itself (shifted)
-            P0 = Store<R, ST>::kShifted ? nv[0] : s;
+            P0 = Io<R, ST>::kShifted ? nv[0] : s;
         }
-        if (l < 4) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) ring[slot][q][hj] = hv[q];
-        }
-        // ---- prefetch row r + 1
-        if (it + 1 < iters) {
-            const int ry = wrap_idx(ys - 1 + it, a.ny);
-            if (act) Store<R, ST>::load(a, (int64_t)ry * a.pitch + x, nv);
-            if (l < 4) Store<R, ST>::load(a, (int64_t)ry * a.pitch + hx, hv);
-        }
+        // ---- prefetch row r + dir
+        if (it + 1 < iters && ld_lane)
+            io.load((uint32_t)wrap_idx(down ? ys + hh - it : ys - 1 + it, a.ny) * (uint32_t)a.pitch + col, nv);
         lds_barrier();
 
-        // ---- phi (Eq. (12)) and psi (Eq. (13)) on row r - 1
-        if (it >= 2) {
-            // pulled population q at ring column jc of row r-1 comes from row r-1-cy(q), column jc-cx(q)
-            // phi at ring column jc of row r-1 (Eq. (12)); pulled values into f
-            auto pulled_sum = [&](int jc, R (&f)[9]) -> R {
-                if constexpr (Store<R, ST>::kShifted) {
-                    double s = (double)ring[slot1][0][jc];
+        // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row
+        if (it >= 2 && psi_lane) {
+            R s;
+            if constexpr (Io<R, ST>::kShifted) {
+                // phi = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] in FP64, rounded once
+                double d = (double)ring[slot1][0][l];
 #pragma unroll
-                    for (int q = 1; q < 9; ++q) {
-                        const int sl = cy(q) == 1 ? slot2 : (cy(q) == 0 ? slot1 : slot);
-                        f[q] = ring[sl][q][jc - cx(q)];
-                        s += (double)f[q] - (double)ring[slot1][q][jc];
-                    }
-                    f[0] = R(0);  // not needed: the rest population is the remainder after collision
-                    return R(s);
-                } else {
-                    R s = R(0);
-#pragma unroll
-                    for (int q = 0; q < 9; ++q) {
-                        const int sl = cy(q) == 1 ? slot2 : (cy(q) == 0 ? slot1 : slot);
-                        f[q] = ring[sl][q][jc - cx(q)];
-                        s += f[q];
-                    }
-                    return s;
+                for (int q = 1; q < 9; ++q) {
+                    const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
+                    fcur[q] = ring[sl][q][l - cx(q)];
+                    d += (double)fcur[q] - (double)ring[slot1][q][l];
                 }
-            };
-            if (act) {
-                const R s = pulled_sum(l + 2, fcur);
-                phicur = s;
-                sring[slot][l + 1] = normal_source<R, MODEL>(s, eps, delta);
+                fcur[0] = R(0);  // the rest population is formed as the remainder after collision
+                s = R(d);
+            } else {
+                s = R(0);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) {
+                    const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
+                    fcur[q] = ring[sl][q][l - cx(q)];
+                    s += fcur[q];
+                }
             }
-            if (l < 2) {
-                const int jc = l == 0 ? 1 : w + 2;
-                R tmp[9];
-                const R s = pulled_sum(jc, tmp);
-                sring[slot][jc - 1] = normal_source<R, MODEL>(s, eps, delta);
+            phicur = s;
+            R src;
+            if (MODEL == MODEL_CONVENTIONAL) {
+                src = s;
+            } else {
+                const R pc = s < R(0) ? R(0) : (s > R(1) ? R(1) : s);
+                src = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
             }
+            sring[slot][l] = src;
         }
         lds_barrier();
 
-        // ---- update row y = r - 2
-        if (it >= 4 && act) {
-            const int y = ys + it - 4;
-            const int sm = (it + 1) % 3, s0 = (it + 2) % 3, sp = it % 3;  // psi rows y-1, y, y+1
-            const int j = l + 1;
-            const R pE = sring[s0][j + 1], pW = sring[s0][j - 1];
-            const R pN = sring[sp][j], pS = sring[sm][j];
-            const R pNE = sring[sp][j + 1], pNW = sring[sp][j - 1];
-            const R pSE = sring[sm][j + 1], pSW = sring[sm][j - 1];
+        // ---- update row y = c - dir
+        if (it >= 4 && upd_lane) {
+            const int y = down ? ys + hh + 3 - it : ys + it - 4;
+            // psi rows y-1, y, y+1 (the newest psi row is y + dir)
+            const int s0 = (it + 2) % 3;
+            const int sm = down ? it % 3 : (it + 1) % 3;
+            const int sp = down ? (it + 1) % 3 : it % 3;
+            const R pE = sring[s0][l + 1], pW = sring[s0][l - 1];
+            const R pN = sring[sp][l], pS = sring[sm][l];
+            const R pNE = sring[sp][l + 1], pNW = sring[sp][l - 1];
+            const R pSE = sring[sm][l + 1], pSW = sring[sm][l - 1];
             // isotropic gradient: grad chi = sum_i w_i c_i chi(x + c_i) / c_s^2
             const R gx = (pE - pW) * R(1.0 / 3.0) + ((pNE - pNW) + (pSE - pSW)) * R(1.0 / 12.0);
             const R gy = (pN - pS) * R(1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * R(1.0 / 12.0);
-            const R mag = sqrt(gx * gx + gy * gy);
-            const R inv = R(1) / (mag + delta);
+            // n = grad psi / (|grad psi| + delta), Eq. (13)
+            const R inv = Math<R>::rcp(Math<R>::sqrt(gx * gx + gy * gy) + delta);
             const R phi = phiprev;
-            const R S = sharpening<R, MODEL>(phi, eps, delta);
+            R S;  // sharpening magnitude
+            if (MODEL == MODEL_CONVENTIONAL) {
+                S = phi * (R(1) - phi) / eps;
+            } else {
+                // (1 - tanh^2(psi/(2 eps)))/(4 eps) = a b / (eps (a + b)^2), a = phi_c + delta, b = 1 - phi_c + delta
+                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+                S = (pc + delta) * (R(1) - pc + delta) * s_scale;
+            }
             const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
             const R uxr = Axl * Ayv, uyr = Bxl * Byv;
             const R u = s_now * uxr, v = s_now * uyr;
             const R phio = first ? phi : P2;
             const R uo = s_old * uxr, vo = s_old * uyr;
             // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
-            const R Gx = (phi * u - phio * uo) + R(1.0 / 3.0) * (S * gx * inv);
-            const R Gy = (phi * v - phio * vo) + R(1.0 / 3.0) * (S * gy * inv);
-            // Eq. (9)-(11): f* = (1 - 1/tau) f + w_i [phi/tau + 3 c_i.(phi u / tau + (1 - 1/(2 tau)) G)]
+            const R Sn = R(1.0 / 3.0) * S * inv;
+            const R Gx = (phi * u - phio * uo) + Sn * gx;
+            const R Gy = (phi * v - phio * vo) + Sn * gy;
+            // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)]
             const R A0 = omega * phi;
             const R bx = R(3) * (A0 * u + kforce * Gx);
             const R by = R(3) * (A0 * v + kforce * Gy);
-            const R keep = R(1) - omega;
+            const R a1 = wq<R>(1) * A0, x1 = wq<R>(1) * bx, y1 = wq<R>(1) * by;
+            const R a5 = wq<R>(5) * A0, x5 = wq<R>(5) * bx, y5 = wq<R>(5) * by;
             R out[9];
-            R rest = phi;
-#pragma unroll
-            for (int q = 1; q < 9; ++q) {
-                R e = A0;
-                if (cx(q) == 1) e += bx;
-                if (cx(q) == -1) e -= bx;
-                if (cy(q) == 1) e += by;
-                if (cy(q) == -1) e -= by;
-                out[q] = keep * fprev[q] + wq<R>(q) * e;
-                rest -= out[q];
-            }
+            out[1] = keep * fprev[1] + (a1 + x1);
+            out[2] = keep * fprev[2] + (a1 + y1);
+            out[3] = keep * fprev[3] + (a1 - x1);
+            out[4] = keep * fprev[4] + (a1 - y1);
+            out[5] = keep * fprev[5] + ((a5 + x5) + y5);
+            out[6] = keep * fprev[6] + ((a5 - x5) + y5);
+            out[7] = keep * fprev[7] + ((a5 - x5) - y5);
+            out[8] = keep * fprev[8] + ((a5 + x5) - y5);
             // Eq. (9) conserves sum_i f_i = phi exactly; the rest population is
             // taken as the remainder so that rounded weights (sum_i w_i != 1 in
             // floating point) cannot make the total mass drift
+            R rest = phi;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) rest -= out[q];
             out[0] = rest;
-            Store<R, ST>::store(a, (int64_t)y * a.pitch + x, out, phi);
+            io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) fprev[q] = fcur[q];
@@ -344,7 +443,16 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int bxi, int syi, i
 template <typename R, int ST, int MODEL, int BX>
 __global__ __launch_bounds__(BX) void step_kernel(StepArgs a) {
     __shared__ TileLds<R, BX> lds;
-    step_tile<R, ST, MODEL, BX>(a, blockIdx.x, blockIdx.y, a.t_dev[0] + a.k, lds);
+    // XCD-aware tile order: workgroups are dispatched round-robin over the
+    // XCDs, so XCD (g mod n_xcd) is given one contiguous row-major range of
+    // tiles; horizontally adjacent tiles then share an L2 and run together
+    const int ntile = a.nbx * a.nby;
+    const int g = blockIdx.x;
+    const int xcd = g % a.n_xcd, k = g / a.n_xcd;
+    const int per = ntile / a.n_xcd, extra = ntile % a.n_xcd;
+    const int tile = xcd * per + min(xcd, extra) + k;
+    const int bxi = tile % a.nbx, syi = tile / a.nbx;
+    step_tile<R, ST, MODEL, BX>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -461,7 +569,7 @@ __global__ __launch_bounds__(kRedThreads) void row_sums_kernel(StepArgs a, const
 }
 
 // Adds the per-row sums in row order (one block; deterministic).
-__global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double* __restrict__ rows, int ny,
+static __global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double* __restrict__ rows, int ny,
                                                                    double* __restrict__ out5) {
     __shared__ double sh[kRedThreads / 64];
     for (int c = 0; c < 5; ++c) {
@@ -472,12 +580,120 @@ __global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double* 
     }
 }
 
-__global__ void advance_kernel(int64_t* t_dev, int64_t n) {
+static __global__ void advance_kernel(int64_t* t_dev, int64_t n) {
     if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] += n;
 }
 
-__global__ void set_time_kernel(int64_t* t_dev, int64_t t) {
+static __global__ void set_time_kernel(int64_t* t_dev, int64_t t) {
     if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] = t;
+}
+
+}  // namespace lbac
+
+// ---------------------------------------------------------------------------
+// Batched form: many independent lattices advanced by ONE persistent launch.
+//
+// Work is split into items = (instance, 64-column block, strip).  Each
+// workgroup (one wavefront) owns a fixed list of items and walks them in
+// step-major order.  Before item I computes step n it waits until the eight
+// items of the same instance whose tiles overlap I's tile grown by two nodes
+// have completed step n-1: they wrote the rows and columns I pulls, and
+// (the relation is symmetric) they have finished reading the part of the
+// buffer I is about to overwrite.  With every workgroup resident
+// (the grid never exceeds the occupancy limit) the lowest pending step can
+// always proceed, so the schedule cannot deadlock; every wait is also bounded
+// in wall-clock time and sets an error flag that makes all workgroups exit.
+namespace lbac {
+
+struct BatchInst {
+    StepArgs a;       // src/dst as seen by even steps; odd steps swap them
+    int64_t nsteps;   // steps of this instance in this run
+};
+
+struct BatchItem {
+    int32_t inst, bxi, syi, down;
+    // ids of the items whose tiles overlap this item's read region (its tile
+    // grown by two nodes, periodic), itself excluded; repeats pad the list
+    int32_t nbr[16];
+};
+
+struct BatchCtl {
+    int64_t max_steps;
+    int64_t timeout_ticks;  // wall-clock ticks a wait may take before giving up
+    int32_t dry;            // 1: every step reads src and writes dst (state untouched)
+    int32_t err;            // set to 1 when a wait gave up
+    int32_t test_stall;     // 1: waits ask for a step that never completes (tests the time-out path)
+    int32_t pad;
+};
+
+constexpr int kBatchBX = 64;
+
+__device__ __forceinline__ bool batch_wait(const int32_t* done, const BatchItem* item, int32_t need, BatchCtl* ctl) {
+    const int32_t* p = done + item->nbr[threadIdx.x & 15];
+    if (ctl->test_stall) need += (1 << 30);
+    const uint64_t t0 = wall_clock64();
+    for (;;) {
+        const int32_t v = __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        if (__all(v >= need)) break;
+        if (__hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - t0 > (uint64_t)ctl->timeout_ticks) {
+            __hip_atomic_store(&ctl->err, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    // make the neighbours' rows visible to this workgroup's loads
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    return true;
+}
+
+template <int MODEL>
+__global__ __launch_bounds__(kBatchBX) void batch_kernel(const BatchInst* __restrict__ insts,
+                                                         const BatchItem* __restrict__ items,
+                                                         const int32_t* __restrict__ wg_off,
+                                                         const int32_t* __restrict__ wg_items, int32_t* done,
+                                                         BatchCtl* ctl) {
+    __shared__ TileLds<float, kBatchBX> lds;
+    const int beg = wg_off[blockIdx.x], end = wg_off[blockIdx.x + 1];
+    const int64_t max_steps = ctl->max_steps;
+    const bool dry = ctl->dry != 0;
+    for (int64_t n = 0; n < max_steps; ++n) {
+        bool any = false;
+        for (int i = beg; i < end; ++i) {
+            const int id = wg_items[i];
+            const BatchItem* item = items + id;
+            const BatchInst& in = insts[item->inst];
+            if (n >= in.nsteps) continue;
+            any = true;
+            if (n > 0 && !batch_wait(done, item, (int32_t)(n - 1), ctl)) return;
+            StepArgs a = in.a;
+            if ((n & 1) && !dry) {
+                const void* s = a.src;
+                a.src = a.dst;
+                a.dst = const_cast<void*>(s);
+            }
+            step_tile<float, ST_PLAIN, MODEL, kBatchBX>(a, item->bxi, item->syi, a.t_dev[0] + (dry ? 0 : n),
+                                                        item->down != 0, lds);
+            // publish: this wavefront's stores are visible before the counter moves
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (threadIdx.x == 0) __hip_atomic_store(done + id, (int32_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        }
+        if (!any) break;
+    }
+}
+
+// Resets the progress counters and the error flag (a kernel, not a memset, so
+// that the whole run can be replayed from a captured graph).
+static __global__ void batch_reset_kernel(int32_t* done, int32_t nitems, BatchCtl* ctl) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < nitems) done[i] = -1;
+    if (i == 0) ctl->err = 0;
+}
+
+// Advances every instance's step counter by its step count (skipped on dry runs).
+static __global__ void batch_advance_kernel(const BatchInst* __restrict__ insts, int32_t count, const BatchCtl* ctl) {
+    const int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k < count && ctl->dry == 0 && ctl->err == 0) const_cast<int64_t*>(insts[k].a.t_dev)[0] += insts[k].nsteps;
 }
 
 }  // namespace lbac

@@ -47,6 +47,9 @@ EXPORTS = [
     "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
     "lbac_set_launch", "lbac_get_launch", "lbac_autotune", "lbac_set_graph_chunk", "lbac_bytes_per_node",
     "lbac_stream", "lbac_strerror", "lbac_last_error",
+    "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
+    "lbac_batch_set_shape", "lbac_batch_get_shape", "lbac_batch_autotune", "lbac_batch_set_timeout",
+    "lbac_batch_last_error",
 ]
 
 _lib = None
@@ -92,8 +95,20 @@ def load():
     L.lbac_strerror.restype = C.c_char_p
     L.lbac_last_error.argtypes = [C.c_void_p]
     L.lbac_last_error.restype = C.c_char_p
+    L.lbac_batch_init.argtypes = [P(lbac_params), P(P(C.c_double)), C.c_int32, ctx_pp]
+    L.lbac_batch_free.argtypes = [C.c_void_p]
+    L.lbac_batch_run.argtypes = [C.c_void_p, P(C.c_int64)]
+    L.lbac_batch_instance.argtypes = [C.c_void_p, C.c_int32, ctx_pp]
+    L.lbac_batch_count.argtypes = [C.c_void_p, P(C.c_int32)]
+    L.lbac_batch_set_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
+    L.lbac_batch_get_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+    L.lbac_batch_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
+    L.lbac_batch_set_timeout.argtypes = [C.c_void_p, C.c_double, C.c_int32]
+    L.lbac_batch_last_error.argtypes = [C.c_void_p]
+    L.lbac_batch_last_error.restype = C.c_char_p
     for name in EXPORTS:
-        if name not in ("lbac_default_params", "lbac_stream", "lbac_strerror", "lbac_last_error"):
+        if name not in ("lbac_default_params", "lbac_stream", "lbac_strerror", "lbac_last_error",
+                        "lbac_batch_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -245,3 +260,72 @@ class Simulation:
 
     def stream(self):
         return load().lbac_stream(self.h)
+
+
+class _Borrowed(Simulation):
+    """A context owned by a batch (not freed by this object)."""
+
+    def __init__(self, h, nx, ny):
+        self.h, self.nx, self.ny, self._keep = h, nx, ny, []
+
+    def close(self):
+        self.h = None
+
+
+class Batch:
+    """Independent instances advanced together by one persistent launch."""
+
+    def __init__(self, cases, phi0s, stream=None):
+        L = load()
+        n = len(cases)
+        params = (lbac_params * n)()
+        for k, c in enumerate(cases):
+            params[k] = make_params(**{**c, "precision": "f32", "stream": stream if k == 0 else None})
+        self._phi = [np.ascontiguousarray(p, dtype=np.float64).reshape(c["ny"], c["nx"]) for c, p in zip(cases, phi0s)]
+        ptrs = (C.POINTER(C.c_double) * n)(*[_dp(a) for a in self._phi])
+        h = C.c_void_p()
+        _check(L.lbac_batch_init(params, ptrs, n, C.byref(h)), what="lbac_batch_init")
+        self.h = h
+        self.count = n
+        self.shapes = [(c["nx"], c["ny"]) for c in cases]
+
+    def _err(self, rc):
+        if rc != LBAC_OK:
+            raise LbacError(rc, load().lbac_batch_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbac_batch_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def run(self, nsteps):
+        ns = (C.c_int64 * self.count)(*[int(v) for v in nsteps])
+        self._err(load().lbac_batch_run(self.h, ns))
+
+    def instance(self, k):
+        c = C.c_void_p()
+        self._err(load().lbac_batch_instance(self.h, int(k), C.byref(c)))
+        nx, ny = self.shapes[k]
+        return _Borrowed(c, nx, ny)
+
+    def set_shape(self, strip_h, workgroups=0):
+        self._err(load().lbac_batch_set_shape(self.h, int(strip_h), int(workgroups)))
+
+    def get_shape(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        self._err(load().lbac_batch_get_shape(self.h, C.byref(a), C.byref(b), C.byref(c)))
+        return a.value, b.value, c.value
+
+    def autotune(self, steps=8):
+        ms = C.c_double()
+        self._err(load().lbac_batch_autotune(self.h, int(steps), C.byref(ms)))
+        return ms.value
+
+    def set_timeout(self, seconds, test_stall=False):
+        self._err(load().lbac_batch_set_timeout(self.h, float(seconds), 1 if test_stall else 0))

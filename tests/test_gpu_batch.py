@@ -1,0 +1,135 @@
+"""Batched form: many instances in one persistent launch, through the C ABI.
+
+Each instance must be bitwise equal to the same instance advanced alone by
+lbac_step with FP32 storage (whose parity against the oracle is tested in
+test_gpu_parity.py); one instance is also checked against the oracle
+directly.  The time-out path is forced from the host (waits that ask for a
+step that never completes, with a short time-out), so every workgroup exits.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lib as O
+from paper_2203_05230_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def mixed_cases():
+    cases, phis, steps = [], [], []
+    c = W.single_vortex_case(64, eps=1.0, tau=0.8, U=0.04, period_T=80.0)
+    cases.append(c), phis.append(W.circle(64, 1.0)), steps.append(40)
+    c = W.zalesak_case(128, eps=0.5, tau=0.7, rev_steps=4000)
+    cases.append(c), phis.append(W.slotted_disk(128, 0.5)), steps.append(33)
+    c = dict(nx=100, ny=70, eps=1.5, tau=0.9, delta=1e-10, vel="uniform", ux=0.03, uy=-0.02)
+    cases.append(c), phis.append(W.circle(100, 1.5, R_frac=0.2, yc_frac=0.5)[:70]), steps.append(27)
+    c = W.single_vortex_case(192, eps=2.0, tau=0.65, U=0.02, period_T=384.0)
+    cases.append(c), phis.append(W.circle(192, 2.0)), steps.append(17)
+    c = W.single_vortex_case(64, eps=1.0)
+    cases.append(c), phis.append(W.circle(64, 1.0)), steps.append(0)
+    c = dict(nx=130, ny=90, eps=1.0, tau=0.75, delta=1e-10, vel="vortex", U=0.03, period_T=200.0)
+    cases.append(c), phis.append(W.circle(130, 1.0)[:90]), steps.append(25)
+    return cases, phis, steps
+
+
+def single(lb, case, phi0, n):
+    sim = lb.Simulation({**case, "precision": "f32"}, phi0)
+    sim.step(n)
+    out = sim.phi()
+    sim.close()
+    return out
+
+
+def test_batch_bitwise_equals_single_instances(gpu_lib):
+    say("case: batch of 6 mixed instances vs single-instance runs")
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases, phis)
+    b.run(steps)
+    for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
+        inst = b.instance(k)
+        assert inst.time() == n
+        assert np.array_equal(inst.phi(), single(gpu_lib, c, p, n)), k
+    b.close()
+
+
+@pytest.mark.parametrize("strip_h,wgs", [(2, 0), (7, 5), (32, 1), (64, 0)])
+def test_batch_shapes_and_continuation(gpu_lib, strip_h, wgs):
+    say("case: batch shape", strip_h, wgs)
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases, phis)
+    b.set_shape(strip_h, wgs)
+    first = [n // 2 for n in steps]
+    b.run(first)
+    b.run([n - f for n, f in zip(steps, first)])
+    for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
+        assert np.array_equal(b.instance(k).phi(), single(gpu_lib, c, p, n)), k
+    b.close()
+
+
+def test_batch_autotune_keeps_state(gpu_lib):
+    say("case: batch autotune")
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases, phis)
+    b.run(steps)
+    before = [b.instance(k).phi() for k in range(len(cases))]
+    ms = b.autotune(4)
+    assert ms > 0
+    for k in range(len(cases)):
+        assert np.array_equal(b.instance(k).phi(), before[k])
+        assert b.instance(k).time() == steps[k]
+    b.run([3] * len(cases))
+    for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
+        assert np.array_equal(b.instance(k).phi(), single(gpu_lib, c, p, n + 3)), k
+    b.close()
+
+
+def test_batch_instance_matches_oracle(gpu_lib):
+    say("case: batch instance vs oracle")
+    n = 96
+    case = W.single_vortex_case(n, eps=1.0, tau=0.8, U=0.03, period_T=600.0)
+    phi0 = W.circle(n, 1.0)
+    other = W.zalesak_case(128, eps=1.0, tau=0.9, rev_steps=4000)
+    b = gpu_lib.Batch([case, other], [phi0, W.slotted_disk(128, 1.0)])
+    b.run([300, 150])
+    ref = O.run(O.Params(n, n, eps=1.0, tau=0.8, delta=1e-10, vel_kind=O.VEL_VORTEX, U=0.03, period_T=600.0),
+                phi0, 300)
+    got = b.instance(0).phi()
+    assert np.linalg.norm(got - ref) / np.linalg.norm(ref) <= 1e-5
+    m = b.instance(1).mass()
+    assert abs(m - W.slotted_disk(128, 1.0).sum()) / m < 1e-5
+    b.close()
+
+
+def test_batch_seeded_list_subset(gpu_lib):
+    """Instances drawn by the seeded generator of the batched workload (sides
+    128..512, eps in {0.5, 1, 2}, tau in [0.6, 1]; vortex and slotted disk),
+    with the step counts cut short for the test."""
+    say("case: seeded batch list, 12 instances")
+    cases = W.batch_cases(count=12, seed=3)
+    phis = [W.initial_field(c) for c in cases]
+    steps = [min(c["steps"], 20 + 3 * k) for k, c in enumerate(cases)]
+    b = gpu_lib.Batch(cases, phis)
+    b.run(steps)
+    for k in (0, 5, 6, 11):
+        assert np.array_equal(b.instance(k).phi(), single(gpu_lib, cases[k], phis[k], steps[k])), k
+    b.close()
+
+
+def test_batch_stall_times_out_and_reports(gpu_lib):
+    """Every wait asks for a step that never completes; with a 50 ms time-out
+    every workgroup exits and the run reports a device error."""
+    say("case: batch forced stall")
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases, phis)
+    b.set_timeout(0.05, test_stall=True)
+    with pytest.raises(gpu_lib.LbacError) as ei:
+        b.run([5] * len(cases))
+    assert ei.value.code == gpu_lib.LBAC_EDEVICE
+    b.close()
