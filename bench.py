@@ -64,7 +64,7 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     if launch:
         sim.set_launch(*launch)
     if autotune:
-        sim.autotune(4)
+        sim.autotune(12)
     launch = sim.get_launch()
     if warmup:
         sim.step(warmup)
@@ -126,7 +126,7 @@ def main():
     ap.add_argument("--forms", default="f32_f16store,f32_bf16store",
                     help="extra storage forms timed on the same workload ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
-    ap.add_argument("--launch", default="", help="bx,strip_h (default: autotune)")
+    ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
                          "scaling HBM byte counters) and exit")

@@ -142,11 +142,16 @@ int lbac_time(lbac_ctx* h, int64_t* t);
 int lbac_get_state(lbac_ctx* h, void* buf, size_t* bytes);
 int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
 
-/* Launch shape of the step kernel: block width bx (64, 128 or 256 lattice
- * columns) and strip height (rows marched per block, >= 1).  Results do not
- * depend on the shape (bitwise).  LBAC_EINVAL for unsupported values. */
-int lbac_set_launch(lbac_ctx* h, int32_t bx, int32_t strip_h);
-int lbac_get_launch(lbac_ctx* h, int32_t* bx, int32_t* strip_h);
+/* Launch shape of the step kernel.  variant LBAC_KERNEL_BLOCK: a block of bx
+ * threads (64, 128 or 256) owns a tile of bx - 4 columns and shares rows
+ * through LDS; LBAC_KERNEL_WAVE: every wavefront owns a 60-column tile held
+ * in registers, bx / 64 wavefronts per block.  strip_h: rows each tile
+ * marches (>= 1).  Results do not depend on the shape or variant (bitwise).
+ * LBAC_EINVAL for unsupported values. */
+#define LBAC_KERNEL_BLOCK 0
+#define LBAC_KERNEL_WAVE 1
+int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
+int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
 /* Times every supported launch shape over `steps` steps each (state is left
  * unchanged) and keeps the fastest; *us_per_step (may be NULL) gets its time. */
@@ -156,6 +161,15 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step);
  * graph of `chunk` step kernels for every full chunk; 0 launches kernels one
  * by one.  Bitwise identical either way. */
 int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk);
+
+/* Learned closure in the step (LBAC_F32 contexts): params = the network's
+ * LBAC_MLP_NPARAM FP32 parameters (host, copied; layout below); the kernel
+ * runs the network in BF16 with FP32 accumulation (MFMA) on the 5x5
+ * neighbourhood of phi at every node whose clipped phi lies in
+ * (theta, 1 - theta), and adds its output to the sharpening flux S n of
+ * Eq. (11).  params == NULL switches the closure off.  LBAC_EINVAL for
+ * another precision, theta outside [0, 0.5) or non-finite parameters. */
+int lbac_set_closure(lbac_ctx* h, const float* params, float theta);
 
 /* HBM bytes one step moves by design (read + write of the stored state). */
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
@@ -213,6 +227,53 @@ const char* lbac_batch_last_error(lbac_batch* b);
 /* Text of a status code, and of the last failure of a context. */
 const char* lbac_strerror(int code);
 const char* lbac_last_error(lbac_ctx* h);
+
+/* ---- learned closure: the network and its training ------------------------
+ * A 25 -> 64 -> 64 -> 2 multilayer perceptron with the tanh form of GELU,
+ * mapping the 5x5 neighbourhood of phi around a node (row-major, dy = -2..2
+ * outer, dx = -2..2 inner) to a correction (cx, cy) of the sharpening flux
+ * S n of Eq. (11).  Parameters: LBAC_MLP_NPARAM FP32 values laid out as
+ * W1[64][25], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].  Training runs
+ * on the GPU in FP32 (hand-written forward, backward, Adam kernels); loss
+ * L = (1/B) sum_samples sum_outputs (out - y)^2.  Sample arrays are device
+ * memory owned by the caller: x_dev is batch*25 floats, y_dev and out_dev
+ * batch*2 floats, row-major. */
+#define LBAC_MLP_NPARAM 5954
+typedef struct lbac_mlp lbac_mlp;
+
+/* init: host, LBAC_MLP_NPARAM finite values (copied); stream: hipStream_t or NULL. */
+int lbac_mlp_create(const float* init, void* stream, lbac_mlp** out);
+int lbac_mlp_free(lbac_mlp* m);
+int lbac_mlp_get_weights(lbac_mlp* m, float* out_host);
+int lbac_mlp_set_weights(lbac_mlp* m, const float* in_host);
+/* out_dev = network(x_dev), asynchronous on the network's stream. */
+int lbac_mlp_forward(lbac_mlp* m, const float* x_dev, int64_t batch, float* out_dev);
+/* Loss and gradient (host, LBAC_MLP_NPARAM floats; may be NULL) without an
+ * update.  Synchronises. */
+int lbac_mlp_loss_grad(lbac_mlp* m, const float* x_dev, const float* y_dev, int64_t batch, double* loss,
+                       float* grad_host);
+/* One Adam step (beta1 0.9, beta2 0.999, 1e-8) with learning rate lr on the
+ * batch.  *loss (may be NULL) receives the loss before the update; asking for
+ * it synchronises. */
+int lbac_mlp_train_step(lbac_mlp* m, const float* x_dev, const float* y_dev, int64_t batch, float lr, double* loss);
+const char* lbac_mlp_last_error(lbac_mlp* m);
+
+/* Training samples for the closure from a fine field phi_f (device, nyf*nxf
+ * doubles, a run r times finer, width eps_f = r eps_c in its own units):
+ * coarse phi_c = mean of each r x r block; target = mean over the block of
+ * r S_f n_f minus S_c(phi_c) n_c(phi_c), the sharpening flux of Eq. (6), (7),
+ * (13) on each grid; one sample per coarse node with theta < clip(phi_c) <
+ * 1 - theta: its 5x5 neighbourhood of phi_c (the network's input layout)
+ * and the target, plus the 7 images under the symmetries of the square when
+ * augment != 0.  Samples go to x_dev (25 floats each) and y_dev (2 floats)
+ * from index base on, in row-major node order, as long as the index is below
+ * capacity; *count receives the number of samples the field yields (stored
+ * or not).  workspace: device memory of lbac_closure_workspace_bytes(nxf,
+ * nyf, r) bytes.  Synchronises the stream (hipStream_t or NULL). */
+int64_t lbac_closure_workspace_bytes(int32_t nxf, int32_t nyf, int32_t r);
+int lbac_closure_extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f, double eps_c,
+                         double delta, float theta, int32_t augment, void* workspace, float* x_dev, float* y_dev,
+                         int64_t base, int64_t capacity, int64_t* count, void* stream);
 
 #ifdef __cplusplus
 }

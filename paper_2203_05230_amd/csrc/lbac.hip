@@ -62,6 +62,9 @@ void release(lbac_ctx* h) {
     dev_free(h, h->rows);
     dev_free(h, h->red5);
     dev_free(h, h->dtmp);
+    dev_free(h, h->cl_param);
+    dev_free(h, h->cl_w);
+    dev_free(h, h->cl_b);
     if (h->host5) (void)hipHostFree(h->host5);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -146,26 +149,48 @@ StepArgs lbac_host::make_args(const lbac_ctx* h, int src, int32_t k) {
     a.eps = h->p.eps;
     a.tau = h->p.tau;
     a.delta = h->p.delta;
+    a.cl_w = h->cl_w;
+    a.cl_b = h->cl_b;
+    a.cl_theta = h->cl_theta;
     return a;
 }
 
 namespace {
 
 template <typename R, int ST, int MODEL>
-hipError_t launch_step_bx(StepArgs a, int bx, hipStream_t s) {
-    a.nbx = (a.nx + bx - 5) / (bx - 4);  // tiles of bx - 4 output columns
+hipError_t launch_step_bx(StepArgs a, int variant, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
-    dim3 grid(a.nbx * a.nby);
-    switch (bx) {
-    case 64:
-        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 64>), grid, dim3(64), 0, s, a);
+    if (variant == LBAC_KERNEL_BLOCK) {
+        // one block of bx threads per tile of bx - 4 output columns
+        a.nbx = (a.nx + bx - 5) / (bx - 4);
+        dim3 grid(a.nbx * a.nby);
+        switch (bx) {
+        case 64:
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64>), grid, dim3(64), 0, s, a);
+            break;
+        case 128:
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128>), grid, dim3(128), 0, s, a);
+            break;
+        default:
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256>), grid, dim3(256), 0, s, a);
+            break;
+        }
+        return hipGetLastError();
+    }
+    // bx / 64 wavefronts per block, each owning one 60-column tile
+    const int wpb = bx / kWave;
+    a.nbx = (a.nx + kTileW - 1) / kTileW;
+    dim3 grid(((a.nbx + wpb - 1) / wpb) * a.nby);
+    switch (wpb) {
+    case 1:
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 1>), grid, dim3(64), 0, s, a);
         break;
-    case 128:
-        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 128>), grid, dim3(128), 0, s, a);
+    case 2:
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 2>), grid, dim3(128), 0, s, a);
         break;
     default:
-        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 256>), grid, dim3(256), 0, s, a);
+        hipLaunchKernelGGL((step_kernel<R, ST, MODEL, 4>), grid, dim3(256), 0, s, a);
         break;
     }
     return hipGetLastError();
@@ -173,12 +198,24 @@ hipError_t launch_step_bx(StepArgs a, int bx, hipStream_t s) {
 
 template <typename R, int ST>
 hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a) {
-    if (h->p.model == LBAC_MODEL_CONVENTIONAL) return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, h->bx, h->stream);
-    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, h->bx, h->stream);
+    if (h->p.model == LBAC_MODEL_CONVENTIONAL)
+        return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, h->variant, h->bx, h->stream);
+    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, h->variant, h->bx, h->stream);
 }
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
-    const StepArgs a = make_args(h, src, k);
+    StepArgs a = make_args(h, src, k);
+    if (h->closure) {
+        // one wavefront per 58-column tile; FP32 plain storage
+        a.nbx = (a.nx + WaveGeom<true>::kW - 1) / WaveGeom<true>::kW;
+        a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
+        a.n_xcd = kXcds;
+        if (h->p.model == LBAC_MODEL_CONVENTIONAL)
+            hipLaunchKernelGGL(step_kernel_closure<MODEL_CONVENTIONAL>, dim3(a.nbx * a.nby), dim3(kWave), 0, h->stream, a);
+        else
+            hipLaunchKernelGGL(step_kernel_closure<MODEL_IMPROVED>, dim3(a.nbx * a.nby), dim3(kWave), 0, h->stream, a);
+        return hipGetLastError();
+    }
     switch (h->p.precision) {
     case LBAC_F64:
         return launch_step_m<double, ST_PLAIN>(h, a);
@@ -293,7 +330,14 @@ int lbac_host::create(const lbac_params* p, const double* phi0, bool phi0_on_dev
                  : (p->precision == LBAC_F32_F16STORE ? ST_F16 : ST_BF16);
     h->elem_bytes = p->precision == LBAC_F64 ? 8 : (p->precision == LBAC_F32 ? 4 : 2);
     h->nplanes = h->storage == ST_PLAIN ? 9 : 8;
-    h->pitch = (p->nx + 63) / 64 * 64;
+    // rows are an odd multiple of 256 bytes apart: with a power-of-two row
+    // pitch, rows processed at the same time by different strips and XCDs
+    // land on the same HBM channels
+    {
+        const int unit = 256 / h->elem_bytes;
+        h->pitch = (p->nx + unit - 1) / unit * unit;
+        if ((h->pitch / unit) % 2 == 0) h->pitch += unit;
+    }
     h->plane_stride = (int64_t)h->pitch * p->ny + kPlanePadBytes / h->elem_bytes;
     // default launch shape: full-width blocks when the grid allows, strips of 64 rows
     h->bx = p->nx >= 256 ? 256 : (p->nx >= 128 ? 128 : 64);
@@ -555,18 +599,21 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
     return LBAC_OK;
 }
 
-int lbac_set_launch(lbac_ctx* h, int32_t bx, int32_t strip_h) {
+int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (!h) return LBAC_EINVAL;
+    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE) return fail(h, LBAC_EINVAL, "unknown kernel variant");
     if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
+    h->variant = variant;
     h->bx = bx;
     h->strip_h = std::min(strip_h, h->p.ny);
     drop_graphs(h);
     return LBAC_OK;
 }
 
-int lbac_get_launch(lbac_ctx* h, int32_t* bx, int32_t* strip_h) {
+int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h) {
     if (!h) return LBAC_EINVAL;
+    if (variant) *variant = h->variant;
     if (bx) *bx = h->bx;
     if (strip_h) *strip_h = h->strip_h;
     return LBAC_OK;
@@ -580,14 +627,16 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
-    const int keep_bx = h->bx, keep_h = h->strip_h;
-    int best_bx = keep_bx, best_h = keep_h;
+    const int keep_bx = h->bx, keep_h = h->strip_h, keep_v = h->variant;
+    int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
+    for (int var = LBAC_KERNEL_BLOCK; var <= LBAC_KERNEL_WAVE && e == hipSuccess; ++var)
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
         for (int sh : hs) {
             if (sh > h->p.ny && sh != hs[0]) continue;
+            h->variant = var;
             h->bx = bx;
             h->strip_h = std::min(sh, h->p.ny);
             // repeated step from pop[cur] into the scratch buffer: the state is untouched
@@ -601,6 +650,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
             if (e != hipSuccess) break;
             if (ms < best) {
                 best = ms;
+                best_v = var;
                 best_bx = bx;
                 best_h = h->strip_h;
             }
@@ -609,10 +659,12 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    h->variant = best_v;
     h->bx = best_bx;
     h->strip_h = best_h;
     drop_graphs(h);
     if (e != hipSuccess) {
+        h->variant = keep_v;
         h->bx = keep_bx;
         h->strip_h = keep_h;
         return fail(h, LBAC_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
@@ -625,6 +677,35 @@ int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk) {
     if (!h) return LBAC_EINVAL;
     if (chunk < 0 || (chunk & 1)) return fail(h, LBAC_EINVAL, "graph chunk must be an even number >= 0");
     h->graph_chunk = chunk;
+    drop_graphs(h);
+    return LBAC_OK;
+}
+
+int lbac_set_closure(lbac_ctx* h, const float* params, float theta) {
+    if (!h) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    if (!params) {
+        h->closure = false;
+        drop_graphs(h);
+        return LBAC_OK;
+    }
+    if (h->p.precision != LBAC_F32) return fail(h, LBAC_EINVAL, "the learned closure runs with LBAC_F32 only");
+    if (!(theta >= 0.f) || !(theta < 0.5f)) return fail(h, LBAC_EINVAL, "theta must lie in [0, 0.5)");
+    for (int i = 0; i < LBAC_MLP_NPARAM; ++i)
+        if (!std::isfinite(params[i])) return fail(h, LBAC_EINVAL, "non-finite closure parameter");
+    if (!h->cl_param) {
+        h->cl_param = (float*)dev_alloc(h, sizeof(float) * LBAC_MLP_NPARAM);
+        h->cl_w = (uint16_t*)dev_alloc(h, sizeof(uint16_t) * kClWN);
+        h->cl_b = (float*)dev_alloc(h, sizeof(float) * kClBN);
+        if (!h->cl_param || !h->cl_w || !h->cl_b) return fail(h, LBAC_ENOMEM, "closure buffers");
+    }
+    HIPCHK(h, hipMemcpyAsync(h->cl_param, params, sizeof(float) * LBAC_MLP_NPARAM, hipMemcpyHostToDevice, h->stream));
+    hipLaunchKernelGGL(closure_pack_kernel, dim3((64 * 64 + 255) / 256), dim3(256), 0, h->stream, h->cl_param, h->cl_w,
+                       h->cl_b);
+    HIPCHK(h, hipGetLastError());
+    HIPCHK(h, hipStreamSynchronize(h->stream));
+    h->closure = true;
+    h->cl_theta = theta;
     drop_graphs(h);
     return LBAC_OK;
 }

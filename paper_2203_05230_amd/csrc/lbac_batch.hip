@@ -101,7 +101,7 @@ void release(lbac_batch* b) {
 // neighbours of an item are the items whose tiles overlap its read region,
 // columns x0-2 .. x0+w+1 and rows ys-2 .. ys+hh+1 (periodic).
 void build_items(lbac_batch* b) {
-    constexpr int W = tile_width<kBatchBX>();
+    constexpr int W = kTileW;
     b->items.clear();
     b->item_nodes.clear();
     for (int k = 0; k < (int)b->inst.size(); ++k) {

@@ -51,11 +51,18 @@ struct lbac_ctx {
     double* host5 = nullptr; // pinned
     int cur = 0;
     int64_t t = 0;
+    int variant = LBAC_KERNEL_BLOCK;
     int bx = 256, strip_h = 64;
     int graph_chunk = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gexec_chunk[2] = {0, 0};
     bool in_batch = false;   // owned by a batch: lbac_free refuses it
+    // learned closure (FP32 plain storage only)
+    bool closure = false;
+    float cl_theta = 0.f;
+    float* cl_param = nullptr;   // FP32 parameters as given
+    uint16_t* cl_w = nullptr;    // packed BF16 weights
+    float* cl_b = nullptr;       // padded biases
     std::string err;
 };
 

@@ -63,6 +63,9 @@ struct StepArgs {
     double eps, tau, delta;
     int32_t nbx, nby;       // tiles of the step launch (columns blocks x strips)
     int32_t n_xcd;          // XCDs the workgroups are dispatched over
+    const uint16_t* cl_w;   // learned closure: packed BF16 weights (ClosurePack layout), or null
+    const float* cl_b;      // learned closure: biases b1[64], b2[64], b3[32] (rows >= 2 zero)
+    float cl_theta;         // closure band: theta < clip(phi) < 1 - theta
 };
 
 __device__ __forceinline__ int wrap_idx(int a, int n) {
@@ -257,7 +260,7 @@ struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
 };
 
 // ---------------------------------------------------------------------------
-// The step on one tile.  A block of BX threads owns BX - 4 output columns
+// The step on one tile, block-wide variant.  A block of BX threads owns BX - 4 output columns
 // (tiles overlap by two columns on each side): lane l loads lattice column
 // x0 - 2 + l of every plane, lanes 1..BX-2 form phi and psi, lanes 2..BX-3
 // update, so every lane runs the same instruction stream (no halo passes).
@@ -277,7 +280,7 @@ __host__ __device__ constexpr int tile_width() {
 // (odd strips are flipped so that two strips sharing a boundary read its halo
 // rows at about the same time, while they are still in cache).
 template <typename R, int ST, int MODEL, int BX>
-__device__ __forceinline__ void step_tile(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
+__device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
                                           TileLds<R, BX>& lds) {
     constexpr int W = tile_width<BX>();
     auto& ring = lds.ring;
@@ -441,7 +444,7 @@ __device__ __forceinline__ void step_tile(const StepArgs& a, int bxi, int syi, i
 }
 
 template <typename R, int ST, int MODEL, int BX>
-__global__ __launch_bounds__(BX) void step_kernel(StepArgs a) {
+__global__ __launch_bounds__(BX) void step_kernel_lds(StepArgs a) {
     __shared__ TileLds<R, BX> lds;
     // XCD-aware tile order: workgroups are dispatched round-robin over the
     // XCDs, so XCD (g mod n_xcd) is given one contiguous row-major range of
@@ -452,7 +455,447 @@ __global__ __launch_bounds__(BX) void step_kernel(StepArgs a) {
     const int per = ntile / a.n_xcd, extra = ntile % a.n_xcd;
     const int tile = xcd * per + min(xcd, extra) + k;
     const int bxi = tile % a.nbx, syi = tile / a.nbx;
-    step_tile<R, ST, MODEL, BX>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+    step_tile_lds<R, ST, MODEL, BX>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+}
+
+// ---------------------------------------------------------------------------
+// The step on one tile, one wavefront per tile.
+//
+// A wavefront owns kTileW = 60 output columns and marches a strip of
+// a.strip_h rows.  Lane l loads lattice column x0 - 2 + l of every plane;
+// lanes 1..62 form phi and psi, lanes 2..61 update, so neighbouring tiles
+// overlap by two columns on each side.  Everything stays in registers: the
+// last three rows of each plane, the pulled populations, three rows of psi.
+// A neighbour in x is one lane away and is read with a DPP wave shift, so
+// there is no LDS, no barrier, and every lane runs every instruction (only
+// the stores are masked).  DIR = +1 marches up the strip, -1 down it.
+constexpr int kWave = 64;
+constexpr int kTileW = kWave - 4;
+
+// lane l receives the value of lane l - 1 (wave_shr:1) or l + 1 (wave_shl:1)
+constexpr int kDppFromLeft = 0x138;
+constexpr int kDppFromRight = 0x130;
+
+template <int CTRL>
+__device__ __forceinline__ float lane_shift(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xf, 0xf, false));
+}
+template <int CTRL>
+__device__ __forceinline__ double lane_shift(double v) {
+    const long long b = __builtin_bit_cast(long long, v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffll), CTRL, 0xf, 0xf, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xf, 0xf, false);
+    return __builtin_bit_cast(double, ((long long)hi << 32) | (unsigned int)lo);
+}
+// value of lane l - cx (the pulled population of a direction with x-component cx)
+template <int CX, typename R>
+__device__ __forceinline__ R from_lane(R v) {
+    if constexpr (CX == 1) return lane_shift<kDppFromLeft>(v);
+    else if constexpr (CX == -1) return lane_shift<kDppFromRight>(v);
+    else return v;
+}
+
+template <typename R, int ST, int MODEL, int DIR, int Q>
+__device__ __forceinline__ R pulled(const R (&r0)[9], const R (&r1)[9], const R (&r2)[9]) {
+    // plane Q is read at row c - cy(Q); the centre row c is r - DIR, so the
+    // row is the newest (r0) when DIR * cy(Q) = -1, r1 when cy(Q) = 0, and
+    // r2 (loaded two rows ago) when DIR * cy(Q) = +1
+    constexpr int d = DIR * cy(Q);
+    const R v = d == -1 ? r0[Q] : (d == 0 ? r1[Q] : r2[Q]);
+    return from_lane<cx(Q)>(v);
+}
+
+// ---- learned closure: fused BF16 MFMA inference ------------------------------
+// Packed weights (built on the device by closure_pack_kernel): W1 as 64 rows of
+// 32 (inputs 25..31 zero), W2 64 x 64, W3 as 32 rows of 64 (rows 2..31 zero),
+// all BF16, row-major.  The network runs on the 64 samples of a wavefront as
+// three chained products Z^T = W H^T with the 32x32x8 BF16 MFMA (features on
+// the M side, samples on the N side): the FP32 accumulator tile of one layer
+// holds, per lane, exactly the K-fragment the next layer's B operand needs,
+// so only the input stencils pass through LDS.
+constexpr int kClW1 = 0, kClW2 = kClW1 + 64 * 32, kClW3 = kClW2 + 64 * 64, kClWN = kClW3 + 32 * 64;
+constexpr int kClB1 = 0, kClB2 = 64, kClB3 = 128, kClBN = 160;
+
+typedef short bf16x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x16_t __attribute__((ext_vector_type(16)));
+
+struct ClosureLds {
+    uint16_t w[kClWN];
+    float b[kClBN];
+    uint16_t x[kWave * 32];  // the wavefront's stencils, one row of 32 BF16 per sample
+};
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    // round to nearest even (inputs are finite)
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// tanh form of GELU, tanh(u) = 1 - 2 / (exp(2u) + 1) with the hardware exp2
+__device__ __forceinline__ float gelu_fast(float x) {
+    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * u);  // exp(2u)
+    return 0.5f * x * (2.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f));
+}
+
+// All 64 lanes must call this together.  xin: this lane's 25 inputs;
+// returns this lane's correction (cx, cy).
+__device__ __forceinline__ void closure_mlp(ClosureLds& L, const float (&xin)[25], float& cxo, float& cyo) {
+    const int l = threadIdx.x % kWave;
+    const int lr = l % 32, lk = 4 * (l / 32);
+    uint16_t* xs = L.x;
+#pragma unroll
+    for (int k = 0; k < 32; k += 2) {
+        const uint32_t lo = k < 25 ? bf16_bits(xin[k]) : 0u;
+        const uint32_t hi = k + 1 < 25 ? bf16_bits(xin[k + 1]) : 0u;
+        *reinterpret_cast<uint32_t*>(&xs[l * 32 + k]) = lo | (hi << 16);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+
+    bf16x4_t h1[2][2][4], h2[2][2][4];
+    // layer 1: Z1^T (64 hidden x 64 samples) = W1 (64 x 32) X^T (32 x 64)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16_t acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB1 + 32 * mt + 8 * (v / 4) + lk + (v % 4)];
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x4_t A = *reinterpret_cast<const bf16x4_t*>(&L.w[kClW1 + (32 * mt + lr) * 32 + 8 * ks + lk]);
+                const bf16x4_t B = *reinterpret_cast<const bf16x4_t*>(&xs[(32 * nt + lr) * 32 + 8 * ks + lk]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, acc, 0, 0, 0);
+            }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h1[mt][nt][ks][t] = (short)bf16_bits(gelu_fast(acc[4 * ks + t]));
+        }
+    // layer 2: Z2^T = W2 (64 x 64) H1^T (64 x 64)
+#pragma unroll
+    for (int mt = 0; mt < 2; ++mt)
+#pragma unroll
+        for (int nt = 0; nt < 2; ++nt) {
+            f32x16_t acc;
+#pragma unroll
+            for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB2 + 32 * mt + 8 * (v / 4) + lk + (v % 4)];
+#pragma unroll
+            for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+                for (int ks = 0; ks < 4; ++ks) {
+                    const bf16x4_t A =
+                        *reinterpret_cast<const bf16x4_t*>(&L.w[kClW2 + (32 * mt + lr) * 64 + 32 * kt + 8 * ks + lk]);
+                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, h1[kt][nt][ks], acc, 0, 0, 0);
+                }
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks)
+#pragma unroll
+                for (int t = 0; t < 4; ++t) h2[mt][nt][ks][t] = (short)bf16_bits(gelu_fast(acc[4 * ks + t]));
+        }
+    // layer 3: out^T (2 of 32 rows x 64 samples) = W3 (32 x 64) H2^T
+    float o[2][2];
+#pragma unroll
+    for (int nt = 0; nt < 2; ++nt) {
+        f32x16_t acc;
+#pragma unroll
+        for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB3 + 8 * (v / 4) + lk + (v % 4)];
+#pragma unroll
+        for (int kt = 0; kt < 2; ++kt)
+#pragma unroll
+            for (int ks = 0; ks < 4; ++ks) {
+                const bf16x4_t A = *reinterpret_cast<const bf16x4_t*>(&L.w[kClW3 + lr * 64 + 32 * kt + 8 * ks + lk]);
+                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, h2[kt][nt][ks], acc, 0, 0, 0);
+            }
+        o[nt][0] = acc[0];  // row 0 (c_x) of sample 32 nt + lr, valid on lanes 0..31
+        o[nt][1] = acc[1];  // row 1 (c_y)
+    }
+    // sample l lives in tile l / 32 at lane l % 32
+    const float t0 = __shfl(o[1][0], (l + 32) & 63, kWave);
+    const float t1 = __shfl(o[1][1], (l + 32) & 63, kWave);
+    cxo = l < 32 ? o[0][0] : t0;
+    cyo = l < 32 ? o[0][1] : t1;
+    __builtin_amdgcn_wave_barrier();  // the staging rows are reused by the next call
+}
+
+// Stages the packed closure weights into LDS (all threads of the block).
+__device__ __forceinline__ void closure_stage(const StepArgs& a, ClosureLds& L) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.cl_w);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(L.w);
+    for (int i = threadIdx.x; i < kClWN / 2; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < kClBN; i += blockDim.x) L.b[i] = a.cl_b[i];
+    __syncthreads();
+}
+
+// Builds the packed BF16 weights and padded biases from the FP32 parameter
+// vector W1[64][25], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+static __global__ void closure_pack_kernel(const float* __restrict__ p, uint16_t* __restrict__ w,
+                                           float* __restrict__ b) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < 64 * 32) {
+        const int r = i / 32, k = i % 32;
+        w[kClW1 + i] = k < 25 ? bf16_bits(p[r * 25 + k]) : 0;
+    }
+    if (i < 64 * 64) w[kClW2 + i] = bf16_bits(p[1600 + 64 + i]);
+    if (i < 32 * 64) {
+        const int r = i / 64, k = i % 64;
+        w[kClW3 + i] = r < 2 ? bf16_bits(p[1600 + 64 + 4096 + 64 + r * 64 + k]) : 0;
+    }
+    if (i < 64) {
+        b[kClB1 + i] = p[1600 + i];
+        b[kClB2 + i] = p[1600 + 64 + 4096 + i];
+    }
+    if (i < 32) b[kClB3 + i] = i < 2 ? p[1600 + 64 + 4096 + 64 + 128 + i] : 0.f;
+}
+
+// ---- the wavefront step ----------------------------------------------------
+// Without the closure: halo 2, tiles of 60 columns, row y = c - DIR updated.
+// With the closure: halo 3 (the 5x5 stencil of phi needs phi two columns out),
+// tiles of 58 columns, and the update waits one more row (phi on y +- 2).
+template <bool CLOSURE>
+struct WaveGeom {
+    static constexpr int kHalo = CLOSURE ? 3 : 2;
+    static constexpr int kW = kWave - 2 * kHalo;
+    static constexpr int kDelay = CLOSURE ? 2 : 1;
+};
+
+template <typename R, int ST, int MODEL, int DIR, bool CLOSURE>
+__device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int syi, int64_t t, ClosureLds* cl) {
+    using G = WaveGeom<CLOSURE>;
+    constexpr int D = G::kDelay;
+    const int l = threadIdx.x % kWave;
+    const int x0 = bxi * G::kW;
+    const int w = min(G::kW, a.nx - x0);
+    const int ys = syi * a.strip_h;
+    const int hh = min(a.strip_h, a.ny - ys);
+    const bool upd_lane = l >= G::kHalo && l < G::kHalo + w;
+    const int col = wrap_idx(x0 - G::kHalo + l, a.nx);  // column this lane loads
+    const int x = x0 - G::kHalo + l;                     // column this lane updates (upd_lane)
+    const Io<R, ST> io(a);
+
+    const bool first = (t == 0);
+    const R s_now = R(time_factor(a.period_T, t));
+    const R s_old = first ? s_now : R(time_factor(a.period_T, t - 1));
+    const R Axl = upd_lane ? R(a.vtab[x]) : R(0);
+    const R Bxl = upd_lane ? R(a.vtab[a.nx + x]) : R(0);
+    const R eps = R(a.eps), delta = R(a.delta);
+    const R psi_scale = R(a.eps * 0.69314718055994530942);  // psi = eps ln2 (log2 a - log2 b)
+    const R s_scale = R(1.0 / (a.eps * (1.0 + 2.0 * a.delta) * (1.0 + 2.0 * a.delta)));
+    const R omega = R(1.0 / a.tau);
+    const R kforce = R(1.0 - 0.5 / a.tau);
+    const R keep = R(1.0 - 1.0 / a.tau);
+
+    R r0[9], r1[9], r2[9];   // rows r, r - DIR, r - 2 DIR of every plane (own column)
+    R fh[D + 1][9];          // pulled populations on rows c, c - DIR, ...
+    R ph[2 * D + 1];         // phi on rows c, c - DIR, ...
+    R ps[D + 2];             // psi on rows c, c - DIR, ...
+    R P[D + 2];              // own-column phi at t-1 on rows r, r - DIR, ...
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        r0[q] = r1[q] = r2[q] = R(0);
+#pragma unroll
+        for (int j = 0; j <= D; ++j) fh[j][q] = R(0);
+    }
+#pragma unroll
+    for (int j = 0; j < 2 * D + 1; ++j) ph[j] = R(0);
+#pragma unroll
+    for (int j = 0; j < D + 2; ++j) ps[j] = P[j] = R(0);
+
+    const int start = DIR > 0 ? ys - (D + 1) : ys + hh + D;
+    R nv[9];  // prefetch registers for the next row
+    io.load((uint32_t)wrap_idx(start, a.ny) * (uint32_t)a.pitch + (uint32_t)col, nv);
+
+    const int iters = hh + 2 * (D + 1);
+    for (int it = 0; it < iters; ++it) {
+        // ---- row r = start + DIR it becomes the newest row
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            r2[q] = r1[q];
+            r1[q] = r0[q];
+            r0[q] = nv[q];
+        }
+#pragma unroll
+        for (int j = D + 1; j > 0; --j) P[j] = P[j - 1];
+        if constexpr (Io<R, ST>::kShifted) {
+            P[0] = r0[0];  // phi* itself
+        } else {
+            R s = R(0);
+#pragma unroll
+            for (int q = 0; q < 9; ++q) s += r0[q];
+            P[0] = s;
+        }
+        if (it + 1 < iters)
+            io.load((uint32_t)wrap_idx(start + DIR * (it + 1), a.ny) * (uint32_t)a.pitch + (uint32_t)col, nv);
+
+        // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row c = r - DIR
+        if (it >= 2) {
+#pragma unroll
+            for (int j = D; j > 0; --j)
+#pragma unroll
+                for (int q = 0; q < 9; ++q) fh[j][q] = fh[j - 1][q];
+#pragma unroll
+            for (int j = 2 * D; j > 0; --j) ph[j] = ph[j - 1];
+#pragma unroll
+            for (int j = D + 1; j > 0; --j) ps[j] = ps[j - 1];
+            R* fc = fh[0];
+            fc[0] = pulled<R, ST, MODEL, DIR, 0>(r0, r1, r2);
+            fc[1] = pulled<R, ST, MODEL, DIR, 1>(r0, r1, r2);
+            fc[2] = pulled<R, ST, MODEL, DIR, 2>(r0, r1, r2);
+            fc[3] = pulled<R, ST, MODEL, DIR, 3>(r0, r1, r2);
+            fc[4] = pulled<R, ST, MODEL, DIR, 4>(r0, r1, r2);
+            fc[5] = pulled<R, ST, MODEL, DIR, 5>(r0, r1, r2);
+            fc[6] = pulled<R, ST, MODEL, DIR, 6>(r0, r1, r2);
+            fc[7] = pulled<R, ST, MODEL, DIR, 7>(r0, r1, r2);
+            fc[8] = pulled<R, ST, MODEL, DIR, 8>(r0, r1, r2);
+            R s;
+            if constexpr (Io<R, ST>::kShifted) {
+                // phi = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] in FP64, rounded once
+                double d = (double)r1[0];
+#pragma unroll
+                for (int q = 1; q < 9; ++q) d += (double)fc[q] - (double)r1[q];
+                fc[0] = R(0);  // the rest population is formed as the remainder after collision
+                s = R(d);
+            } else {
+                s = R(0);
+#pragma unroll
+                for (int q = 0; q < 9; ++q) s += fc[q];
+            }
+            ph[0] = s;
+            if (MODEL == MODEL_CONVENTIONAL) {
+                ps[0] = s;
+            } else {
+                const R pc = s < R(0) ? R(0) : (s > R(1) ? R(1) : s);
+                ps[0] = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
+            }
+        }
+
+        // ---- update row y = c - D DIR
+        if (it >= 2 + 2 * D) {
+            const int y = DIR > 0 ? ys + it - 2 - 2 * D : ys + hh + 1 + 2 * D - it;
+            // psi rows y + 1, y, y - 1 (the march produced y + DIR first)
+            const R pN0 = DIR > 0 ? ps[D - 1] : ps[D + 1], pC0 = ps[D], pS0 = DIR > 0 ? ps[D + 1] : ps[D - 1];
+            const R pE = from_lane<-1>(pC0), pW = from_lane<1>(pC0);
+            const R pNE = from_lane<-1>(pN0), pNW = from_lane<1>(pN0);
+            const R pSE = from_lane<-1>(pS0), pSW = from_lane<1>(pS0);
+            // isotropic gradient: grad chi = sum_i w_i c_i chi(x + c_i) / c_s^2
+            const R gx = (pE - pW) * R(1.0 / 3.0) + ((pNE - pNW) + (pSE - pSW)) * R(1.0 / 12.0);
+            const R gy = (pN0 - pS0) * R(1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * R(1.0 / 12.0);
+            // n = grad psi / (|grad psi| + delta), Eq. (13)
+            const R inv = Math<R>::rcp(Math<R>::sqrt(gx * gx + gy * gy) + delta);
+            const R phi = ph[D];
+            R S;  // sharpening magnitude
+            if (MODEL == MODEL_CONVENTIONAL) {
+                S = phi * (R(1) - phi) / eps;
+            } else {
+                // (1 - tanh^2(psi/(2 eps)))/(4 eps) = a b / (eps (a + b)^2), a = phi_c + delta, b = 1 - phi_c + delta
+                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+                S = (pc + delta) * (R(1) - pc + delta) * s_scale;
+            }
+            const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
+            const R uxr = Axl * Ayv, uyr = Bxl * Byv;
+            const R u = s_now * uxr, v = s_now * uyr;
+            const R phio = first ? phi : P[D + 1];
+            const R uo = s_old * uxr, vo = s_old * uyr;
+            // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
+            const R Sn = R(1.0 / 3.0) * S * inv;
+            R Gx = (phi * u - phio * uo) + Sn * gx;
+            R Gy = (phi * v - phio * vo) + Sn * gy;
+            if constexpr (CLOSURE) {
+                // learned correction of the sharpening flux on interface-band nodes: G += c_s^2 c
+                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+                const bool band = upd_lane && pc > R(a.cl_theta) && pc < R(1) - R(a.cl_theta);
+                if (__any(band)) {
+                    float xin[25];
+#pragma unroll
+                    for (int dy = -2; dy <= 2; ++dy) {
+                        const R row = ph[D - DIR * dy];  // phi on lattice row y + dy
+                        const R w1 = from_lane<1>(row), e1 = from_lane<-1>(row);
+                        xin[(dy + 2) * 5 + 0] = (float)from_lane<1>(w1);
+                        xin[(dy + 2) * 5 + 1] = (float)w1;
+                        xin[(dy + 2) * 5 + 2] = (float)row;
+                        xin[(dy + 2) * 5 + 3] = (float)e1;
+                        xin[(dy + 2) * 5 + 4] = (float)from_lane<-1>(e1);
+                    }
+                    float ccx, ccy;
+                    closure_mlp(*cl, xin, ccx, ccy);
+                    if (band) {
+                        Gx += R(1.0 / 3.0) * R(ccx);
+                        Gy += R(1.0 / 3.0) * R(ccy);
+                    }
+                }
+            }
+            // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)]
+            const R* fp = fh[D];
+            const R A0 = omega * phi;
+            const R bx = R(3) * (A0 * u + kforce * Gx);
+            const R by = R(3) * (A0 * v + kforce * Gy);
+            const R a1 = wq<R>(1) * A0, x1 = wq<R>(1) * bx, y1 = wq<R>(1) * by;
+            const R a5 = wq<R>(5) * A0, x5 = wq<R>(5) * bx, y5 = wq<R>(5) * by;
+            R out[9];
+            out[1] = keep * fp[1] + (a1 + x1);
+            out[2] = keep * fp[2] + (a1 + y1);
+            out[3] = keep * fp[3] + (a1 - x1);
+            out[4] = keep * fp[4] + (a1 - y1);
+            out[5] = keep * fp[5] + ((a5 + x5) + y5);
+            out[6] = keep * fp[6] + ((a5 - x5) + y5);
+            out[7] = keep * fp[7] + ((a5 - x5) - y5);
+            out[8] = keep * fp[8] + ((a5 + x5) - y5);
+            // Eq. (9) conserves sum_i f_i = phi exactly; the rest population is
+            // taken as the remainder so that rounded weights (sum_i w_i != 1 in
+            // floating point) cannot make the total mass drift
+            R rest = phi;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) rest -= out[q];
+            out[0] = rest;
+            if (upd_lane) io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
+        }
+    }
+}
+
+// One step on the tile of column block `bxi` and strip `syi` (a.strip_h rows)
+// at time t, by the calling wavefront.  Odd strips march downward so that
+// two strips sharing a boundary read its halo rows at about the same time,
+// while they are still in cache.
+template <typename R, int ST, int MODEL, bool CLOSURE = false>
+__device__ __forceinline__ void step_wave(const StepArgs& a, int bxi, int syi, int64_t t, ClosureLds* cl = nullptr) {
+    if (syi & 1)
+        step_wave_dir<R, ST, MODEL, -1, CLOSURE>(a, bxi, syi, t, cl);
+    else
+        step_wave_dir<R, ST, MODEL, 1, CLOSURE>(a, bxi, syi, t, cl);
+}
+
+// Tile order shared by the launch kernels: workgroups are dispatched
+// round-robin over the XCDs, so XCD (g mod n_xcd) is given one contiguous
+// row-major range of block tiles; horizontally adjacent tiles then share an
+// L2 and run together.
+__device__ __forceinline__ int xcd_tile(int g, int ntile, int n_xcd) {
+    const int xcd = g % n_xcd, k = g / n_xcd;
+    const int per = ntile / n_xcd, extra = ntile % n_xcd;
+    return xcd * per + min(xcd, extra) + k;
+}
+
+// One launch = one step.  WPB wavefronts per block take WPB horizontally
+// adjacent tiles.
+template <typename R, int ST, int MODEL, int WPB>
+__global__ __launch_bounds__(WPB * kWave) void step_kernel(StepArgs a) {
+    const int nbb = (a.nbx + WPB - 1) / WPB;  // block tiles per strip
+    const int tile = xcd_tile(blockIdx.x, nbb * a.nby, a.n_xcd);
+    const int bxi = (tile % nbb) * WPB + (int)(threadIdx.x / kWave), syi = tile / nbb;
+    if (bxi >= a.nbx) return;  // whole wavefront idle
+    step_wave<R, ST, MODEL>(a, bxi, syi, a.t_dev[0] + a.k);
+}
+
+// One launch = one step with the learned closure (FP32, plain storage, one
+// wavefront per block: 58-column tiles).
+template <int MODEL>
+__global__ __launch_bounds__(kWave) void step_kernel_closure(StepArgs a) {
+    __shared__ ClosureLds cl;
+    closure_stage(a, cl);
+    const int tile = xcd_tile(blockIdx.x, a.nbx * a.nby, a.n_xcd);
+    step_wave<float, ST_PLAIN, MODEL, true>(a, tile % a.nbx, tile / a.nbx, a.t_dev[0] + a.k, &cl);
 }
 
 // ---------------------------------------------------------------------------
@@ -653,7 +1096,6 @@ __global__ __launch_bounds__(kBatchBX) void batch_kernel(const BatchInst* __rest
                                                          const int32_t* __restrict__ wg_off,
                                                          const int32_t* __restrict__ wg_items, int32_t* done,
                                                          BatchCtl* ctl) {
-    __shared__ TileLds<float, kBatchBX> lds;
     const int beg = wg_off[blockIdx.x], end = wg_off[blockIdx.x + 1];
     const int64_t max_steps = ctl->max_steps;
     const bool dry = ctl->dry != 0;
@@ -672,8 +1114,7 @@ __global__ __launch_bounds__(kBatchBX) void batch_kernel(const BatchInst* __rest
                 a.src = a.dst;
                 a.dst = const_cast<void*>(s);
             }
-            step_tile<float, ST_PLAIN, MODEL, kBatchBX>(a, item->bxi, item->syi, a.t_dev[0] + (dry ? 0 : n),
-                                                        item->down != 0, lds);
+            step_wave<float, ST_PLAIN, MODEL>(a, item->bxi, item->syi, a.t_dev[0] + (dry ? 0 : n));
             // publish: this wavefront's stores are visible before the counter moves
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             if (threadIdx.x == 0) __hip_atomic_store(done + id, (int32_t)n, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);

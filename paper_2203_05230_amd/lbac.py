@@ -46,11 +46,16 @@ EXPORTS = [
     "lbac_default_params", "lbac_init", "lbac_init_device", "lbac_free", "lbac_step", "lbac_phi",
     "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
     "lbac_set_launch", "lbac_get_launch", "lbac_autotune", "lbac_set_graph_chunk", "lbac_bytes_per_node",
+    "lbac_set_closure",
     "lbac_stream", "lbac_strerror", "lbac_last_error",
     "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
     "lbac_batch_set_shape", "lbac_batch_get_shape", "lbac_batch_autotune", "lbac_batch_set_timeout",
     "lbac_batch_last_error",
+    "lbac_mlp_create", "lbac_mlp_free", "lbac_mlp_get_weights", "lbac_mlp_set_weights", "lbac_mlp_forward",
+    "lbac_mlp_loss_grad", "lbac_mlp_train_step", "lbac_mlp_last_error",
+    "lbac_closure_workspace_bytes", "lbac_closure_extract",
 ]
+MLP_NPARAM = 5954
 
 _lib = None
 
@@ -84,11 +89,12 @@ def load():
     L.lbac_time.argtypes = [C.c_void_p, P(C.c_int64)]
     L.lbac_get_state.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.lbac_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
-    L.lbac_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
-    L.lbac_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+    L.lbac_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    L.lbac_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.lbac_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac_set_graph_chunk.argtypes = [C.c_void_p, C.c_int32]
     L.lbac_bytes_per_node.argtypes = [C.c_void_p, dp]
+    L.lbac_set_closure.argtypes = [C.c_void_p, P(C.c_float), C.c_float]
     L.lbac_stream.argtypes = [C.c_void_p]
     L.lbac_stream.restype = C.c_void_p
     L.lbac_strerror.argtypes = [C.c_int]
@@ -106,9 +112,24 @@ def load():
     L.lbac_batch_set_timeout.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     L.lbac_batch_last_error.argtypes = [C.c_void_p]
     L.lbac_batch_last_error.restype = C.c_char_p
+    fp = P(C.c_float)
+    L.lbac_mlp_create.argtypes = [fp, C.c_void_p, ctx_pp]
+    L.lbac_mlp_free.argtypes = [C.c_void_p]
+    L.lbac_mlp_get_weights.argtypes = [C.c_void_p, fp]
+    L.lbac_mlp_set_weights.argtypes = [C.c_void_p, fp]
+    L.lbac_mlp_forward.argtypes = [C.c_void_p, C.c_void_p, C.c_int64, C.c_void_p]
+    L.lbac_mlp_loss_grad.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, dp, fp]
+    L.lbac_mlp_train_step.argtypes = [C.c_void_p, C.c_void_p, C.c_void_p, C.c_int64, C.c_float, dp]
+    L.lbac_mlp_last_error.argtypes = [C.c_void_p]
+    L.lbac_mlp_last_error.restype = C.c_char_p
+    L.lbac_closure_workspace_bytes.argtypes = [C.c_int32, C.c_int32, C.c_int32]
+    L.lbac_closure_workspace_bytes.restype = C.c_int64
+    L.lbac_closure_extract.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                       C.c_double, C.c_float, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
+                                       C.c_int64, C.c_int64, P(C.c_int64), C.c_void_p]
     for name in EXPORTS:
         if name not in ("lbac_default_params", "lbac_stream", "lbac_strerror", "lbac_last_error",
-                        "lbac_batch_last_error"):
+                        "lbac_batch_last_error", "lbac_mlp_last_error", "lbac_closure_workspace_bytes"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -237,13 +258,15 @@ class Simulation:
         buf = np.ascontiguousarray(buf, dtype=np.uint8)
         _check(load().lbac_set_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), self.h)
 
-    def set_launch(self, bx, strip_h):
-        _check(load().lbac_set_launch(self.h, int(bx), int(strip_h)), self.h)
+    def set_launch(self, bx, strip_h, variant=0):
+        """variant 0: block-wide tiles through LDS; 1: one tile per wavefront in registers."""
+        _check(load().lbac_set_launch(self.h, int(variant), int(bx), int(strip_h)), self.h)
 
     def get_launch(self):
-        bx, sh = C.c_int32(), C.c_int32()
-        _check(load().lbac_get_launch(self.h, C.byref(bx), C.byref(sh)), self.h)
-        return bx.value, sh.value
+        """(bx, strip_h, variant)"""
+        v, bx, sh = C.c_int32(), C.c_int32(), C.c_int32()
+        _check(load().lbac_get_launch(self.h, C.byref(v), C.byref(bx), C.byref(sh)), self.h)
+        return bx.value, sh.value, v.value
 
     def autotune(self, steps=10):
         us = C.c_double()
@@ -252,6 +275,15 @@ class Simulation:
 
     def set_graph_chunk(self, chunk):
         _check(load().lbac_set_graph_chunk(self.h, int(chunk)), self.h)
+
+    def set_closure(self, params, theta=0.02):
+        """Learned closure on (FP32 parameter vector) or off (None)."""
+        if params is None:
+            _check(load().lbac_set_closure(self.h, None, 0.0), self.h)
+            return
+        w = np.ascontiguousarray(params, dtype=np.float32)
+        assert w.size == MLP_NPARAM
+        _check(load().lbac_set_closure(self.h, w.ctypes.data_as(C.POINTER(C.c_float)), float(theta)), self.h)
 
     def bytes_per_node(self):
         b = C.c_double()
@@ -329,3 +361,75 @@ class Batch:
 
     def set_timeout(self, seconds, test_stall=False):
         self._err(load().lbac_batch_set_timeout(self.h, float(seconds), 1 if test_stall else 0))
+
+
+def _fp(a):
+    return a.ctypes.data_as(C.POINTER(C.c_float))
+
+
+class Mlp:
+    """The closure network on the GPU (FP32 training kernels).  Sample arrays
+    are device pointers (for example torch tensors' data_ptr())."""
+
+    def __init__(self, init, stream=None):
+        w = np.ascontiguousarray(init, dtype=np.float32)
+        assert w.size == MLP_NPARAM
+        h = C.c_void_p()
+        _check(load().lbac_mlp_create(_fp(w), stream, C.byref(h)), what="lbac_mlp_create")
+        self.h = h
+
+    def _err(self, rc):
+        if rc != LBAC_OK:
+            raise LbacError(rc, load().lbac_mlp_last_error(self.h).decode())
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbac_mlp_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def weights(self):
+        w = np.empty(MLP_NPARAM, dtype=np.float32)
+        self._err(load().lbac_mlp_get_weights(self.h, _fp(w)))
+        return w
+
+    def set_weights(self, w):
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        self._err(load().lbac_mlp_set_weights(self.h, _fp(w)))
+
+    def forward(self, x_ptr, batch, out_ptr):
+        self._err(load().lbac_mlp_forward(self.h, C.c_void_p(x_ptr), int(batch), C.c_void_p(out_ptr)))
+
+    def loss_grad(self, x_ptr, y_ptr, batch):
+        L = C.c_double()
+        g = np.empty(MLP_NPARAM, dtype=np.float32)
+        self._err(load().lbac_mlp_loss_grad(self.h, C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(batch), C.byref(L),
+                                            _fp(g)))
+        return L.value, g
+
+    def train_step(self, x_ptr, y_ptr, batch, lr, want_loss=False):
+        L = C.c_double()
+        self._err(load().lbac_mlp_train_step(self.h, C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(batch),
+                                             float(lr), C.byref(L) if want_loss else None))
+        return L.value if want_loss else None
+
+
+def closure_extract(phi_f_ptr, nxf, nyf, r, eps_f, eps_c, delta, theta, augment, workspace_ptr, x_ptr, y_ptr,
+                    base, capacity, stream=None):
+    """Appends closure training samples from a fine field (device pointers);
+    returns how many the field yields."""
+    n = C.c_int64()
+    _check(load().lbac_closure_extract(C.c_void_p(phi_f_ptr), int(nxf), int(nyf), int(r), float(eps_f),
+                                       float(eps_c), float(delta), float(theta), 1 if augment else 0,
+                                       C.c_void_p(workspace_ptr), C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(base),
+                                       int(capacity), C.byref(n), stream), what="lbac_closure_extract")
+    return n.value
+
+
+def closure_workspace_bytes(nxf, nyf, r):
+    return int(load().lbac_closure_workspace_bytes(int(nxf), int(nyf), int(r)))

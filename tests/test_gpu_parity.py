@@ -155,7 +155,7 @@ def test_ragged_and_degenerate_grids(gpu_lib, nx, ny):
     rng = np.random.default_rng(nx * 1000 + ny)
     phi0 = W.circle(max(nx, ny), 1.5, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
     ref = O.run(oparams(case), phi0, 40)
-    for launch in ((64, 7), (128, 64), (256, 3)):
+    for launch in ((64, 7, 0), (128, 64, 1), (256, 3, 0), (64, 5, 1)):
         sim = gpu_run(gpu_lib, case, phi0, 40, "f64", launch=launch)
         assert_fp64_parity(sim.phi(), ref, 40, 1.0)
 
@@ -187,7 +187,7 @@ def test_launch_shape_does_not_change_results(gpu_lib, prec):
     case = W.single_vortex_case(320, U=0.05, period_T=100.0)
     phi0 = W.circle(320, 1.0)
     base = None
-    for launch in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17)):
+    for launch in ((256, 64, 0), (64, 5, 0), (128, 320, 0), (256, 1, 1), (64, 17, 1), (128, 40, 1)):
         phi = gpu_run(gpu_lib, case, phi0, 12, prec, launch=launch).phi()
         if base is None:
             base = phi
@@ -293,7 +293,8 @@ def test_full_size_8192_fp32_sampled(gpu_lib):
     case = W.single_vortex_case(n, eps=1.0, period_T=4096.0)
     phi0 = W.circle(n, 1.0)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
-    sim.set_launch(256, 256)
+    sim.autotune(12)  # the same selection the benchmark makes
+    say("  launch", sim.get_launch())
     m0 = sim.mass()
     sim.step(steps)
     m1 = sim.mass()
