@@ -143,8 +143,9 @@ int lbac_get_state(lbac_ctx* h, void* buf, size_t* bytes);
 int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
 
 /* Launch shape of the step kernel.  variant LBAC_KERNEL_BLOCK: a block of bx
- * threads (64, 128 or 256) owns a tile of bx - 4 columns and shares rows
- * through LDS; LBAC_KERNEL_WAVE: every wavefront owns a 60-column tile held
+ * column threads (bx = 64, 128 or 256) plus one wavefront for the halo owns
+ * bx aligned columns and shares rows through LDS; LBAC_KERNEL_WAVE: every
+ * wavefront owns a 60-column tile held
  * in registers, bx / 64 wavefronts per block.  strip_h: rows each tile
  * marches (>= 1).  Results do not depend on the shape or variant (bitwise).
  * LBAC_EINVAL for unsupported values. */
@@ -241,7 +242,11 @@ const char* lbac_last_error(lbac_ctx* h);
 #define LBAC_MLP_NPARAM 5954
 typedef struct lbac_mlp lbac_mlp;
 
-/* init: host, LBAC_MLP_NPARAM finite values (copied); stream: hipStream_t or NULL. */
+/* init: host, LBAC_MLP_NPARAM finite values (copied).  stream: the hipStream_t
+ * every call of this network runs on, or NULL for a non-blocking stream of the
+ * network's own; calls return before the GPU is done, so a caller that
+ * rewrites x_dev / y_dev between calls must order that with this stream
+ * (simplest: pass the stream its own writes run on). */
 int lbac_mlp_create(const float* init, void* stream, lbac_mlp** out);
 int lbac_mlp_free(lbac_mlp* m);
 int lbac_mlp_get_weights(lbac_mlp* m, float* out_host);

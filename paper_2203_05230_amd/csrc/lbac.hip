@@ -162,18 +162,18 @@ hipError_t launch_step_bx(StepArgs a, int variant, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
     if (variant == LBAC_KERNEL_BLOCK) {
-        // one block of bx threads per tile of bx - 4 output columns
-        a.nbx = (a.nx + bx - 5) / (bx - 4);
+        // one block of bx column threads plus one halo wavefront per bx-column tile
+        a.nbx = (a.nx + bx - 1) / bx;
         dim3 grid(a.nbx * a.nby);
         switch (bx) {
         case 64:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64>), grid, dim3(64), 0, s, a);
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64>), grid, dim3(block_threads<64>()), 0, s, a);
             break;
         case 128:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128>), grid, dim3(128), 0, s, a);
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128>), grid, dim3(block_threads<128>()), 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256>), grid, dim3(256), 0, s, a);
+            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256>), grid, dim3(block_threads<256>()), 0, s, a);
             break;
         }
         return hipGetLastError();

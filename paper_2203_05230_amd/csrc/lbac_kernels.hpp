@@ -134,18 +134,18 @@ struct StoreShifted {
         const float ph = a.src_phi[off];
         v[0] = ph;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) v[q] = wq<float>(q) * ph + h2f<H>(s[(q - 1) * a.plane_stride + off]);
+        for (int q = 1; q < 9; ++q) v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(s[(q - 1) * a.plane_stride + off]));
     }
     __device__ __forceinline__ static float load_one(const StepArgs& a, int64_t off, int q) {
         const H* s = static_cast<const H*>(a.src);
         const float ph = a.src_phi[off];
         if (q == 0) return ph;
-        return wq<float>(q) * ph + h2f<H>(s[(q - 1) * a.plane_stride + off]);
+        return __builtin_fmaf(wq<float>(q), ph, h2f<H>(s[(q - 1) * a.plane_stride + off]));
     }
     __device__ __forceinline__ static void store(const StepArgs& a, int64_t off, const float (&v)[9], float phi) {
         H* d = static_cast<H*>(a.dst);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) d[(q - 1) * a.plane_stride + off] = f2h<H>(v[q] - wq<float>(q) * phi);
+        for (int q = 1; q < 9; ++q) d[(q - 1) * a.plane_stride + off] = f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]));
         a.dst_phi[off] = phi;
     }
 };
@@ -193,6 +193,103 @@ struct Math<double> {
     __device__ __forceinline__ static double rcp(double x) { return 1.0 / x; }
     __device__ __forceinline__ static double sqrt(double x) { return ::sqrt(x); }
 };
+
+// ---------------------------------------------------------------------------
+// Node arithmetic shared by every kernel variant.  The library is compiled
+// with automatic multiply-add contraction off and the fused operations are
+// written out here, so every variant rounds identically and the variants
+// (and the batched form) agree bit for bit.
+
+__device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
+template <typename R>
+__device__ __forceinline__ R clip01(R p) {
+    return p < R(0) ? R(0) : (p > R(1) ? R(1) : p);
+}
+
+// Per-step constants of the update.
+template <typename R>
+struct NodeConst {
+    R eps, delta, psi_scale, s_scale, omega, kforce, keep, s_now, s_old;
+    bool first;
+    __device__ __forceinline__ NodeConst(const StepArgs& a, int64_t t) {
+        first = (t == 0);
+        s_now = R(time_factor(a.period_T, t));
+        s_old = first ? s_now : R(time_factor(a.period_T, t - 1));
+        eps = R(a.eps);
+        delta = R(a.delta);
+        psi_scale = R(a.eps * 0.69314718055994530942);  // eps ln 2: psi = eps ln2 (log2 a - log2 b)
+        s_scale = R(1.0 / (a.eps * (1.0 + 2.0 * a.delta) * (1.0 + 2.0 * a.delta)));
+        omega = R(1.0 / a.tau);
+        kforce = R(1.0 - 0.5 / a.tau);
+        keep = R(1.0 - 1.0 / a.tau);
+    }
+};
+
+// The field whose gradient gives the normal: psi of Eq. (13) (clipped phi),
+// or phi itself for the conventional model of Eq. (1).
+template <typename R, int MODEL>
+__device__ __forceinline__ R normal_source(R phi, const NodeConst<R>& k) {
+    if (MODEL == MODEL_CONVENTIONAL) return phi;
+    const R pc = clip01(phi);
+    return k.psi_scale * (Math<R>::log2(pc + k.delta) - Math<R>::log2(R(1) - pc + k.delta));
+}
+
+// Isotropic gradient grad chi = sum_i w_i c_i chi(x + c_i) / c_s^2 from the
+// eight neighbours of a node.
+template <typename R>
+__device__ __forceinline__ void iso_gradient(R pE, R pW, R pN, R pS, R pNE, R pNW, R pSE, R pSW, R& gx, R& gy) {
+    gx = fmaR(pE - pW, R(1.0 / 3.0), ((pNE - pNW) + (pSE - pSW)) * R(1.0 / 12.0));
+    gy = fmaR(pN - pS, R(1.0 / 3.0), ((pNE + pNW) - (pSE + pSW)) * R(1.0 / 12.0));
+}
+
+// Bracket of Eq. (11): d_t(phi u) by explicit Euler plus c_s^2 S n, with
+// n = grad psi / (|grad psi| + delta) (Eq. (13)) and S the sharpening
+// magnitude (Eq. (6) in the algebraic form below, or phi (1 - phi)/eps for
+// the conventional model).  u, v at t; uo, vo at t - 1; phio = phi at t - 1.
+template <typename R, int MODEL>
+__device__ __forceinline__ void flux_bracket(R gx, R gy, R phi, R phio, R u, R v, R uo, R vo, const NodeConst<R>& k,
+                                             R& Gx, R& Gy) {
+    const R inv = Math<R>::rcp(Math<R>::sqrt(fmaR(gx, gx, gy * gy)) + k.delta);
+    R S;
+    if (MODEL == MODEL_CONVENTIONAL) {
+        S = phi * (R(1) - phi) / k.eps;
+    } else {
+        // (1 - tanh^2(psi/(2 eps)))/(4 eps) = a b / (eps (a + b)^2), a = phi_c + delta, b = 1 - phi_c + delta
+        const R pc = clip01(phi);
+        S = (pc + k.delta) * (R(1) - pc + k.delta) * k.s_scale;
+    }
+    const R Sn = R(1.0 / 3.0) * S * inv;
+    Gx = fmaR(Sn, gx, fmaR(phi, u, -(phio * uo)));
+    Gy = fmaR(Sn, gy, fmaR(phi, v, -(phio * vo)));
+}
+
+// Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)].
+// Eq. (9) conserves sum_i f_i = phi exactly; the rest population is taken as
+// the remainder so that rounded weights (sum_i w_i != 1 in floating point)
+// cannot make the total mass drift.
+template <typename R>
+__device__ __forceinline__ void collide(const R* fp, R phi, R u, R v, R Gx, R Gy, const NodeConst<R>& k,
+                                        R (&out)[9]) {
+    const R A0 = k.omega * phi;
+    const R bx = R(3) * fmaR(A0, u, k.kforce * Gx);
+    const R by = R(3) * fmaR(A0, v, k.kforce * Gy);
+    const R a1 = wq<R>(1) * A0, x1 = wq<R>(1) * bx, y1 = wq<R>(1) * by;
+    const R a5 = wq<R>(5) * A0, x5 = wq<R>(5) * bx, y5 = wq<R>(5) * by;
+    out[1] = fmaR(k.keep, fp[1], a1 + x1);
+    out[2] = fmaR(k.keep, fp[2], a1 + y1);
+    out[3] = fmaR(k.keep, fp[3], a1 - x1);
+    out[4] = fmaR(k.keep, fp[4], a1 - y1);
+    out[5] = fmaR(k.keep, fp[5], (a5 + x5) + y5);
+    out[6] = fmaR(k.keep, fp[6], (a5 - x5) + y5);
+    out[7] = fmaR(k.keep, fp[7], (a5 - x5) - y5);
+    out[8] = fmaR(k.keep, fp[8], (a5 + x5) - y5);
+    R rest = phi;
+#pragma unroll
+    for (int q = 1; q < 9; ++q) rest -= out[q];
+    out[0] = rest;
+}
 
 // Uniform per-plane base pointers and 32-bit byte offsets (a plane is far
 // below 4 GiB), so a load or store is one instruction on a scalar base.
@@ -242,11 +339,11 @@ struct IoShifted {
         const float ph = *reinterpret_cast<const float*>(s[0] + off * 4u);
         v[0] = ph;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) v[q] = wq<float>(q) * ph + h2f<H>(*reinterpret_cast<const H*>(s[q] + off * 2u));
+        for (int q = 1; q < 9; ++q) v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(*reinterpret_cast<const H*>(s[q] + off * 2u)));
     }
     __device__ __forceinline__ void store(uint32_t off, const float (&v)[9], float phi) const {
 #pragma unroll
-        for (int q = 1; q < 9; ++q) *reinterpret_cast<H*>(d[q] + off * 2u) = f2h<H>(v[q] - wq<float>(q) * phi);
+        for (int q = 1; q < 9; ++q) *reinterpret_cast<H*>(d[q] + off * 2u) = f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]));
         *reinterpret_cast<float*>(d[0] + off * 4u) = phi;
     }
 };
@@ -260,62 +357,65 @@ struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
 };
 
 // ---------------------------------------------------------------------------
-// The step on one tile, block-wide variant.  A block of BX threads owns BX - 4 output columns
-// (tiles overlap by two columns on each side): lane l loads lattice column
-// x0 - 2 + l of every plane, lanes 1..BX-2 form phi and psi, lanes 2..BX-3
-// update, so every lane runs the same instruction stream (no halo passes).
+// The step on one tile, block-wide variant.
+//
+// A block owns BX aligned columns [x0, x0 + BX) and marches a strip of
+// a.strip_h rows.  Threads 0..BX-1 each own one column; one extra wavefront
+// (threads BX..BX+63) serves the two-column halo on each side: its lanes 0..3
+// load the halo columns and lanes 0..1 form psi there, so no column wave
+// carries halo work and every row of every plane is read and written as
+// whole, aligned cache lines.  Rows are shared through a three-row LDS ring.
 template <typename R, int BX>
 struct TileLds {
-    R ring[3][9][BX];  // rows r-2..r of every plane; index j <-> column x0 - 2 + j
-    R sring[3][BX];    // psi on the last three centre rows, same column index
+    R ring[3][9][BX + 4];  // rows r-2..r of every plane; index j <-> column x0 - 2 + j
+    R sring[3][BX + 2];    // psi on the last three centre rows; index j <-> column x0 - 1 + j
 };
 
 template <int BX>
-__host__ __device__ constexpr int tile_width() {
-    return BX - 4;
+__host__ __device__ constexpr int block_threads() {
+    return BX + 64;
 }
 
-// One step on the tile of column block `bxi` and strip `syi` (a.strip_h rows)
-// at time t.  The strip is marched upward, or downward when `down` is set
-// (odd strips are flipped so that two strips sharing a boundary read its halo
-// rows at about the same time, while they are still in cache).
+// One step on the tile of column block `bxi` and strip `syi` at time t.  The
+// strip is marched upward, or downward when `down` is set (the kernel flips
+// odd strips so that two strips sharing a boundary read its halo rows at
+// about the same time, while they are still in cache).
 template <typename R, int ST, int MODEL, int BX>
 __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
-                                          TileLds<R, BX>& lds) {
-    constexpr int W = tile_width<BX>();
+                                              TileLds<R, BX>& lds) {
     auto& ring = lds.ring;
     auto& sring = lds.sring;
     const int l = threadIdx.x;
-    const int x0 = bxi * W;
-    const int w = min(W, a.nx - x0);
+    const bool colw = l < BX;                 // a column thread
+    const int h = l - BX;                     // halo lane (halo wavefront)
+    const int x0 = bxi * BX;
+    const int w = min(BX, a.nx - x0);
     const int ys = syi * a.strip_h;
     const int hh = min(a.strip_h, a.ny - ys);
-    const bool ld_lane = l < w + 4;
-    const bool psi_lane = l >= 1 && l <= w + 2;
-    const bool upd_lane = l >= 2 && l <= w + 1;
-    const int col = wrap_idx(x0 - 2 + l, a.nx);  // column this lane loads
-    const int x = x0 - 2 + l;                    // column this lane updates (upd_lane)
+    const bool act = colw && l < w;           // owns column x0 + l
+    const bool hl = !colw && h < 4;           // loads halo column
+    const int hj = h < 2 ? h : w + h;         // its ring index: x0-2, x0-1, x0+w, x0+w+1
+    const int lj = act ? l + 2 : hj;          // ring index this thread loads
+    const int lcol = act ? x0 + l : wrap_idx(x0 - 2 + hj, a.nx);
+    const bool ld = act || hl;
+    const bool pl = act || (!colw && h < 2);  // forms psi
+    const int pj = act ? l + 2 : (h == 0 ? 1 : w + 2);  // ring index of that column
+    const int x = x0 + l;
     const Io<R, ST> io(a);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
-    const bool first = (t == 0);
-    const R s_now = R(time_factor(a.period_T, t));
-    const R s_old = first ? s_now : R(time_factor(a.period_T, t - 1));
-    const R Axl = upd_lane ? R(a.vtab[x]) : R(0);
-    const R Bxl = upd_lane ? R(a.vtab[a.nx + x]) : R(0);
-    const R eps = R(a.eps), delta = R(a.delta);
-    const R psi_scale = R(a.eps * 0.69314718055994530942);  // eps ln 2: psi = eps ln2 (log2 a - log2 b)
-    const R s_scale = R(1.0 / (a.eps * (1.0 + 2.0 * a.delta) * (1.0 + 2.0 * a.delta)));
-    const R omega = R(1.0 / a.tau);
-    const R kforce = R(1.0 - 0.5 / a.tau);
-    const R keep = R(1.0 - 1.0 / a.tau);
+    const NodeConst<R> kc(a, t);
+    const R Axl = act ? R(a.vtab[x]) : R(0);
+    const R Bxl = act ? R(a.vtab[a.nx + x]) : R(0);
 
     R fprev[9], fcur[9];
     R phiprev = R(0), phicur = R(0);
     R P2 = R(0), P1 = R(0), P0 = R(0);  // own-column phi at t-1, rows r-2, r-1, r
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fprev[q] = fcur[q] = R(0);
 
     R nv[9];  // prefetch registers for the next row
-    if (ld_lane) io.load((uint32_t)wrap_idx(down ? ys + hh + 1 : ys - 2, a.ny) * (uint32_t)a.pitch + col, nv);
+    if (ld) io.load((uint32_t)wrap_idx(down ? ys + hh + 1 : ys - 2, a.ny) * (uint32_t)a.pitch + lcol, nv);
 
     const int iters = hh + 4;
     for (int it = 0; it < iters; ++it) {
@@ -327,32 +427,32 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
         const int slot_n = down ? slot2 : slot;  // row c + 1
         const int slot_s = down ? slot : slot2;  // row c - 1
         // ---- row r into the ring
-        if (ld_lane) {
+        if (ld) {
             R s = R(0);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                ring[slot][q][l] = nv[q];
+                ring[slot][q][lj] = nv[q];
                 s += nv[q];
             }
             // phi at t-1 on this row: the stored sum (plain) or phi* itself (shifted)
             P0 = Io<R, ST>::kShifted ? nv[0] : s;
         }
         // ---- prefetch row r + dir
-        if (it + 1 < iters && ld_lane)
-            io.load((uint32_t)wrap_idx(down ? ys + hh - it : ys - 1 + it, a.ny) * (uint32_t)a.pitch + col, nv);
+        if (it + 1 < iters && ld)
+            io.load((uint32_t)wrap_idx(down ? ys + hh - it : ys - 1 + it, a.ny) * (uint32_t)a.pitch + lcol, nv);
         lds_barrier();
 
         // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row
-        if (it >= 2 && psi_lane) {
+        if (it >= 2 && pl) {
             R s;
             if constexpr (Io<R, ST>::kShifted) {
                 // phi = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] in FP64, rounded once
-                double d = (double)ring[slot1][0][l];
+                double d = (double)ring[slot1][0][pj];
 #pragma unroll
                 for (int q = 1; q < 9; ++q) {
                     const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
-                    fcur[q] = ring[sl][q][l - cx(q)];
-                    d += (double)fcur[q] - (double)ring[slot1][q][l];
+                    fcur[q] = ring[sl][q][pj - cx(q)];
+                    d += (double)fcur[q] - (double)ring[slot1][q][pj];
                 }
                 fcur[0] = R(0);  // the rest population is formed as the remainder after collision
                 s = R(d);
@@ -361,78 +461,36 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
                     const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
-                    fcur[q] = ring[sl][q][l - cx(q)];
+                    fcur[q] = ring[sl][q][pj - cx(q)];
                     s += fcur[q];
                 }
             }
             phicur = s;
-            R src;
-            if (MODEL == MODEL_CONVENTIONAL) {
-                src = s;
-            } else {
-                const R pc = s < R(0) ? R(0) : (s > R(1) ? R(1) : s);
-                src = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
-            }
-            sring[slot][l] = src;
+            sring[slot][pj - 1] = normal_source<R, MODEL>(s, kc);
         }
         lds_barrier();
 
         // ---- update row y = c - dir
-        if (it >= 4 && upd_lane) {
+        if (it >= 4 && act) {
             const int y = down ? ys + hh + 3 - it : ys + it - 4;
             // psi rows y-1, y, y+1 (the newest psi row is y + dir)
             const int s0 = (it + 2) % 3;
             const int sm = down ? it % 3 : (it + 1) % 3;
             const int sp = down ? (it + 1) % 3 : it % 3;
-            const R pE = sring[s0][l + 1], pW = sring[s0][l - 1];
-            const R pN = sring[sp][l], pS = sring[sm][l];
-            const R pNE = sring[sp][l + 1], pNW = sring[sp][l - 1];
-            const R pSE = sring[sm][l + 1], pSW = sring[sm][l - 1];
-            // isotropic gradient: grad chi = sum_i w_i c_i chi(x + c_i) / c_s^2
-            const R gx = (pE - pW) * R(1.0 / 3.0) + ((pNE - pNW) + (pSE - pSW)) * R(1.0 / 12.0);
-            const R gy = (pN - pS) * R(1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * R(1.0 / 12.0);
-            // n = grad psi / (|grad psi| + delta), Eq. (13)
-            const R inv = Math<R>::rcp(Math<R>::sqrt(gx * gx + gy * gy) + delta);
+            const int j = l + 1;
+            const R pE = sring[s0][j + 1], pW = sring[s0][j - 1];
+            const R pN = sring[sp][j], pS = sring[sm][j];
+            const R pNE = sring[sp][j + 1], pNW = sring[sp][j - 1];
+            const R pSE = sring[sm][j + 1], pSW = sring[sm][j - 1];
+            R gx, gy, Gx, Gy;
+            iso_gradient(pE, pW, pN, pS, pNE, pNW, pSE, pSW, gx, gy);
             const R phi = phiprev;
-            R S;  // sharpening magnitude
-            if (MODEL == MODEL_CONVENTIONAL) {
-                S = phi * (R(1) - phi) / eps;
-            } else {
-                // (1 - tanh^2(psi/(2 eps)))/(4 eps) = a b / (eps (a + b)^2), a = phi_c + delta, b = 1 - phi_c + delta
-                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
-                S = (pc + delta) * (R(1) - pc + delta) * s_scale;
-            }
             const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
             const R uxr = Axl * Ayv, uyr = Bxl * Byv;
-            const R u = s_now * uxr, v = s_now * uyr;
-            const R phio = first ? phi : P2;
-            const R uo = s_old * uxr, vo = s_old * uyr;
-            // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
-            const R Sn = R(1.0 / 3.0) * S * inv;
-            const R Gx = (phi * u - phio * uo) + Sn * gx;
-            const R Gy = (phi * v - phio * vo) + Sn * gy;
-            // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)]
-            const R A0 = omega * phi;
-            const R bx = R(3) * (A0 * u + kforce * Gx);
-            const R by = R(3) * (A0 * v + kforce * Gy);
-            const R a1 = wq<R>(1) * A0, x1 = wq<R>(1) * bx, y1 = wq<R>(1) * by;
-            const R a5 = wq<R>(5) * A0, x5 = wq<R>(5) * bx, y5 = wq<R>(5) * by;
+            flux_bracket<R, MODEL>(gx, gy, phi, kc.first ? phi : P2, kc.s_now * uxr, kc.s_now * uyr, kc.s_old * uxr,
+                                   kc.s_old * uyr, kc, Gx, Gy);
             R out[9];
-            out[1] = keep * fprev[1] + (a1 + x1);
-            out[2] = keep * fprev[2] + (a1 + y1);
-            out[3] = keep * fprev[3] + (a1 - x1);
-            out[4] = keep * fprev[4] + (a1 - y1);
-            out[5] = keep * fprev[5] + ((a5 + x5) + y5);
-            out[6] = keep * fprev[6] + ((a5 - x5) + y5);
-            out[7] = keep * fprev[7] + ((a5 - x5) - y5);
-            out[8] = keep * fprev[8] + ((a5 + x5) - y5);
-            // Eq. (9) conserves sum_i f_i = phi exactly; the rest population is
-            // taken as the remainder so that rounded weights (sum_i w_i != 1 in
-            // floating point) cannot make the total mass drift
-            R rest = phi;
-#pragma unroll
-            for (int q = 1; q < 9; ++q) rest -= out[q];
-            out[0] = rest;
+            collide(fprev, phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, out);
             io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
         }
 #pragma unroll
@@ -444,7 +502,7 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
 }
 
 template <typename R, int ST, int MODEL, int BX>
-__global__ __launch_bounds__(BX) void step_kernel_lds(StepArgs a) {
+__global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs a) {
     __shared__ TileLds<R, BX> lds;
     // XCD-aware tile order: workgroups are dispatched round-robin over the
     // XCDs, so XCD (g mod n_xcd) is given one contiguous row-major range of
@@ -676,17 +734,9 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
     const int x = x0 - G::kHalo + l;                     // column this lane updates (upd_lane)
     const Io<R, ST> io(a);
 
-    const bool first = (t == 0);
-    const R s_now = R(time_factor(a.period_T, t));
-    const R s_old = first ? s_now : R(time_factor(a.period_T, t - 1));
+    const NodeConst<R> kc(a, t);
     const R Axl = upd_lane ? R(a.vtab[x]) : R(0);
     const R Bxl = upd_lane ? R(a.vtab[a.nx + x]) : R(0);
-    const R eps = R(a.eps), delta = R(a.delta);
-    const R psi_scale = R(a.eps * 0.69314718055994530942);  // psi = eps ln2 (log2 a - log2 b)
-    const R s_scale = R(1.0 / (a.eps * (1.0 + 2.0 * a.delta) * (1.0 + 2.0 * a.delta)));
-    const R omega = R(1.0 / a.tau);
-    const R kforce = R(1.0 - 0.5 / a.tau);
-    const R keep = R(1.0 - 1.0 / a.tau);
 
     R r0[9], r1[9], r2[9];   // rows r, r - DIR, r - 2 DIR of every plane (own column)
     R fh[D + 1][9];          // pulled populations on rows c, c - DIR, ...
@@ -764,12 +814,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
                 for (int q = 0; q < 9; ++q) s += fc[q];
             }
             ph[0] = s;
-            if (MODEL == MODEL_CONVENTIONAL) {
-                ps[0] = s;
-            } else {
-                const R pc = s < R(0) ? R(0) : (s > R(1) ? R(1) : s);
-                ps[0] = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
-            }
+            ps[0] = normal_source<R, MODEL>(s, kc);
         }
 
         // ---- update row y = c - D DIR
@@ -780,32 +825,17 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
             const R pE = from_lane<-1>(pC0), pW = from_lane<1>(pC0);
             const R pNE = from_lane<-1>(pN0), pNW = from_lane<1>(pN0);
             const R pSE = from_lane<-1>(pS0), pSW = from_lane<1>(pS0);
-            // isotropic gradient: grad chi = sum_i w_i c_i chi(x + c_i) / c_s^2
-            const R gx = (pE - pW) * R(1.0 / 3.0) + ((pNE - pNW) + (pSE - pSW)) * R(1.0 / 12.0);
-            const R gy = (pN0 - pS0) * R(1.0 / 3.0) + ((pNE + pNW) - (pSE + pSW)) * R(1.0 / 12.0);
-            // n = grad psi / (|grad psi| + delta), Eq. (13)
-            const R inv = Math<R>::rcp(Math<R>::sqrt(gx * gx + gy * gy) + delta);
+            R gx, gy, Gx, Gy;
+            iso_gradient(pE, pW, pN0, pS0, pNE, pNW, pSE, pSW, gx, gy);
             const R phi = ph[D];
-            R S;  // sharpening magnitude
-            if (MODEL == MODEL_CONVENTIONAL) {
-                S = phi * (R(1) - phi) / eps;
-            } else {
-                // (1 - tanh^2(psi/(2 eps)))/(4 eps) = a b / (eps (a + b)^2), a = phi_c + delta, b = 1 - phi_c + delta
-                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
-                S = (pc + delta) * (R(1) - pc + delta) * s_scale;
-            }
             const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
             const R uxr = Axl * Ayv, uyr = Bxl * Byv;
-            const R u = s_now * uxr, v = s_now * uyr;
-            const R phio = first ? phi : P[D + 1];
-            const R uo = s_old * uxr, vo = s_old * uyr;
-            // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
-            const R Sn = R(1.0 / 3.0) * S * inv;
-            R Gx = (phi * u - phio * uo) + Sn * gx;
-            R Gy = (phi * v - phio * vo) + Sn * gy;
+            const R u = kc.s_now * uxr, v = kc.s_now * uyr;
+            flux_bracket<R, MODEL>(gx, gy, phi, kc.first ? phi : P[D + 1], u, v, kc.s_old * uxr, kc.s_old * uyr, kc,
+                                   Gx, Gy);
             if constexpr (CLOSURE) {
                 // learned correction of the sharpening flux on interface-band nodes: G += c_s^2 c
-                const R pc = phi < R(0) ? R(0) : (phi > R(1) ? R(1) : phi);
+                const R pc = clip01(phi);
                 const bool band = upd_lane && pc > R(a.cl_theta) && pc < R(1) - R(a.cl_theta);
                 if (__any(band)) {
                     float xin[25];
@@ -822,34 +852,13 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
                     float ccx, ccy;
                     closure_mlp(*cl, xin, ccx, ccy);
                     if (band) {
-                        Gx += R(1.0 / 3.0) * R(ccx);
-                        Gy += R(1.0 / 3.0) * R(ccy);
+                        Gx = fmaR(R(1.0 / 3.0), R(ccx), Gx);
+                        Gy = fmaR(R(1.0 / 3.0), R(ccy), Gy);
                     }
                 }
             }
-            // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)]
-            const R* fp = fh[D];
-            const R A0 = omega * phi;
-            const R bx = R(3) * (A0 * u + kforce * Gx);
-            const R by = R(3) * (A0 * v + kforce * Gy);
-            const R a1 = wq<R>(1) * A0, x1 = wq<R>(1) * bx, y1 = wq<R>(1) * by;
-            const R a5 = wq<R>(5) * A0, x5 = wq<R>(5) * bx, y5 = wq<R>(5) * by;
             R out[9];
-            out[1] = keep * fp[1] + (a1 + x1);
-            out[2] = keep * fp[2] + (a1 + y1);
-            out[3] = keep * fp[3] + (a1 - x1);
-            out[4] = keep * fp[4] + (a1 - y1);
-            out[5] = keep * fp[5] + ((a5 + x5) + y5);
-            out[6] = keep * fp[6] + ((a5 - x5) + y5);
-            out[7] = keep * fp[7] + ((a5 - x5) - y5);
-            out[8] = keep * fp[8] + ((a5 + x5) - y5);
-            // Eq. (9) conserves sum_i f_i = phi exactly; the rest population is
-            // taken as the remainder so that rounded weights (sum_i w_i != 1 in
-            // floating point) cannot make the total mass drift
-            R rest = phi;
-#pragma unroll
-            for (int q = 1; q < 9; ++q) rest -= out[q];
-            out[0] = rest;
+            collide(fh[D], phi, u, v, Gx, Gy, kc, out);
             if (upd_lane) io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
         }
     }

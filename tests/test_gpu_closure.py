@@ -1,0 +1,128 @@
+"""The learned closure on the GPU: fused BF16 MFMA inference inside the step
+and the training-sample extraction, against the FP64 oracle."""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import closure_ref as CR
+from oracle import lib as O
+from oracle import mlp as M
+from paper_2203_05230_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def bf16_round(x):
+    """Round FP32 values to BF16 (nearest even), returned as float64."""
+    u = np.ascontiguousarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) >> 16 << 16
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def closure_params(seed, out_scale):
+    w = M.init_weights(seed, scale=1.0)
+    p = M.unpack(w)
+    p["W3"] *= out_scale
+    p["b3"][:] = 0.1 * out_scale
+    return M.pack(p).astype(np.float32)
+
+
+def oparams(n, eps, U, T, mlp=None, theta=0.0):
+    return O.Params(n, n, eps=eps, tau=0.8, delta=1e-10, vel_kind=O.VEL_VORTEX, U=U, period_T=T, mlp=mlp, theta=theta)
+
+
+def test_zero_output_layer_is_the_plain_step(gpu_lib):
+    say("case: closure with zero output layer")
+    n = 96
+    case = W.single_vortex_case(n, eps=1.0, U=0.04, period_T=200.0)
+    phi0 = W.circle(n, 1.0)
+    w = closure_params(3, 0.0)
+    w[-2:] = 0.0
+    a = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+    a.set_closure(w, theta=0.01)
+    a.step(60)
+    b = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+    b.step(60)
+    assert np.array_equal(a.phi(), b.phi())
+
+
+@pytest.mark.parametrize("eps", [1.0, 0.5])
+def test_fused_closure_matches_oracle(gpu_lib, eps):
+    """The GPU rounds the network's inputs and hidden activations to BF16; the
+    oracle evaluates the same BF16-rounded weights in FP64.  The difference
+    must stay within 5% of what the closure changes."""
+    say("case: fused closure vs oracle, eps", eps)
+    n, steps, theta = 96, 120, 0.02
+    case = W.single_vortex_case(n, eps=eps, U=0.04, period_T=400.0)
+    phi0 = W.circle(n, eps)
+    w = closure_params(5, 0.02)
+    sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+    sim.set_closure(w, theta=theta)
+    sim.step(steps)
+    got = sim.phi()
+    ref_cl = O.run(oparams(n, eps, 0.04, 400.0, mlp=bf16_round(w), theta=theta), phi0, steps)
+    ref_plain = O.run(oparams(n, eps, 0.04, 400.0), phi0, steps)
+    effect = np.linalg.norm(ref_cl - ref_plain)
+    say("  closure effect %.3e, GPU vs oracle %.3e" % (effect / np.linalg.norm(ref_plain),
+                                                      np.linalg.norm(got - ref_cl) / np.linalg.norm(ref_plain)))
+    assert effect > 1e-4 * np.linalg.norm(ref_plain)
+    assert np.linalg.norm(got - ref_cl) <= 0.05 * effect
+
+
+def test_closure_keeps_mass(gpu_lib):
+    say("case: closure mass")
+    n = 128
+    case = W.single_vortex_case(n, eps=0.5, U=0.02, period_T=1024.0)
+    sim = gpu_lib.Simulation({**case, "precision": "f32"}, W.circle(n, 0.5))
+    sim.set_closure(closure_params(7, 0.05), theta=0.02)
+    m0 = sim.mass()
+    sim.step(300)
+    assert abs(sim.mass() - m0) / m0 <= 1e-6
+
+
+def test_extraction_matches_oracle(gpu_lib):
+    import torch
+
+    say("case: closure sample extraction")
+    r, eps_c = 4, 1.0
+    nf = 160
+    rng = np.random.default_rng(4)
+    phi_f = np.clip(W.circle(nf, r * eps_c, R_frac=0.23, xc_frac=0.47, yc_frac=0.55) + 1e-3 * rng.standard_normal(
+        (nf, nf)), -0.01, 1.01)
+    theta = 0.02
+    phi_c, tx, ty = CR.target(phi_f, r * eps_c, eps_c)
+    mask = CR.band(phi_c, theta)
+    Xr, jj, ii = CR.stencils(phi_c, mask)
+    Yr = np.stack([tx[mask], ty[mask]], 1)
+    ws = torch.empty(gpu_lib.closure_workspace_bytes(nf, nf, r), dtype=torch.uint8, device="cuda")
+    pf = torch.from_numpy(phi_f).cuda()
+    cap = 8 * len(Xr) + 10
+    X = torch.zeros((cap, 25), dtype=torch.float32, device="cuda")
+    Y = torch.zeros((cap, 2), dtype=torch.float32, device="cuda")
+    n = gpu_lib.closure_extract(pf.data_ptr(), nf, nf, r, r * eps_c, eps_c, 1e-10, theta, False, ws.data_ptr(),
+                                X.data_ptr(), Y.data_ptr(), 0, cap)
+    assert n == len(Xr) > 50
+    Xg, Yg = X[:n].cpu().numpy(), Y[:n].cpu().numpy()
+    assert np.max(np.abs(Xg - Xr)) <= 1e-7
+    assert np.max(np.abs(Yg - Yr)) <= 1e-6 * max(1.0, np.max(np.abs(Yr)))
+    # with the square's symmetries: 8 images per node, the first is the node itself
+    n8 = gpu_lib.closure_extract(pf.data_ptr(), nf, nf, r, r * eps_c, eps_c, 1e-10, theta, True, ws.data_ptr(),
+                                 X.data_ptr(), Y.data_ptr(), 0, cap)
+    assert n8 == 8 * n
+    Xa, Ya = X[:n8].cpu().numpy().reshape(n, 8, 25), Y[:n8].cpu().numpy().reshape(n, 8, 2)
+    assert np.array_equal(Xa[:, 0], Xg) and np.array_equal(Ya[:, 0], Yg)
+    # image 1 is the rotation by +90 degrees: stencil rotated, target (x, y) -> (-y, x)
+    st = Xg.reshape(n, 5, 5)  # [dy][dx]
+    rot = np.empty_like(st)
+    for dy in range(-2, 3):
+        for dx in range(-2, 3):
+            # X'(dx, dy) = X(T^-1 (dx, dy)) with T^-1 (dx, dy) = (dy, -dx)
+            rot[:, dy + 2, dx + 2] = st[:, -dx + 2, dy + 2]
+    assert np.array_equal(Xa[:, 1].reshape(n, 5, 5), rot)
+    assert np.allclose(Ya[:, 1], np.stack([-Yg[:, 1], Yg[:, 0]], 1))
