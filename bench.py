@@ -19,6 +19,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -87,11 +89,93 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     e1, e2 = sim.shape_error(phi0)
     m1 = sim.mass()
     assert sim.stream() == stream.cuda_stream
+    # practical ceiling: the same bytes moved in the step's access pattern by a plain copy
+    copy_us = sim.copy_ceiling(20)
     out = dict(ms_total=ms, wall_s=wall, launch=list(launch), e1=e1, e2=e2, mass_drift=abs(m1 - m0) / m0,
-               bytes_per_node=sim.bytes_per_node(), t_end=sim.time())
+               bytes_per_node=sim.bytes_per_node(), t_end=sim.time(), copy_us=copy_us)
     sim.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     return out
+
+
+def batch_leg(lbac, torch, W, count, seed, step_cap):
+    """The batched form on the seeded instance list (sides 128..512, eps in
+    {0.5, 1, 2}, tau in [0.6, 1]; half single vortex, half slotted disk under
+    rotation), every instance advanced min(its run length, step_cap) steps in
+    one persistent launch, against the same list advanced one instance after
+    another through lbac_step (default launch shape, HIP-graph replay)."""
+    cases = W.batch_cases(count=count, seed=seed)
+    phis = [W.initial_field(c) for c in cases]
+    steps = [min(c["steps"], step_cap) for c in cases]
+    updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, steps)))
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    b = lbac.Batch(cases, phis, stream=stream.cuda_stream)
+    b.autotune(4)  # dry runs: the instances' state is kept
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    b.run(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_batch = ev0.elapsed_time(ev1)
+    probe = [0, count // 2 - 1, count // 2, count - 1]
+    got = {k: b.instance(k).phi() for k in probe}
+    shape = b.get_shape()
+    b.close()
+    # the sequential form replays a captured graph of `chunk` steps per
+    # instance; the first chunk (which captures it) runs outside the timed region
+    chunk = 64
+    sims = [lbac.Simulation({**c, "precision": "f32"}, p, stream=stream.cuda_stream) for c, p in zip(cases, phis)]
+    for sim, k in zip(sims, steps):
+        sim.set_graph_chunk(chunk)
+        sim.step(min(k, chunk))
+    torch.cuda.synchronize()
+    seq_updates = float(sum(c["nx"] * c["ny"] * max(0, k - chunk) for c, k in zip(cases, steps)))
+    ev0.record(stream)
+    for sim, k in zip(sims, steps):
+        sim.step(max(0, k - chunk))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms_seq = ev0.elapsed_time(ev1)
+    same = all(np.array_equal(got[k], sims[k].phi()) for k in probe)
+    for sim in sims:
+        sim.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    mlups = updates / (ms_batch * 1e-3) / 1e6
+    seq_mlups = seq_updates / (ms_seq * 1e-3) / 1e6
+    return dict(instances=count, seed=seed, step_cap=step_cap, node_updates=updates, mlups=round(mlups, 1),
+                ms=round(ms_batch, 2), sequential_mlups=round(seq_mlups, 1), sequential_ms=round(ms_seq, 2),
+                speedup=round(mlups / seq_mlups, 3), bitwise_equal_probe=bool(same), shape=list(shape))
+
+
+def closure_leg(lbac, torch, case, phi0, steps, theta=0.02):
+    """The step with the learned closure fused in (BF16 MFMA inference on
+    interface-band nodes) on the benchmark grid, with a seeded network; the
+    cost depends on the band's size, not on the weights' values."""
+    from paper_2203_05230_amd import closure as CL
+
+    w = CL.init_weights(7, out_scale=1e-3)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    sim = lbac.Simulation({**case, "precision": "f32"}, phi0, stream=stream.cuda_stream)
+    sim.set_closure(w, theta=theta)
+    sim.step(4)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    phi = sim.phi()
+    pc = np.clip(phi, 0.0, 1.0)
+    band = int(((pc > theta) & (pc < 1.0 - theta)).sum())
+    sim.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    n = case["nx"] * case["ny"]
+    return dict(steps=steps, ms_per_step=round(ms, 4), mlups=round(n / (ms * 1e-3) / 1e6, 1), band_nodes=band,
+                band_fraction=band / n, mac_per_band_node=5824, theta=theta)
 
 
 def cpu_baseline(phi0, case, steps):
@@ -126,6 +210,9 @@ def main():
     ap.add_argument("--forms", default="f32_f16store,f32_bf16store",
                     help="extra storage forms timed on the same workload ('' for none)")
     ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
+    ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
+    ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
@@ -179,6 +266,14 @@ def main():
                         bytes_per_node=r["bytes_per_node"], e2=r["e2"], e1=r["e1"], mass_drift=r["mass_drift"],
                         e2_vs_plain=r["e2"] / main_run["e2"] if main_run["e2"] > 0 else None,
                         launch=r["launch"])
+    batched = None
+    if args.batch > 0:
+        print("bench: batched form, %d instances" % args.batch, file=sys.stderr, flush=True)
+        batched = batch_leg(lbac, torch, W, args.batch, 0, args.batch_steps)
+    closure = None
+    if args.closure_steps > 0:
+        print("bench: closure", file=sys.stderr, flush=True)
+        closure = closure_leg(lbac, torch, case, phi0, args.closure_steps)
     cpu = None
     if args.cpu_steps > 0:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
@@ -202,11 +297,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic, 0),
-                     "algorithmic_bytes_per_launch": alg_bytes},
+                     "algorithmic_bytes_per_launch": alg_bytes,
+                     "pattern_copy_gbs": round(alg_bytes / (main_run["copy_us"] * 1e-6) / 1e9, 1),
+                     "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / ms_per_step, 4)},
         "shape_error": {"t": main_run["t_end"], "e2": main_run["e2"], "e1": main_run["e1"],
                         "mass_drift": main_run["mass_drift"]},
         "wall_s": round(main_run["wall_s"], 3),
         "forms": forms,
+        "batched": batched,
+        "closure": closure,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -77,7 +77,7 @@ typedef struct lbac_allocator {
 } lbac_allocator;
 
 typedef struct lbac_params {
-    int32_t nx, ny;       /* lattice size, 1 <= nx, ny, nx * ny < 2^31 / 16 */
+    int32_t nx, ny;       /* lattice size, 1 <= nx, ny <= 65536, nx * ny <= 2^27 */
     double eps;           /* interface width (> 0), width convention above */
     double tau;           /* relaxation time (> 1/2); M = (tau - 1/2) / 3 */
     double delta;         /* regulariser of Eq. (13) (>= 0), same in psi and n */
@@ -144,13 +144,15 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
 
 /* Launch shape of the step kernel.  variant LBAC_KERNEL_BLOCK: a block of bx
  * column threads (bx = 64, 128 or 256) plus one wavefront for the halo owns
- * bx aligned columns and shares rows through LDS; LBAC_KERNEL_WAVE: every
- * wavefront owns a 60-column tile held
- * in registers, bx / 64 wavefronts per block.  strip_h: rows each tile
- * marches (>= 1).  Results do not depend on the shape or variant (bitwise).
- * LBAC_EINVAL for unsupported values. */
+ * bx aligned columns and shares rows through LDS, with the next row's loads
+ * in flight while a row is processed; LBAC_KERNEL_BLOCK_DEEP: the same with
+ * two rows in flight; LBAC_KERNEL_WAVE: every wavefront owns a 60-column
+ * tile held in registers, bx / 64 wavefronts per block.  strip_h: rows each
+ * tile marches (>= 1).  Results do not depend on the shape or variant
+ * (bitwise).  LBAC_EINVAL for unsupported values. */
 #define LBAC_KERNEL_BLOCK 0
 #define LBAC_KERNEL_WAVE 1
+#define LBAC_KERNEL_BLOCK_DEEP 2
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
 int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
@@ -164,16 +166,30 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step);
 int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk);
 
 /* Learned closure in the step (LBAC_F32 contexts): params = the network's
- * LBAC_MLP_NPARAM FP32 parameters (host, copied; layout below); the kernel
- * runs the network in BF16 with FP32 accumulation (MFMA) on the 5x5
- * neighbourhood of phi at every node whose clipped phi lies in
- * (theta, 1 - theta), and adds its output to the sharpening flux S n of
- * Eq. (11).  params == NULL switches the closure off.  LBAC_EINVAL for
- * another precision, theta outside [0, 0.5) or non-finite parameters. */
+ * LBAC_MLP_NPARAM FP32 parameters (host, copied; layout below).  At every
+ * node whose clipped phi lies in (theta, 1 - theta) the network, run in BF16
+ * with FP32 accumulation (MFMA) on the 5x5 neighbourhood of phi, gives a
+ * correction c that is added to the sharpening flux S n of Eq. (11).  Each
+ * step then runs the block-variant step kernel (which records the band),
+ * a scan that lists the band nodes and a pass that adds the correction's
+ * effect on the post-collision populations at those nodes (the collision is
+ * linear in G).  Needs device memory for nx * ny list entries.
+ * params == NULL switches the closure off.  LBAC_EINVAL for another
+ * precision, a batch instance, theta outside [0, 0.5) or non-finite
+ * parameters. */
 int lbac_set_closure(lbac_ctx* h, const float* params, float theta);
 
 /* HBM bytes one step moves by design (read + write of the stored state). */
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
+
+/* Practical bandwidth ceiling of the step: a plain copy of the stored state
+ * into the context's second buffer with the step kernel's tiling (256-column
+ * tiles marching strips of rows, the same tile order) and access order but
+ * none of its arithmetic.  Times `launches` (>= 1) launches at strip heights
+ * 8, 16, 32 and 64 and gives the fastest mean in *us_per_launch.  Moves the
+ * same bytes per node as a step (lbac_bytes_per_node).  The state is
+ * unchanged.  Synchronises. */
+int lbac_copy_ceiling(lbac_ctx* h, int32_t launches, double* us_per_launch);
 
 /* hipStream_t of the context. */
 void* lbac_stream(lbac_ctx* h);

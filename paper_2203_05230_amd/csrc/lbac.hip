@@ -65,6 +65,9 @@ void release(lbac_ctx* h) {
     dev_free(h, h->cl_param);
     dev_free(h, h->cl_w);
     dev_free(h, h->cl_b);
+    dev_free(h, h->cl_mask);
+    dev_free(h, h->cl_list);
+    dev_free(h, h->cl_count);
     if (h->host5) (void)hipHostFree(h->host5);
     if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
 }
@@ -152,6 +155,8 @@ StepArgs lbac_host::make_args(const lbac_ctx* h, int src, int32_t k) {
     a.cl_w = h->cl_w;
     a.cl_b = h->cl_b;
     a.cl_theta = h->cl_theta;
+    a.cl_mask = h->closure ? h->cl_mask : nullptr;
+    a.cl_words = h->cl_words;
     return a;
 }
 
@@ -161,19 +166,29 @@ template <typename R, int ST, int MODEL>
 hipError_t launch_step_bx(StepArgs a, int variant, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
-    if (variant == LBAC_KERNEL_BLOCK) {
+    if (variant == LBAC_KERNEL_BLOCK || variant == LBAC_KERNEL_BLOCK_DEEP) {
         // one block of bx column threads plus one halo wavefront per bx-column tile
         a.nbx = (a.nx + bx - 1) / bx;
         dim3 grid(a.nbx * a.nby);
+        const bool deep = variant == LBAC_KERNEL_BLOCK_DEEP;
         switch (bx) {
         case 64:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64>), grid, dim3(block_threads<64>()), 0, s, a);
+            if (deep)
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64, 2>), grid, dim3(block_threads<64>()), 0, s, a);
+            else
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 64, 1>), grid, dim3(block_threads<64>()), 0, s, a);
             break;
         case 128:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128>), grid, dim3(block_threads<128>()), 0, s, a);
+            if (deep)
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128, 2>), grid, dim3(block_threads<128>()), 0, s, a);
+            else
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 128, 1>), grid, dim3(block_threads<128>()), 0, s, a);
             break;
         default:
-            hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256>), grid, dim3(block_threads<256>()), 0, s, a);
+            if (deep)
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256, 2>), grid, dim3(block_threads<256>()), 0, s, a);
+            else
+                hipLaunchKernelGGL((step_kernel_lds<R, ST, MODEL, 256, 1>), grid, dim3(block_threads<256>()), 0, s, a);
             break;
         }
         return hipGetLastError();
@@ -206,14 +221,20 @@ hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a) {
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
     if (h->closure) {
-        // one wavefront per 58-column tile; FP32 plain storage
-        a.nbx = (a.nx + WaveGeom<true>::kW - 1) / WaveGeom<true>::kW;
-        a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
-        a.n_xcd = kXcds;
-        if (h->p.model == LBAC_MODEL_CONVENTIONAL)
-            hipLaunchKernelGGL(step_kernel_closure<MODEL_CONVENTIONAL>, dim3(a.nbx * a.nby), dim3(kWave), 0, h->stream, a);
-        else
-            hipLaunchKernelGGL(step_kernel_closure<MODEL_IMPROVED>, dim3(a.nbx * a.nby), dim3(kWave), 0, h->stream, a);
+        // FP32 plain storage.  The block variants write the band masks; then the
+        // band list is rebuilt and the correction pass adds the network's flux
+        // correction at the listed nodes.
+        const int variant = h->variant == LBAC_KERNEL_WAVE ? LBAC_KERNEL_BLOCK : h->variant;
+        const hipError_t e = h->p.model == LBAC_MODEL_CONVENTIONAL
+                                 ? launch_step_bx<float, ST_PLAIN, MODEL_CONVENTIONAL>(a, variant, h->bx, h->stream)
+                                 : launch_step_bx<float, ST_PLAIN, MODEL_IMPROVED>(a, variant, h->bx, h->stream);
+        if (e != hipSuccess) return e;
+        const int64_t nwords = (int64_t)h->p.ny * h->cl_words;
+        hipLaunchKernelGGL(closure_reset_kernel, dim3(1), dim3(64), 0, h->stream, h->cl_count);
+        hipLaunchKernelGGL(closure_scan_kernel, dim3((unsigned)((nwords + 255) / 256)), dim3(256), 0, h->stream,
+                           h->cl_mask, nwords, h->cl_words, h->p.nx, h->cl_list, h->cl_count);
+        hipLaunchKernelGGL(closure_apply_kernel, dim3(kClosureBlocks), dim3(kClWaves * kWave), 0, h->stream, a,
+                           h->cl_list, h->cl_count);
         return hipGetLastError();
     }
     switch (h->p.precision) {
@@ -262,8 +283,10 @@ hipError_t launch_aux(const lbac_ctx* h, int which, const StepArgs& a, double* o
 
 int validate(const lbac_params* p, std::string& why) {
     if (!p) return why = "params is NULL", LBAC_EINVAL;
-    if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536 || (int64_t)p->nx * p->ny > (1ll << 31))
-        return why = "grid size out of range", LBAC_EINVAL;
+    // at most 2^27 nodes: every padded plane then stays below 2 GiB, which the
+    // kernels' 32-bit byte offsets and buffer ranges rely on
+    if (p->nx < 1 || p->ny < 1 || p->nx > 65536 || p->ny > 65536 || (int64_t)p->nx * p->ny > (1ll << 27))
+        return why = "grid size out of range (1 <= nx, ny <= 65536, nx * ny <= 2^27)", LBAC_EINVAL;
     if (!(p->tau > 0.5) || !std::isfinite(p->tau)) return why = "tau must exceed 1/2", LBAC_EINVAL;
     if (!(p->eps > 0.0) || !std::isfinite(p->eps)) return why = "eps must be positive", LBAC_EINVAL;
     if (!(p->delta >= 0.0) || !std::isfinite(p->delta)) return why = "delta must be >= 0", LBAC_EINVAL;
@@ -601,7 +624,8 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
 
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (!h) return LBAC_EINVAL;
-    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE) return fail(h, LBAC_EINVAL, "unknown kernel variant");
+    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE && variant != LBAC_KERNEL_BLOCK_DEEP)
+        return fail(h, LBAC_EINVAL, "unknown kernel variant");
     if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
@@ -631,7 +655,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    for (int var = LBAC_KERNEL_BLOCK; var <= LBAC_KERNEL_WAVE && e == hipSuccess; ++var)
+    for (int var = LBAC_KERNEL_BLOCK; var <= LBAC_KERNEL_BLOCK_DEEP && e == hipSuccess; ++var)
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
         for (int sh : hs) {
@@ -690,6 +714,7 @@ int lbac_set_closure(lbac_ctx* h, const float* params, float theta) {
         return LBAC_OK;
     }
     if (h->p.precision != LBAC_F32) return fail(h, LBAC_EINVAL, "the learned closure runs with LBAC_F32 only");
+    if (h->in_batch) return fail(h, LBAC_EINVAL, "the learned closure is not available for batch instances");
     if (!(theta >= 0.f) || !(theta < 0.5f)) return fail(h, LBAC_EINVAL, "theta must lie in [0, 0.5)");
     for (int i = 0; i < LBAC_MLP_NPARAM; ++i)
         if (!std::isfinite(params[i])) return fail(h, LBAC_EINVAL, "non-finite closure parameter");
@@ -697,7 +722,12 @@ int lbac_set_closure(lbac_ctx* h, const float* params, float theta) {
         h->cl_param = (float*)dev_alloc(h, sizeof(float) * LBAC_MLP_NPARAM);
         h->cl_w = (uint16_t*)dev_alloc(h, sizeof(uint16_t) * kClWN);
         h->cl_b = (float*)dev_alloc(h, sizeof(float) * kClBN);
-        if (!h->cl_param || !h->cl_w || !h->cl_b) return fail(h, LBAC_ENOMEM, "closure buffers");
+        h->cl_words = (h->p.nx + 63) / 64;
+        h->cl_mask = (uint64_t*)dev_alloc(h, sizeof(uint64_t) * (size_t)h->cl_words * h->p.ny);
+        h->cl_list = (int32_t*)dev_alloc(h, sizeof(int32_t) * (size_t)h->p.nx * h->p.ny);
+        h->cl_count = (uint32_t*)dev_alloc(h, 256);
+        if (!h->cl_param || !h->cl_w || !h->cl_b || !h->cl_mask || !h->cl_list || !h->cl_count)
+            return fail(h, LBAC_ENOMEM, "closure buffers");
     }
     HIPCHK(h, hipMemcpyAsync(h->cl_param, params, sizeof(float) * LBAC_MLP_NPARAM, hipMemcpyHostToDevice, h->stream));
     hipLaunchKernelGGL(closure_pack_kernel, dim3((64 * 64 + 255) / 256), dim3(256), 0, h->stream, h->cl_param, h->cl_w,
@@ -707,6 +737,47 @@ int lbac_set_closure(lbac_ctx* h, const float* params, float theta) {
     h->closure = true;
     h->cl_theta = theta;
     drop_graphs(h);
+    return LBAC_OK;
+}
+
+int lbac_copy_ceiling(lbac_ctx* h, int32_t launches, double* us_per_launch) {
+    if (!h || launches < 1 || !us_per_launch) return LBAC_EINVAL;
+    DeviceGuard g(h->device);
+    // copies pop[cur] into the other buffer, which the next step overwrites anyway
+    StepArgs a = make_args(h, h->cur, 0);
+    a.n_xcd = kXcds;
+    hipEvent_t e0, e1;
+    HIPCHK(h, hipEventCreate(&e0));
+    HIPCHK(h, hipEventCreate(&e1));
+    hipError_t e = hipSuccess;
+    float best = 1e30f;
+    for (int sh : {8, 16, 32, 64}) {
+        a.strip_h = std::min(sh, a.ny);
+        a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
+        const dim3 grid(((a.nx + 255) / 256) * a.nby), block(256);
+        auto launch = [&]() {
+            if (h->elem_bytes == 8)
+                hipLaunchKernelGGL(pattern_copy_kernel<uint64_t>, grid, block, 0, h->stream, a, h->nplanes);
+            else if (h->elem_bytes == 4)
+                hipLaunchKernelGGL(pattern_copy_kernel<uint32_t>, grid, block, 0, h->stream, a, h->nplanes);
+            else
+                hipLaunchKernelGGL(pattern_copy_kernel<uint16_t>, grid, block, 0, h->stream, a, h->nplanes);
+            return hipGetLastError();
+        };
+        e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int k = 0; k < launches && e == hipSuccess; ++k) e = launch();
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        best = std::min(best, ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) return fail(h, LBAC_EDEVICE, std::string("copy ceiling: ") + hipGetErrorString(e));
+    *us_per_launch = 1000.0 * best / launches;
     return LBAC_OK;
 }
 

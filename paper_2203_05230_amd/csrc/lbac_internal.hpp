@@ -13,6 +13,7 @@ namespace lbac_host {
 
 constexpr int kPlanePadBytes = 4096 + 256;  // staggers plane bases across HBM channels
 constexpr int kXcds = 8;                    // MI355X: workgroups go round-robin over 8 XCDs
+constexpr int kClosureBlocks = 512;         // blocks of the closure correction pass (grid-stride over the band list)
 constexpr uint64_t kStateMagic = 0x4c42414353543031ull;  // "LBACST01"
 
 struct DeviceGuard {
@@ -63,6 +64,10 @@ struct lbac_ctx {
     float* cl_param = nullptr;   // FP32 parameters as given
     uint16_t* cl_w = nullptr;    // packed BF16 weights
     float* cl_b = nullptr;       // padded biases
+    uint64_t* cl_mask = nullptr;  // band masks written by the step kernel
+    int32_t* cl_list = nullptr;   // band node list (up to nx * ny entries)
+    uint32_t* cl_count = nullptr; // entries in cl_list
+    int32_t cl_words = 0;         // mask words per row
     std::string err;
 };
 

@@ -66,7 +66,11 @@ struct StepArgs {
     const uint16_t* cl_w;   // learned closure: packed BF16 weights (ClosurePack layout), or null
     const float* cl_b;      // learned closure: biases b1[64], b2[64], b3[32] (rows >= 2 zero)
     float cl_theta;         // closure band: theta < clip(phi) < 1 - theta
+    uint64_t* cl_mask;      // closure: band mask, one 64-bit word per 64 columns of a row, or null
+    int32_t cl_words;       // words per row of cl_mask
 };
+
+constexpr int kWave = 64;  // wavefront width of CDNA
 
 __device__ __forceinline__ int wrap_idx(int a, int n) {
     int r = a % n;
@@ -208,6 +212,13 @@ __device__ __forceinline__ R clip01(R p) {
     return p < R(0) ? R(0) : (p > R(1) ? R(1) : p);
 }
 
+// Row factor of the velocity tables (Ay or By at row y): the same for the
+// whole workgroup, read through the constant address space so that it is a
+// scalar load, which does not queue behind the rows being prefetched.
+__device__ __forceinline__ double row_factor(const double* vtab, int64_t i) {
+    return ((const __attribute__((address_space(4))) double*)vtab)[i];
+}
+
 // Per-step constants of the update.
 template <typename R>
 struct NodeConst {
@@ -293,6 +304,35 @@ __device__ __forceinline__ void collide(const R* fp, R phi, R u, R v, R Gx, R Gy
 
 // Uniform per-plane base pointers and 32-bit byte offsets (a plane is far
 // below 4 GiB), so a load or store is one instruction on a scalar base.
+// Stores go through raw buffer resources so that a lane with nothing to
+// store passes an offset beyond the resource's range, which the hardware
+// drops: every lane issues the same stores, no branch surrounds them, and the
+// compiler keeps exact count of the memory operations in flight (a branch
+// around stores makes it wait for all of them before the next row's loads
+// may be consumed).  A plane is below 2 GiB (checked at set-up), so the drop
+// offset 2^31 is outside every plane.
+constexpr uint32_t kDropOffset = 0x80000000u;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t plane_rsrc(void* base) {
+    // raw buffer (stride 0), range 2^31 - 1 bytes; dword 3 = 32-bit data format
+    return __builtin_amdgcn_make_buffer_rsrc(base, (short)0, 0x7FFFFFFF, 0x00020000);
+}
+__device__ __forceinline__ void bstore(float v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, (int)off, 0, 0);
+}
+__device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+    const unsigned long long bits = __double_as_longlong(v);
+    u32x2 w;
+    w.x = (unsigned int)bits;
+    w.y = (unsigned int)(bits >> 32);
+    __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
+}
+template <typename H>
+__device__ __forceinline__ void bstore16(H v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
+    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+}
+
 template <typename R, int ST>
 struct Io;
 
@@ -313,10 +353,11 @@ struct Io<R, ST_PLAIN> {
 #pragma unroll
         for (int q = 0; q < 9; ++q) v[q] = *reinterpret_cast<const R*>(s[q] + b);
     }
-    __device__ __forceinline__ void store(uint32_t off, const R (&v)[9], R /*phi*/) const {
-        const uint32_t b = off * (uint32_t)sizeof(R);
+    // stores v at element offset off when `on`; a lane with on == false stores nothing
+    __device__ __forceinline__ void store(bool on, uint32_t off, const R (&v)[9], R /*phi*/) const {
+        const uint32_t b = on ? off * (uint32_t)sizeof(R) : kDropOffset;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) *reinterpret_cast<R*>(d[q] + b) = v[q];
+        for (int q = 0; q < 9; ++q) bstore(v[q], plane_rsrc(d[q]), b);
     }
 };
 
@@ -341,10 +382,12 @@ struct IoShifted {
 #pragma unroll
         for (int q = 1; q < 9; ++q) v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(*reinterpret_cast<const H*>(s[q] + off * 2u)));
     }
-    __device__ __forceinline__ void store(uint32_t off, const float (&v)[9], float phi) const {
+    // stores g_i = v_i - w_i phi and phi* = phi when `on`; a lane with on == false stores nothing
+    __device__ __forceinline__ void store(bool on, uint32_t off, const float (&v)[9], float phi) const {
+        const uint32_t b2 = on ? off * 2u : kDropOffset, b4 = on ? off * 4u : kDropOffset;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) *reinterpret_cast<H*>(d[q] + off * 2u) = f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]));
-        *reinterpret_cast<float*>(d[0] + off * 4u) = phi;
+        for (int q = 1; q < 9; ++q) bstore16(f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q])), plane_rsrc(d[q]), b2);
+        bstore(phi, plane_rsrc(d[0]), b4);
     }
 };
 template <>
@@ -380,7 +423,14 @@ __host__ __device__ constexpr int block_threads() {
 // strip is marched upward, or downward when `down` is set (the kernel flips
 // odd strips so that two strips sharing a boundary read its halo rows at
 // about the same time, while they are still in cache).
-template <typename R, int ST, int MODEL, int BX>
+//
+// Every iteration issues the same global loads, LDS writes and stores from
+// every thread, with no branch around them: work that has no target is
+// pointed at a harmless one (a duplicate LDS write of the same value, a
+// dropped store, a reload of a row already read).  The compiler then counts
+// the memory operations in flight exactly and keeps PF rows of loads
+// outstanding across the row's arithmetic.
+template <typename R, int ST, int MODEL, int BX, int PF>
 __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
                                               TileLds<R, BX>& lds) {
     auto& ring = lds.ring;
@@ -393,11 +443,23 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
     const int ys = syi * a.strip_h;
     const int hh = min(a.strip_h, a.ny - ys);
     const bool act = colw && l < w;           // owns column x0 + l
-    const bool hl = !colw && h < 4;           // loads halo column
-    const int hj = h < 2 ? h : w + h;         // its ring index: x0-2, x0-1, x0+w, x0+w+1
-    const int lj = act ? l + 2 : hj;          // ring index this thread loads
-    const int lcol = act ? x0 + l : wrap_idx(x0 - 2 + hj, a.nx);
-    const bool ld = act || hl;
+    // Column each thread loads and the ring index it fills: a column thread
+    // its own column (idle ones of a narrow last tile: the tile's last
+    // column, a duplicate); halo lanes 0..3 the halo columns x0-2, x0-1,
+    // x0+w, x0+w+1; the other halo lanes duplicate a column thread's load.
+    int lcol, lj;
+    if (colw) {
+        const int c = min(l, w - 1);
+        lcol = x0 + c;
+        lj = c + 2;
+    } else if (h < 4) {
+        lj = h < 2 ? h : w + h;
+        lcol = wrap_idx(x0 - 2 + lj, a.nx);
+    } else {
+        const int c = min(h - 4, w - 1);
+        lcol = x0 + c;
+        lj = c + 2;
+    }
     const bool pl = act || (!colw && h < 2);  // forms psi
     const int pj = act ? l + 2 : (h == 0 ? 1 : w + 2);  // ring index of that column
     const int x = x0 + l;
@@ -408,17 +470,27 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
     const R Axl = act ? R(a.vtab[x]) : R(0);
     const R Bxl = act ? R(a.vtab[a.nx + x]) : R(0);
 
-    R fprev[9], fcur[9];
-    R phiprev = R(0), phicur = R(0);
+    R fprev[9], fcur[9], out[9];
+    R phiprev = R(0), phicur = R(0), phi_out = R(0);
+    // closure band mask: one word per 64 columns of a row (stores dropped when
+    // the closure is off, or for the halo wavefront and waves past the grid)
+    const __amdgpu_buffer_rsrc_t mrs = __builtin_amdgcn_make_buffer_rsrc(
+        a.cl_mask, (short)0, a.cl_mask ? 0x7FFFFFFF : 0, 0x00020000);
+    const int mcol = x0 + (l & ~(kWave - 1));  // first column of this wavefront
+    const bool mlane = colw && (l & (kWave - 1)) == 0 && mcol < a.nx;
+    const float th = a.cl_theta;
     R P2 = R(0), P1 = R(0), P0 = R(0);  // own-column phi at t-1, rows r-2, r-1, r
 #pragma unroll
-    for (int q = 0; q < 9; ++q) fprev[q] = fcur[q] = R(0);
-
-    R nv[9];  // prefetch registers for the next row
-    if (ld) io.load((uint32_t)wrap_idx(down ? ys + hh + 1 : ys - 2, a.ny) * (uint32_t)a.pitch + lcol, nv);
+    for (int q = 0; q < 9; ++q) fprev[q] = fcur[q] = out[q] = R(0);
 
     const int iters = hh + 4;
-    for (int it = 0; it < iters; ++it) {
+    // lattice row that enters the ring at iteration it (clamped: the loads
+    // issued past the strip's last row repeat its last row and are not used)
+    auto row_of = [&](int it) {
+        it = min(it, iters - 1);
+        return (uint32_t)wrap_idx(down ? ys + hh + 1 - it : ys - 2 + it, a.ny);
+    };
+    auto body = [&](const int it, R(&nv)[9]) __attribute__((always_inline)) {
         // row r = start + dir * it enters the ring; phi and psi are formed on the
         // centre row c = r - dir; row c - dir is updated
         const int slot = it % 3;         // ring slot of row r
@@ -427,7 +499,7 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
         const int slot_n = down ? slot2 : slot;  // row c + 1
         const int slot_s = down ? slot : slot2;  // row c - 1
         // ---- row r into the ring
-        if (ld) {
+        {
             R s = R(0);
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
@@ -437,9 +509,8 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
             // phi at t-1 on this row: the stored sum (plain) or phi* itself (shifted)
             P0 = Io<R, ST>::kShifted ? nv[0] : s;
         }
-        // ---- prefetch row r + dir
-        if (it + 1 < iters && ld)
-            io.load((uint32_t)wrap_idx(down ? ys + hh - it : ys - 1 + it, a.ny) * (uint32_t)a.pitch + lcol, nv);
+        // ---- prefetch row r + PF dir into the registers just consumed
+        io.load(row_of(it + PF) * (uint32_t)a.pitch + lcol, nv);
         lds_barrier();
 
         // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row
@@ -470,14 +541,17 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
         }
         lds_barrier();
 
-        // ---- update row y = c - dir
-        if (it >= 4 && act) {
-            const int y = down ? ys + hh + 3 - it : ys + it - 4;
+        // ---- update row y = c - dir.  The first four iterations fill the
+        // pipeline: they skip the arithmetic (a branch without memory
+        // operations) and their stores are dropped.
+        const bool st = act && it >= 4;
+        const int y = min(max(down ? ys + hh + 3 - it : ys + it - 4, 0), a.ny - 1);
+        if (it >= 4) {
             // psi rows y-1, y, y+1 (the newest psi row is y + dir)
             const int s0 = (it + 2) % 3;
             const int sm = down ? it % 3 : (it + 1) % 3;
             const int sp = down ? (it + 1) % 3 : it % 3;
-            const int j = l + 1;
+            const int j = colw ? l + 1 : 1;
             const R pE = sring[s0][j + 1], pW = sring[s0][j - 1];
             const R pN = sring[sp][j], pS = sring[sm][j];
             const R pNE = sring[sp][j + 1], pNW = sring[sp][j - 1];
@@ -485,23 +559,47 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
             R gx, gy, Gx, Gy;
             iso_gradient(pE, pW, pN, pS, pNE, pNW, pSE, pSW, gx, gy);
             const R phi = phiprev;
-            const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
+            const R Ayv = R(row_factor(a.vtab, 2 * a.nx + y)), Byv = R(row_factor(a.vtab, 2 * a.nx + a.ny + y));
             const R uxr = Axl * Ayv, uyr = Bxl * Byv;
             flux_bracket<R, MODEL>(gx, gy, phi, kc.first ? phi : P2, kc.s_now * uxr, kc.s_now * uyr, kc.s_old * uxr,
                                    kc.s_old * uyr, kc, Gx, Gy);
-            R out[9];
             collide(fprev, phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, out);
-            io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
+            phi_out = phi;
+        }
+        io.store(st, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi_out);
+        {
+            const float pc = (float)clip01(phi_out);
+            const uint64_t m = __ballot(st && pc > th && pc < 1.0f - th);
+            const uint32_t moff = mlane && it >= 4 ? (uint32_t)(y * a.cl_words + (mcol >> 6)) * 8u : kDropOffset;
+            typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+            u32x2 mw;
+            mw.x = (unsigned int)m;
+            mw.y = (unsigned int)(m >> 32);
+            __builtin_amdgcn_raw_buffer_store_b64(mw, mrs, (int)moff, 0, 0);
         }
 #pragma unroll
         for (int q = 0; q < 9; ++q) fprev[q] = fcur[q];
         phiprev = phicur;
         P2 = P1;
         P1 = P0;
+    };
+    // PF rows in flight: row r + PF dir is loaded while row r is processed;
+    // with PF = 2 the loop alternates two register sets, so consuming one
+    // never waits for the loads into the other
+    R na[9], nb[9];
+    io.load(row_of(0) * (uint32_t)a.pitch + lcol, na);
+    if constexpr (PF == 1) {
+        for (int it = 0; it < iters; ++it) body(it, na);
+    } else {
+        io.load(row_of(1) * (uint32_t)a.pitch + lcol, nb);
+        for (int it = 0; it < iters; it += 2) {
+            body(it, na);
+            if (it + 1 < iters) body(it + 1, nb);
+        }
     }
 }
 
-template <typename R, int ST, int MODEL, int BX>
+template <typename R, int ST, int MODEL, int BX, int PF>
 __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs a) {
     __shared__ TileLds<R, BX> lds;
     // XCD-aware tile order: workgroups are dispatched round-robin over the
@@ -513,7 +611,7 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
     const int per = ntile / a.n_xcd, extra = ntile % a.n_xcd;
     const int tile = xcd * per + min(xcd, extra) + k;
     const int bxi = tile % a.nbx, syi = tile / a.nbx;
-    step_tile_lds<R, ST, MODEL, BX>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+    step_tile_lds<R, ST, MODEL, BX, PF>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -527,7 +625,6 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // A neighbour in x is one lane away and is read with a DPP wave shift, so
 // there is no LDS, no barrier, and every lane runs every instruction (only
 // the stores are masked).  DIR = +1 marches up the strip, -1 down it.
-constexpr int kWave = 64;
 constexpr int kTileW = kWave - 4;
 
 // lane l receives the value of lane l - 1 (wave_shr:1) or l + 1 (wave_shl:1)
@@ -563,7 +660,7 @@ __device__ __forceinline__ R pulled(const R (&r0)[9], const R (&r1)[9], const R 
     return from_lane<cx(Q)>(v);
 }
 
-// ---- learned closure: fused BF16 MFMA inference ------------------------------
+// ---- learned closure: BF16 MFMA inference ------------------------------------
 // Packed weights (built on the device by closure_pack_kernel): W1 as 64 rows of
 // 32 (inputs 25..31 zero), W2 64 x 64, W3 as 32 rows of 64 (rows 2..31 zero),
 // all BF16, row-major.  The network runs on the 64 samples of a wavefront as
@@ -577,10 +674,12 @@ constexpr int kClB1 = 0, kClB2 = 64, kClB3 = 128, kClBN = 160;
 typedef short bf16x4_t __attribute__((ext_vector_type(4)));
 typedef float f32x16_t __attribute__((ext_vector_type(16)));
 
+constexpr int kClWaves = 4;  // wavefronts per block of the closure kernel
+
 struct ClosureLds {
     uint16_t w[kClWN];
     float b[kClBN];
-    uint16_t x[kWave * 32];  // the wavefront's stencils, one row of 32 BF16 per sample
+    uint16_t x[kClWaves][kWave * 32];  // each wavefront's stencils, one row of 32 BF16 per sample
 };
 
 __device__ __forceinline__ uint16_t bf16_bits(float f) {
@@ -602,7 +701,7 @@ __device__ __forceinline__ float gelu_fast(float x) {
 __device__ __forceinline__ void closure_mlp(ClosureLds& L, const float (&xin)[25], float& cxo, float& cyo) {
     const int l = threadIdx.x % kWave;
     const int lr = l % 32, lk = 4 * (l / 32);
-    uint16_t* xs = L.x;
+    uint16_t* xs = L.x[(threadIdx.x / kWave) % kClWaves];
 #pragma unroll
     for (int k = 0; k < 32; k += 2) {
         const uint32_t lo = k < 25 ? bf16_bits(xin[k]) : 0u;
@@ -710,19 +809,16 @@ static __global__ void closure_pack_kernel(const float* __restrict__ p, uint16_t
 }
 
 // ---- the wavefront step ----------------------------------------------------
-// Without the closure: halo 2, tiles of 60 columns, row y = c - DIR updated.
-// With the closure: halo 3 (the 5x5 stencil of phi needs phi two columns out),
-// tiles of 58 columns, and the update waits one more row (phi on y +- 2).
-template <bool CLOSURE>
+// Halo 2, tiles of 60 columns, row y = c - DIR updated.
 struct WaveGeom {
-    static constexpr int kHalo = CLOSURE ? 3 : 2;
+    static constexpr int kHalo = 2;
     static constexpr int kW = kWave - 2 * kHalo;
-    static constexpr int kDelay = CLOSURE ? 2 : 1;
+    static constexpr int kDelay = 1;
 };
 
-template <typename R, int ST, int MODEL, int DIR, bool CLOSURE>
-__device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int syi, int64_t t, ClosureLds* cl) {
-    using G = WaveGeom<CLOSURE>;
+template <typename R, int ST, int MODEL, int DIR>
+__device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int syi, int64_t t) {
+    using G = WaveGeom;
     constexpr int D = G::kDelay;
     const int l = threadIdx.x % kWave;
     const int x0 = bxi * G::kW;
@@ -738,6 +834,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
     const R Axl = upd_lane ? R(a.vtab[x]) : R(0);
     const R Bxl = upd_lane ? R(a.vtab[a.nx + x]) : R(0);
 
+    R out[9], phi_out = R(0);  // the update's results (kept across the pipeline-fill iterations)
     R r0[9], r1[9], r2[9];   // rows r, r - DIR, r - 2 DIR of every plane (own column)
     R fh[D + 1][9];          // pulled populations on rows c, c - DIR, ...
     R ph[2 * D + 1];         // phi on rows c, c - DIR, ...
@@ -745,7 +842,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
     R P[D + 2];              // own-column phi at t-1 on rows r, r - DIR, ...
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
-        r0[q] = r1[q] = r2[q] = R(0);
+        r0[q] = r1[q] = r2[q] = out[q] = R(0);
 #pragma unroll
         for (int j = 0; j <= D; ++j) fh[j][q] = R(0);
     }
@@ -777,8 +874,10 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
             for (int q = 0; q < 9; ++q) s += r0[q];
             P[0] = s;
         }
-        if (it + 1 < iters)
-            io.load((uint32_t)wrap_idx(start + DIR * (it + 1), a.ny) * (uint32_t)a.pitch + (uint32_t)col, nv);
+        // unconditional, like the update's stores below, so that the compiler
+        // counts the memory operations in flight exactly (past the strip's
+        // end the last row is reloaded and not used)
+        io.load((uint32_t)wrap_idx(start + DIR * min(it + 1, iters - 1), a.ny) * (uint32_t)a.pitch + (uint32_t)col, nv);
 
         // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row c = r - DIR
         if (it >= 2) {
@@ -817,9 +916,12 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
             ps[0] = normal_source<R, MODEL>(s, kc);
         }
 
-        // ---- update row y = c - D DIR
+        // ---- update row y = c - D DIR.  The first 2 + 2 D iterations fill the
+        // pipeline: they skip the arithmetic (a branch without memory
+        // operations) and their stores are dropped.
+        const bool st = upd_lane && it >= 2 + 2 * D;
+        const int y = min(max(DIR > 0 ? ys + it - 2 - 2 * D : ys + hh + 1 + 2 * D - it, 0), a.ny - 1);
         if (it >= 2 + 2 * D) {
-            const int y = DIR > 0 ? ys + it - 2 - 2 * D : ys + hh + 1 + 2 * D - it;
             // psi rows y + 1, y, y - 1 (the march produced y + DIR first)
             const R pN0 = DIR > 0 ? ps[D - 1] : ps[D + 1], pC0 = ps[D], pS0 = DIR > 0 ? ps[D + 1] : ps[D - 1];
             const R pE = from_lane<-1>(pC0), pW = from_lane<1>(pC0);
@@ -828,39 +930,15 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
             R gx, gy, Gx, Gy;
             iso_gradient(pE, pW, pN0, pS0, pNE, pNW, pSE, pSW, gx, gy);
             const R phi = ph[D];
-            const R Ayv = R(a.vtab[2 * a.nx + y]), Byv = R(a.vtab[2 * a.nx + a.ny + y]);
+            const R Ayv = R(row_factor(a.vtab, 2 * a.nx + y)), Byv = R(row_factor(a.vtab, 2 * a.nx + a.ny + y));
             const R uxr = Axl * Ayv, uyr = Bxl * Byv;
             const R u = kc.s_now * uxr, v = kc.s_now * uyr;
             flux_bracket<R, MODEL>(gx, gy, phi, kc.first ? phi : P[D + 1], u, v, kc.s_old * uxr, kc.s_old * uyr, kc,
                                    Gx, Gy);
-            if constexpr (CLOSURE) {
-                // learned correction of the sharpening flux on interface-band nodes: G += c_s^2 c
-                const R pc = clip01(phi);
-                const bool band = upd_lane && pc > R(a.cl_theta) && pc < R(1) - R(a.cl_theta);
-                if (__any(band)) {
-                    float xin[25];
-#pragma unroll
-                    for (int dy = -2; dy <= 2; ++dy) {
-                        const R row = ph[D - DIR * dy];  // phi on lattice row y + dy
-                        const R w1 = from_lane<1>(row), e1 = from_lane<-1>(row);
-                        xin[(dy + 2) * 5 + 0] = (float)from_lane<1>(w1);
-                        xin[(dy + 2) * 5 + 1] = (float)w1;
-                        xin[(dy + 2) * 5 + 2] = (float)row;
-                        xin[(dy + 2) * 5 + 3] = (float)e1;
-                        xin[(dy + 2) * 5 + 4] = (float)from_lane<-1>(e1);
-                    }
-                    float ccx, ccy;
-                    closure_mlp(*cl, xin, ccx, ccy);
-                    if (band) {
-                        Gx = fmaR(R(1.0 / 3.0), R(ccx), Gx);
-                        Gy = fmaR(R(1.0 / 3.0), R(ccy), Gy);
-                    }
-                }
-            }
-            R out[9];
             collide(fh[D], phi, u, v, Gx, Gy, kc, out);
-            if (upd_lane) io.store((uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi);
+            phi_out = phi;
         }
+        io.store(st, (uint32_t)y * (uint32_t)a.pitch + (uint32_t)x, out, phi_out);
     }
 }
 
@@ -868,12 +946,12 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
 // at time t, by the calling wavefront.  Odd strips march downward so that
 // two strips sharing a boundary read its halo rows at about the same time,
 // while they are still in cache.
-template <typename R, int ST, int MODEL, bool CLOSURE = false>
-__device__ __forceinline__ void step_wave(const StepArgs& a, int bxi, int syi, int64_t t, ClosureLds* cl = nullptr) {
+template <typename R, int ST, int MODEL>
+__device__ __forceinline__ void step_wave(const StepArgs& a, int bxi, int syi, int64_t t) {
     if (syi & 1)
-        step_wave_dir<R, ST, MODEL, -1, CLOSURE>(a, bxi, syi, t, cl);
+        step_wave_dir<R, ST, MODEL, -1>(a, bxi, syi, t);
     else
-        step_wave_dir<R, ST, MODEL, 1, CLOSURE>(a, bxi, syi, t, cl);
+        step_wave_dir<R, ST, MODEL, 1>(a, bxi, syi, t);
 }
 
 // Tile order shared by the launch kernels: workgroups are dispatched
@@ -897,14 +975,113 @@ __global__ __launch_bounds__(WPB * kWave) void step_kernel(StepArgs a) {
     step_wave<R, ST, MODEL>(a, bxi, syi, a.t_dev[0] + a.k);
 }
 
-// One launch = one step with the learned closure (FP32, plain storage, one
-// wavefront per block: 58-column tiles).
-template <int MODEL>
-__global__ __launch_bounds__(kWave) void step_kernel_closure(StepArgs a) {
+// ---- learned closure: band list and correction pass -------------------------
+// Eq. (9)-(11) are linear in G, so adding c_s^2 c to G at a node changes its
+// post-collision populations by (1 - 1/(2 tau)) w_i (c_i . c) for i >= 1 and
+// leaves their sum unchanged.  The step kernel (block variant) records, for
+// every 64 columns of every updated row, a ballot of the interface-band nodes
+// (theta < clip(phi) < 1 - theta); the scan kernel turns the masks into a
+// node list; the apply kernel evaluates the network on 64 listed nodes per
+// wavefront (its 5x5 input stencil of phi(t) rebuilt from the pre-step
+// populations, exactly as the step formed it) and adds the correction.
+
+static __global__ void closure_reset_kernel(uint32_t* count) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) count[0] = 0u;
+}
+
+// Compacts the band masks into node indices y * nx + x (row-major order
+// within a block, blocks in any order).  count must be zero on entry.
+static __global__ __launch_bounds__(256) void closure_scan_kernel(const uint64_t* __restrict__ mask, int64_t nwords,
+                                                                  int words_per_row, int nx,
+                                                                  int32_t* __restrict__ list,
+                                                                  uint32_t* __restrict__ count) {
+    __shared__ uint32_t sh[256];
+    __shared__ uint32_t base;
+    const int64_t wi = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const uint64_t m = wi < nwords ? mask[wi] : 0ull;
+    const uint32_t c = (uint32_t)__popcll(m);
+    sh[threadIdx.x] = c;
+    __syncthreads();
+    // inclusive scan over the block (Hillis-Steele)
+    for (int d = 1; d < 256; d <<= 1) {
+        const uint32_t v = threadIdx.x >= (unsigned)d ? sh[threadIdx.x - d] : 0u;
+        __syncthreads();
+        sh[threadIdx.x] += v;
+        __syncthreads();
+    }
+    if (threadIdx.x == 255) base = sh[255] ? atomicAdd(count, sh[255]) : 0u;
+    __syncthreads();
+    if (m) {
+        uint32_t k = base + sh[threadIdx.x] - c;
+        const int y = (int)(wi / words_per_row), x0 = (int)(wi % words_per_row) * 64;
+        uint64_t r = m;
+        while (r) {
+            const int b = __ffsll((unsigned long long)r) - 1;
+            r &= r - 1;
+            list[k++] = y * nx + x0 + b;
+        }
+    }
+}
+
+// The correction pass (FP32 plain storage): a.src holds the pre-step
+// populations, a.dst the step's result, modified in place at listed nodes.
+// Every wavefront of the grid takes groups of 64 list entries in turn.
+static __global__ __launch_bounds__(kClWaves * kWave) void closure_apply_kernel(StepArgs a,
+                                                                              const int32_t* __restrict__ list,
+                                                                              const uint32_t* __restrict__ count) {
     __shared__ ClosureLds cl;
     closure_stage(a, cl);
-    const int tile = xcd_tile(blockIdx.x, a.nbx * a.nby, a.n_xcd);
-    step_wave<float, ST_PLAIN, MODEL, true>(a, tile % a.nbx, tile / a.nbx, a.t_dev[0] + a.k, &cl);
+    const int l = threadIdx.x % kWave;
+    const int n = (int)count[0];
+    const int waves = gridDim.x * kClWaves;
+    const float kforce = (float)(1.0 - 0.5 / a.tau);
+    const float* src = static_cast<const float*>(a.src);
+    float* dst = static_cast<float*>(a.dst);
+    for (int g = blockIdx.x * kClWaves + (int)(threadIdx.x / kWave); g * kWave < n; g += waves) {
+        const int e = g * kWave + l;
+        const bool on = e < n;
+        const int node = list[on ? e : g * kWave];
+        const int y = node / a.nx, x = node % a.nx;
+        // phi(t) on the 5x5 neighbourhood: sum_i f*_i(z - c_i, t - 1), i = 0..8 in order
+        float xin[25];
+        for (int dy = -2; dy <= 2; ++dy)
+            for (int dx = -2; dx <= 2; ++dx) {
+                const int zy = wrap_idx(y + dy, a.ny), zx = wrap_idx(x + dx, a.nx);
+                float s = 0.f;
+#pragma unroll
+                for (int q = 0; q < 9; ++q)
+                    s += src[q * a.plane_stride + (int64_t)wrap_idx(zy - cy(q), a.ny) * a.pitch +
+                             wrap_idx(zx - cx(q), a.nx)];
+                xin[(dy + 2) * 5 + (dx + 2)] = s;
+            }
+        float ccx, ccy;
+        closure_mlp(cl, xin, ccx, ccy);
+        if (on) {
+            const float phi = xin[12];
+            const int64_t off = (int64_t)y * a.pitch + x;
+            const float kx = kforce * ccx, ky = kforce * ccy;
+            float f[9];
+#pragma unroll
+            for (int q = 1; q < 9; ++q) f[q] = dst[q * a.plane_stride + off];
+            // w_i (c_i . (1 - 1/(2 tau)) c): the pairs i, opposite(i) change by exact negatives
+            const float ax = wq<float>(1) * kx, ay = wq<float>(1) * ky;
+            const float dx5 = wq<float>(5) * kx, dy5 = wq<float>(5) * ky;
+            f[1] += ax;
+            f[3] -= ax;
+            f[2] += ay;
+            f[4] -= ay;
+            f[5] += dx5 + dy5;
+            f[7] -= dx5 + dy5;
+            f[6] += dy5 - dx5;
+            f[8] -= dy5 - dx5;
+            float rest = phi;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) rest -= f[q];
+            dst[off] = rest;
+#pragma unroll
+            for (int q = 1; q < 9; ++q) dst[q * a.plane_stride + off] = f[q];
+        }
+    }
 }
 
 // ---------------------------------------------------------------------------
@@ -1038,6 +1215,31 @@ static __global__ void advance_kernel(int64_t* t_dev, int64_t n) {
 
 static __global__ void set_time_kernel(int64_t* t_dev, int64_t t) {
     if (threadIdx.x == 0 && blockIdx.x == 0) t_dev[0] = t;
+}
+
+// Copy of the stored state with the step kernel's tiling and access order
+// (256-column tiles, strips marched row by row, the XCD-aware tile order) but
+// none of its arithmetic: the HBM rate this access pattern reaches is a
+// practical ceiling for the step.  E: the stored element type; the optional
+// second plane set (src2/dst2) is the FP32 phi* plane of the shifted forms.
+template <typename E>
+static __global__ __launch_bounds__(256) void pattern_copy_kernel(StepArgs a, int nplanes) {
+    const int nbx = (a.nx + 255) / 256;
+    const int tile = xcd_tile(blockIdx.x, nbx * a.nby, a.n_xcd);
+    const int bxi = tile % nbx, syi = tile / nbx;
+    const int x = min(bxi * 256 + (int)threadIdx.x, a.nx - 1);
+    const int ys = syi * a.strip_h, ye = min(ys + a.strip_h, a.ny);
+    const E* src = static_cast<const E*>(a.src);
+    E* dst = static_cast<E*>(a.dst);
+    for (int y = ys; y < ye; ++y) {
+        const int64_t off = (int64_t)y * a.pitch + x;
+        E v[9];
+        float ph = 0.f;
+        for (int q = 0; q < nplanes; ++q) v[q] = src[q * a.plane_stride + off];
+        if (a.src_phi) ph = a.src_phi[off];
+        for (int q = 0; q < nplanes; ++q) dst[q * a.plane_stride + off] = v[q];
+        if (a.src_phi) a.dst_phi[off] = ph;
+    }
 }
 
 }  // namespace lbac

@@ -46,7 +46,7 @@ EXPORTS = [
     "lbac_default_params", "lbac_init", "lbac_init_device", "lbac_free", "lbac_step", "lbac_phi",
     "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
     "lbac_set_launch", "lbac_get_launch", "lbac_autotune", "lbac_set_graph_chunk", "lbac_bytes_per_node",
-    "lbac_set_closure",
+    "lbac_copy_ceiling", "lbac_set_closure",
     "lbac_stream", "lbac_strerror", "lbac_last_error",
     "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
     "lbac_batch_set_shape", "lbac_batch_get_shape", "lbac_batch_autotune", "lbac_batch_set_timeout",
@@ -90,6 +90,7 @@ def load():
     L.lbac_get_state.argtypes = [C.c_void_p, C.c_void_p, P(C.c_size_t)]
     L.lbac_set_state.argtypes = [C.c_void_p, C.c_void_p, C.c_size_t]
     L.lbac_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    L.lbac_copy_ceiling.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
     L.lbac_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.lbac_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac_set_graph_chunk.argtypes = [C.c_void_p, C.c_int32]
@@ -289,6 +290,12 @@ class Simulation:
         b = C.c_double()
         _check(load().lbac_bytes_per_node(self.h, C.byref(b)), self.h)
         return b.value
+
+    def copy_ceiling(self, launches=20):
+        """Mean microseconds of a plain copy of the state in the step's access pattern."""
+        us = C.c_double()
+        _check(load().lbac_copy_ceiling(self.h, int(launches), C.byref(us)), self.h)
+        return us.value
 
     def stream(self):
         return load().lbac_stream(self.h)

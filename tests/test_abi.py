@@ -80,7 +80,7 @@ def test_nonfinite_phi0_rejected():
 
 def test_bad_sizes_rejected():
     L = lbac.load()
-    for nx, ny in ((0, 16), (16, 0), (-3, 4), (70000, 4)):
+    for nx, ny in ((0, 16), (16, 0), (-3, 4), (70000, 4), (65536, 4096)):
         p = lbac.make_params(16, 16)
         p.nx, p.ny = nx, ny
         h = C.c_void_p()

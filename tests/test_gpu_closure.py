@@ -1,5 +1,6 @@
-"""The learned closure on the GPU: fused BF16 MFMA inference inside the step
-and the training-sample extraction, against the FP64 oracle."""
+"""The learned closure on the GPU: BF16 MFMA inference in the step (band
+list + correction pass) and the training-sample extraction, against the FP64
+oracle."""
 import sys
 
 import numpy as np
@@ -53,11 +54,11 @@ def test_zero_output_layer_is_the_plain_step(gpu_lib):
 
 
 @pytest.mark.parametrize("eps", [1.0, 0.5])
-def test_fused_closure_matches_oracle(gpu_lib, eps):
+def test_closure_matches_oracle(gpu_lib, eps):
     """The GPU rounds the network's inputs and hidden activations to BF16; the
     oracle evaluates the same BF16-rounded weights in FP64.  The difference
     must stay within 5% of what the closure changes."""
-    say("case: fused closure vs oracle, eps", eps)
+    say("case: closure vs oracle, eps", eps)
     n, steps, theta = 96, 120, 0.02
     case = W.single_vortex_case(n, eps=eps, U=0.04, period_T=400.0)
     phi0 = W.circle(n, eps)
@@ -126,3 +127,37 @@ def test_extraction_matches_oracle(gpu_lib):
             rot[:, dy + 2, dx + 2] = st[:, -dx + 2, dy + 2]
     assert np.array_equal(Xa[:, 1].reshape(n, 5, 5), rot)
     assert np.allclose(Ya[:, 1], np.stack([-Yg[:, 1], Yg[:, 0]], 1))
+
+
+def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib):
+    """The band list is built with atomics (its order varies), but every listed
+    node is corrected independently, so launch shapes, variants and graph
+    replay give identical results."""
+    say("case: closure launch shapes and graph replay")
+    n = 200
+    case = W.single_vortex_case(n, eps=1.0, U=0.04, period_T=400.0)
+    phi0 = W.circle(n, 1.0)
+    w = closure_params(5, 0.05)
+    base = None
+    for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8)):
+        sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+        sim.set_launch(*launch)
+        if graph:
+            sim.set_graph_chunk(graph)
+        sim.set_closure(w, theta=0.02)
+        sim.step(40)
+        phi = sim.phi()
+        sim.close()
+        if base is None:
+            base = phi
+        assert np.array_equal(phi, base), (launch, graph)
+
+
+def test_closure_rejected_for_batch_instances(gpu_lib):
+    say("case: closure on a batch instance")
+    case = W.single_vortex_case(64, eps=1.0)
+    b = gpu_lib.Batch([case], [W.circle(64, 1.0)])
+    with pytest.raises(gpu_lib.LbacError) as ei:
+        b.instance(0).set_closure(closure_params(3, 0.01), theta=0.02)
+    assert ei.value.code == gpu_lib.LBAC_EINVAL
+    b.close()

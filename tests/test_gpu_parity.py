@@ -155,7 +155,7 @@ def test_ragged_and_degenerate_grids(gpu_lib, nx, ny):
     rng = np.random.default_rng(nx * 1000 + ny)
     phi0 = W.circle(max(nx, ny), 1.5, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
     ref = O.run(oparams(case), phi0, 40)
-    for launch in ((64, 7, 0), (128, 64, 1), (256, 3, 0), (64, 5, 1)):
+    for launch in ((64, 7, 0), (128, 64, 1), (256, 3, 0), (64, 5, 1), (128, 6, 2), (256, 1, 2)):
         sim = gpu_run(gpu_lib, case, phi0, 40, "f64", launch=launch)
         assert_fp64_parity(sim.phi(), ref, 40, 1.0)
 
@@ -187,7 +187,8 @@ def test_launch_shape_does_not_change_results(gpu_lib, prec):
     case = W.single_vortex_case(320, U=0.05, period_T=100.0)
     phi0 = W.circle(320, 1.0)
     base = None
-    for launch in ((256, 64, 0), (64, 5, 0), (128, 320, 0), (256, 1, 1), (64, 17, 1), (128, 40, 1)):
+    for launch in ((256, 64, 0), (64, 5, 0), (128, 320, 0), (256, 1, 1), (64, 17, 1), (128, 40, 1), (256, 2, 2),
+                   (64, 9, 2), (128, 33, 2)):
         phi = gpu_run(gpu_lib, case, phi0, 12, prec, launch=launch).phi()
         if base is None:
             base = phi
@@ -262,6 +263,22 @@ def test_autotune_keeps_state(gpu_lib):
     assert us > 0
     a.step(5)
     b.step(5)
+    assert np.array_equal(a.phi(), b.phi())
+
+
+@pytest.mark.parametrize("prec", ["f32", "f32_f16store", "f64"])
+def test_copy_ceiling_keeps_state(gpu_lib, prec):
+    say("case: copy ceiling", prec)
+    case = W.single_vortex_case(300, U=0.05, period_T=100.0)
+    phi0 = W.circle(300, 1.0)
+    a = gpu_lib.Simulation({**case, "precision": prec}, phi0)
+    b = gpu_lib.Simulation({**case, "precision": prec}, phi0)
+    a.step(3)
+    b.step(3)
+    assert a.copy_ceiling(4) > 0
+    assert np.array_equal(a.phi(), b.phi())
+    a.step(4)
+    b.step(4)
     assert np.array_equal(a.phi(), b.phi())
 
 
