@@ -756,12 +756,13 @@ int lbac_copy_ceiling(lbac_ctx* h, int32_t launches, double* us_per_launch) {
         a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
         const dim3 grid(((a.nx + 255) / 256) * a.nby), block(256);
         auto launch = [&]() {
+            // plain storage: 9 planes; shifted storage: 8 16-bit planes plus the FP32 phi* plane
             if (h->elem_bytes == 8)
-                hipLaunchKernelGGL(pattern_copy_kernel<uint64_t>, grid, block, 0, h->stream, a, h->nplanes);
+                hipLaunchKernelGGL((pattern_copy_kernel<uint64_t, 9>), grid, block, 0, h->stream, a);
             else if (h->elem_bytes == 4)
-                hipLaunchKernelGGL(pattern_copy_kernel<uint32_t>, grid, block, 0, h->stream, a, h->nplanes);
+                hipLaunchKernelGGL((pattern_copy_kernel<uint32_t, 9>), grid, block, 0, h->stream, a);
             else
-                hipLaunchKernelGGL(pattern_copy_kernel<uint16_t>, grid, block, 0, h->stream, a, h->nplanes);
+                hipLaunchKernelGGL((pattern_copy_kernel<uint16_t, 8>), grid, block, 0, h->stream, a);
             return hipGetLastError();
         };
         e = launch();

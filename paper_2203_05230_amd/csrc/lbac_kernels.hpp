@@ -1220,10 +1220,10 @@ static __global__ void set_time_kernel(int64_t* t_dev, int64_t t) {
 // Copy of the stored state with the step kernel's tiling and access order
 // (256-column tiles, strips marched row by row, the XCD-aware tile order) but
 // none of its arithmetic: the HBM rate this access pattern reaches is a
-// practical ceiling for the step.  E: the stored element type; the optional
-// second plane set (src2/dst2) is the FP32 phi* plane of the shifted forms.
-template <typename E>
-static __global__ __launch_bounds__(256) void pattern_copy_kernel(StepArgs a, int nplanes) {
+// practical ceiling for the step.  E: the stored element type; NP: 9 planes
+// (plain storage), or 8 planes plus the FP32 phi* plane (shifted storage).
+template <typename E, int NP>
+static __global__ __launch_bounds__(256) void pattern_copy_kernel(StepArgs a) {
     const int nbx = (a.nx + 255) / 256;
     const int tile = xcd_tile(blockIdx.x, nbx * a.nby, a.n_xcd);
     const int bxi = tile % nbx, syi = tile / nbx;
@@ -1233,12 +1233,14 @@ static __global__ __launch_bounds__(256) void pattern_copy_kernel(StepArgs a, in
     E* dst = static_cast<E*>(a.dst);
     for (int y = ys; y < ye; ++y) {
         const int64_t off = (int64_t)y * a.pitch + x;
-        E v[9];
+        E v[NP];
         float ph = 0.f;
-        for (int q = 0; q < nplanes; ++q) v[q] = src[q * a.plane_stride + off];
-        if (a.src_phi) ph = a.src_phi[off];
-        for (int q = 0; q < nplanes; ++q) dst[q * a.plane_stride + off] = v[q];
-        if (a.src_phi) a.dst_phi[off] = ph;
+#pragma unroll
+        for (int q = 0; q < NP; ++q) v[q] = src[q * a.plane_stride + off];
+        if constexpr (NP == 8) ph = a.src_phi[off];
+#pragma unroll
+        for (int q = 0; q < NP; ++q) dst[q * a.plane_stride + off] = v[q];
+        if constexpr (NP == 8) a.dst_phi[off] = ph;
     }
 }
 

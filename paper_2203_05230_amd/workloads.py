@@ -83,6 +83,19 @@ def single_vortex_case(n, eps=1.0, tau=0.8, U=0.02, period_T=2000.0, delta=1e-10
     return dict(nx=n, ny=n, eps=eps, tau=tau, delta=delta, vel="vortex", U=U, period_T=float(period_T))
 
 
+def paper_vortex_case(eps_paper, L=200):
+    """The paper's own single-vortex test (Sec. 3, Eq. (14)): an L x L grid
+    (L = 200), disk R = 0.2 L at (0.5 L, 0.75 L), U0 = 0.04, mobility
+    M = 0.001 (tau = 3 M + 1/2 = 0.503), period T = 6 L / U0 = 30 000 steps,
+    the printed velocity signs and regulariser e^-20.  eps_paper is the
+    paper's interface width (3 and 1.5 in its figures); the library's width
+    convention has eps = eps_paper / 4."""
+    U0, M = 0.04, 0.001
+    T = 6.0 * L / U0
+    return dict(nx=L, ny=L, eps=eps_paper / 4.0, tau=3.0 * M + 0.5, delta=float(np.exp(-20.0)), vel="vortex_paper",
+                U=U0, period_T=T, steps=int(round(T)), phi0=("circle", dict(R_frac=0.2)))
+
+
 def zalesak_case(n, eps=1.0, tau=0.8, delta=1e-10, rev_steps=None):
     """Slotted disk under solid-body rotation about the grid centre, one
     revolution in rev_steps (default 64 n) steps."""

@@ -161,3 +161,23 @@ def test_closure_rejected_for_batch_instances(gpu_lib):
         b.instance(0).set_closure(closure_params(3, 0.01), theta=0.02)
     assert ei.value.code == gpu_lib.LBAC_EINVAL
     b.close()
+
+
+def test_trained_closure_reduces_shape_error(gpu_lib):
+    """The whole pipeline at the size of the closure experiment (coarse 128^2,
+    eps 0.5; 64 fine runs at 512^2; training on the GPU): on held-out runs the
+    coarse scheme with the trained closure returns closer to phi0 (E2 at
+    t = T) than the plain coarse scheme.  Deterministic: seeded inputs, seeded
+    minibatches, deterministic kernels."""
+    from paper_2203_05230_amd import closure as CL
+
+    say("case: closure training and held-out evaluation")
+    train = CL.coarse_cases(64, 1, n=128, eps=0.5)
+    X, Y = CL.generate(train, snapshots=16, theta=0.02, log=say)
+    w, hist, _ = CL.train(X, Y, steps=3000, batch=4096, lr=2e-3, seed=1, log=lambda m: None)
+    say("  loss %.3e -> %.3e" % (hist[0][1], hist[-1][1]))
+    assert hist[-1][1] < 0.1 * hist[0][1]
+    rows = CL.evaluate(w, CL.coarse_cases(4, 1001, n=128, eps=0.5), theta=0.02, log=say)
+    ratios = [r["closure"][1] / r["plain"][1] for r in rows]
+    say("  E2 closure / plain:", ["%.3f" % v for v in ratios])
+    assert max(ratios) < 1.0 and np.mean(ratios) < 0.97
