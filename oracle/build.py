@@ -1,4 +1,5 @@
-"""Builds liboracle.so from lbm_oracle.c with gcc (test infrastructure)."""
+"""Builds liboracle.so (lbm_oracle.c, D2Q9) and liboracle3.so (lbm_oracle3.c,
+D3Q19) with gcc (test infrastructure)."""
 import os
 import subprocess
 import sys
@@ -6,17 +7,24 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liboracle.so")
+SRC3 = os.path.join(HERE, "lbm_oracle3.c")
+LIB3 = os.path.join(HERE, "liboracle3.so")
+
+
+def _build_one(src, lib, force):
+    if not force and os.path.exists(lib) and os.path.getmtime(lib) >= os.path.getmtime(src):
+        return lib
+    tmp = lib + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
+           "-std=c11", "-Wall", "-o", tmp, src, "-lm"]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, lib)
+    return lib
 
 
 def build(force: bool = True) -> str:
-    if not force and os.path.exists(LIB) and os.path.getmtime(LIB) >= os.path.getmtime(SRC):
-        return LIB
-    tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["gcc", "-O2", "-fopenmp", "-fPIC", "-shared", "-ffp-contract=off",
-           "-std=c11", "-Wall", "-o", tmp, SRC, "-lm"]
-    subprocess.run(cmd, check=True)
-    os.replace(tmp, LIB)
-    return LIB
+    _build_one(SRC3, LIB3, force)
+    return _build_one(SRC, LIB, force)
 
 
 if __name__ == "__main__":

@@ -164,3 +164,28 @@ def closure_training_cases(count=64, seed=1, n=512, eps=2.0, tau=1.7):
             c["phi0"] = ("slotted_disk", geom)
         out.append(c)
     return out
+
+
+# ---- three dimensions (D3Q19 form) -------------------------------------------
+
+def sphere(nx, eps, R_frac=0.15, centre_frac=(0.35, 0.35, 0.35), ny=None, nz=None):
+    """Ball of radius R_frac*nx at centre_frac*(nx, ny, nz) on an nz-by-ny-by-nx
+    grid (cell centres), with the tanh profile of width eps; array (nz, ny, nx)."""
+    ny = nx if ny is None else ny
+    nz = nx if nz is None else nz
+    X = np.arange(nx, dtype=np.float64) + 0.5
+    Y = np.arange(ny, dtype=np.float64) + 0.5
+    Z = np.arange(nz, dtype=np.float64) + 0.5
+    r = np.sqrt((Z[:, None, None] - centre_frac[2] * nz) ** 2 + (Y[None, :, None] - centre_frac[1] * ny) ** 2 +
+                (X[None, None, :] - centre_frac[0] * nx) ** 2)
+    return smoothed_indicator(R_frac * nx - r, eps)
+
+
+def deformation_case(n, eps=1.0, tau=0.8, U=0.02, period_T=None, delta=1e-10):
+    """Sphere (R = 0.15 n at 0.35 n in each direction) in the three-dimensional
+    deformation field, amplitude U (|u| <= 2 U), reversed at t = T / 2 and back
+    at t = T; by default T = 3 n / U steps (three domain lengths at speed U,
+    the field's classic period)."""
+    T = float(3.0 * n / U) if period_T is None else float(period_T)
+    return dict(nx=n, ny=n, nz=n, eps=eps, tau=tau, delta=delta, vel="deformation", U=U, period_T=T,
+                steps=int(round(T)))
