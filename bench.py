@@ -178,6 +178,35 @@ def closure_leg(lbac, torch, case, phi0, steps, theta=0.02):
                 band_fraction=band / n, mac_per_band_node=5824, theta=theta)
 
 
+def leg_3d(lbac, torch, W, n, steps):
+    """The D3Q19 form on an n^3 ball in the deformation field (FP32 storage),
+    launch shape autotuned; timed on the library's stream."""
+    case = dict(nx=n, ny=n, nz=n, eps=1.0, tau=0.8, delta=1e-10, vel="deformation", U=0.02,
+                period_T=3.0 * n / 0.02, precision="f32")
+    phi0 = W.sphere(n, 1.0, R_frac=0.15)
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    sim = lbac.Simulation3(case, phi0, stream=stream.cuda_stream)
+    sim.autotune(4)
+    sim.step(4)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    sim.step(steps)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / steps
+    m = sim.mass()
+    bpn = sim.bytes_per_node()
+    strip = sim.get_strip()
+    sim.close()
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    nodes = n ** 3
+    return dict(grid=n, steps=steps, ms_per_step=round(ms, 4), mlups=round(nodes / (ms * 1e-3) / 1e6, 1),
+                bytes_per_node=bpn, hbm_gbs_algorithmic=round(bpn * nodes / (ms * 1e-3) / 1e9, 1),
+                mass_drift=abs(m - phi0.sum()) / phi0.sum(), strip_z=strip)
+
+
 def cpu_baseline(phi0, case, steps):
     """The FP64 oracle as it stands, on the host cores, for `steps` steps of the
     same grid (a bounded sample of the workload)."""
@@ -213,6 +242,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
+    ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
@@ -274,6 +304,10 @@ def main():
     if args.closure_steps > 0:
         print("bench: closure", file=sys.stderr, flush=True)
         closure = closure_leg(lbac, torch, case, phi0, args.closure_steps)
+    d3 = None
+    if args.grid3d > 0:
+        print("bench: 3-D form %d^3" % args.grid3d, file=sys.stderr, flush=True)
+        d3 = leg_3d(lbac, torch, W, args.grid3d, 200)
     cpu = None
     if args.cpu_steps > 0:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)
@@ -306,6 +340,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "closure": closure,
+        "d3q19": d3,
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

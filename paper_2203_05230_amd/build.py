@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "liblbac.so")
-SOURCES = [os.path.join(CSRC, f) for f in ("lbac.hip", "lbac_batch.hip", "lbac_mlp.hip", "lbac_closure.hip")]
+SOURCES = [os.path.join(CSRC, f) for f in ("lbac.hip", "lbac_batch.hip", "lbac_mlp.hip", "lbac_closure.hip", "lbac3.hip")]
 DEPS = SOURCES + [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith((".hpp", ".h"))] + \
     [os.path.join(ROOT, "include", "lbac.h")]
 

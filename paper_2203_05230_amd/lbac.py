@@ -42,6 +42,18 @@ class lbac_params(C.Structure):
     ]
 
 
+class lbac3_params(C.Structure):
+    _fields_ = [
+        ("nx", C.c_int32), ("ny", C.c_int32), ("nz", C.c_int32),
+        ("eps", C.c_double), ("tau", C.c_double), ("delta", C.c_double),
+        ("vel_kind", C.c_int32),
+        ("U", C.c_double), ("period_T", C.c_double),
+        ("ux", C.c_double), ("uy", C.c_double), ("uz", C.c_double),
+        ("precision", C.c_int32),
+        ("stream", C.c_void_p),
+    ]
+
+
 EXPORTS = [
     "lbac_default_params", "lbac_init", "lbac_init_device", "lbac_free", "lbac_step", "lbac_phi",
     "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
@@ -55,6 +67,13 @@ EXPORTS = [
     "lbac_mlp_loss_grad", "lbac_mlp_train_step", "lbac_mlp_last_error",
     "lbac_closure_workspace_bytes", "lbac_closure_extract",
 ]
+# include/lbac3.h (the D3Q19 form)
+EXPORTS3 = [
+    "lbac3_default_params", "lbac3_init", "lbac3_step", "lbac3_phi", "lbac3_mass", "lbac3_shape_error",
+    "lbac3_time", "lbac3_set_strip", "lbac3_get_strip", "lbac3_autotune", "lbac3_bytes_per_node",
+    "lbac3_last_error", "lbac3_free",
+]
+VEL3 = {"zero": 0, "deformation": 1, "vortex_xy": 2, "uniform": 3}
 MLP_NPARAM = 5954
 
 _lib = None
@@ -128,9 +147,26 @@ def load():
     L.lbac_closure_extract.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_float, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_int64, P(C.c_int64), C.c_void_p]
-    for name in EXPORTS:
+    p3 = P(lbac3_params)
+    L.lbac3_default_params.argtypes = [p3, C.c_int32, C.c_int32, C.c_int32]
+    L.lbac3_default_params.restype = None
+    L.lbac3_init.argtypes = [p3, dp, ctx_pp]
+    L.lbac3_step.argtypes = [C.c_void_p, C.c_int64]
+    L.lbac3_phi.argtypes = [C.c_void_p, dp]
+    L.lbac3_mass.argtypes = [C.c_void_p, dp]
+    L.lbac3_shape_error.argtypes = [C.c_void_p, dp, dp, dp]
+    L.lbac3_time.argtypes = [C.c_void_p, P(C.c_int64)]
+    L.lbac3_set_strip.argtypes = [C.c_void_p, C.c_int32]
+    L.lbac3_get_strip.argtypes = [C.c_void_p, P(C.c_int32)]
+    L.lbac3_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
+    L.lbac3_bytes_per_node.argtypes = [C.c_void_p, dp]
+    L.lbac3_last_error.argtypes = [C.c_void_p]
+    L.lbac3_last_error.restype = C.c_char_p
+    L.lbac3_free.argtypes = [C.c_void_p]
+    for name in EXPORTS + EXPORTS3:
         if name not in ("lbac_default_params", "lbac_stream", "lbac_strerror", "lbac_last_error",
-                        "lbac_batch_last_error", "lbac_mlp_last_error", "lbac_closure_workspace_bytes"):
+                        "lbac_batch_last_error", "lbac_mlp_last_error", "lbac_closure_workspace_bytes",
+                        "lbac3_default_params", "lbac3_last_error"):
             getattr(L, name).restype = C.c_int
     _lib = L
     return L
@@ -440,3 +476,92 @@ def closure_extract(phi_f_ptr, nxf, nyf, r, eps_f, eps_c, delta, theta, augment,
 
 def closure_workspace_bytes(nxf, nyf, r):
     return int(load().lbac_closure_workspace_bytes(int(nxf), int(nyf), int(r)))
+
+
+def make_params3(nx, ny, nz, eps=1.0, tau=0.8, delta=1e-10, vel="deformation", U=0.02, period_T=None, ux=0.0,
+                 uy=0.0, uz=0.0, precision="f32", stream=None, **_ignored):
+    p = lbac3_params()
+    load().lbac3_default_params(C.byref(p), int(nx), int(ny), int(nz))
+    p.eps, p.tau, p.delta = float(eps), float(tau), float(delta)
+    p.vel_kind = VEL3[vel] if isinstance(vel, str) else int(vel)
+    p.U = float(U)
+    if period_T is not None:
+        p.period_T = float(period_T)
+    p.ux, p.uy, p.uz = float(ux), float(uy), float(uz)
+    p.precision = PRECISION[precision] if isinstance(precision, str) else int(precision)
+    p.stream = stream
+    return p
+
+
+def _check3(rc, h=None, what=""):
+    if rc != LBAC_OK:
+        msg = load().lbac3_last_error(h).decode() if h else load().lbac3_last_error(None).decode()
+        raise LbacError(rc, msg or what)
+
+
+class Simulation3:
+    """One run of the D3Q19 form (include/lbac3.h).  `case` keys mirror
+    lbac3_params; phi arrays are (nz, ny, nx)."""
+
+    def __init__(self, case, phi0, stream=None):
+        L = load()
+        p = make_params3(**{**case, "stream": stream})
+        self.nx, self.ny, self.nz = p.nx, p.ny, p.nz
+        self.params = p
+        phi0 = np.ascontiguousarray(phi0, dtype=np.float64).reshape(p.nz, p.ny, p.nx)
+        h = C.c_void_p()
+        _check3(L.lbac3_init(C.byref(p), _dp(phi0), C.byref(h)), what="lbac3_init")
+        self.h = h
+
+    def close(self):
+        if getattr(self, "h", None):
+            load().lbac3_free(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, n):
+        _check3(load().lbac3_step(self.h, int(n)), self.h)
+
+    def phi(self):
+        out = np.empty((self.nz, self.ny, self.nx))
+        _check3(load().lbac3_phi(self.h, _dp(out)), self.h)
+        return out
+
+    def mass(self):
+        m = C.c_double()
+        _check3(load().lbac3_mass(self.h, C.byref(m)), self.h)
+        return m.value
+
+    def shape_error(self, ref):
+        ref = np.ascontiguousarray(ref, dtype=np.float64).reshape(self.nz, self.ny, self.nx)
+        e1, e2 = C.c_double(), C.c_double()
+        _check3(load().lbac3_shape_error(self.h, _dp(ref), C.byref(e1), C.byref(e2)), self.h)
+        return e1.value, e2.value
+
+    def time(self):
+        t = C.c_int64()
+        _check3(load().lbac3_time(self.h, C.byref(t)), self.h)
+        return t.value
+
+    def set_strip(self, strip_z):
+        _check3(load().lbac3_set_strip(self.h, int(strip_z)), self.h)
+
+    def get_strip(self):
+        v = C.c_int32()
+        _check3(load().lbac3_get_strip(self.h, C.byref(v)), self.h)
+        return v.value
+
+    def autotune(self, steps=8):
+        us = C.c_double()
+        _check3(load().lbac3_autotune(self.h, int(steps), C.byref(us)), self.h)
+        return us.value
+
+    def bytes_per_node(self):
+        b = C.c_double()
+        _check3(load().lbac3_bytes_per_node(self.h, C.byref(b)), self.h)
+        return b.value

@@ -19,7 +19,7 @@ def header_functions():
         if h.endswith(".h"):
             src = open(os.path.join(ROOT, "include", h)).read()
             src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lbac_\w+)\s*\(", src, flags=re.M))
+            names |= set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(lbac3?_\w+)\s*\(", src, flags=re.M))
     return sorted(names)
 
 
@@ -33,21 +33,23 @@ def test_library_exports_every_declared_symbol():
     L = lbac.load()
     for name in header_functions():
         assert hasattr(L, name), name
-    assert set(header_functions()) == set(lbac.EXPORTS)
+    assert set(header_functions()) == set(lbac.EXPORTS) | set(lbac.EXPORTS3)
 
 
-def test_params_struct_layout_matches_header(tmp_path):
-    """The ctypes mirror of lbac_params has the offsets the C compiler gives the header."""
-    fields = [name for name, _ in lbac.lbac_params._fields_]
+@pytest.mark.parametrize("struct,header", [("lbac_params", "lbac.h"), ("lbac3_params", "lbac3.h")])
+def test_params_struct_layout_matches_header(tmp_path, struct, header):
+    """The ctypes mirrors of lbac_params / lbac3_params have the offsets the C compiler gives the header."""
+    cls = getattr(lbac, struct)
+    fields = [name for name, _ in cls._fields_]
     src = tmp_path / "layout.c"
-    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbac.h"\nint main(void){\n'
-                   + "".join('printf("%%zu\\n", offsetof(lbac_params, %s));\n' % f for f in fields)
-                   + 'printf("%zu\\n", sizeof(lbac_params));return 0;}\n')
+    src.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "%s"\nint main(void){\n' % header
+                   + "".join('printf("%%zu\\n", offsetof(%s, %s));\n' % (struct, f) for f in fields)
+                   + 'printf("%%zu\\n", sizeof(%s));return 0;}\n' % struct)
     exe = tmp_path / "layout"
     import subprocess
     subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), "-o", str(exe), str(src)], check=True)
     got = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
-    want = [getattr(lbac.lbac_params, f).offset for f in fields] + [C.sizeof(lbac.lbac_params)]
+    want = [getattr(cls, f).offset for f in fields] + [C.sizeof(cls)]
     assert got == want
 
 
@@ -103,3 +105,28 @@ def test_status_strings():
     for code in (0, -1, -2, -3, -4, -5):
         assert L.lbac_strerror(code)
     assert L.lbac_strerror(0) == b"ok"
+
+
+@pytest.mark.parametrize("kw", [dict(tau=0.5), dict(eps=0.0), dict(delta=-1.0), dict(vel=9), dict(precision=2),
+                                dict(vel="deformation", period_T=0.0), dict(vel="uniform", ux=0.2, uy=0.1, uz=0.1),
+                                dict(vel="deformation", U=0.2)])
+def test_3d_invalid_parameters_rejected(kw):
+    L = lbac.load()
+    p = lbac.make_params3(8, 8, 8, **kw)
+    h = C.c_void_p()
+    phi0 = np.full(512, 0.5)
+    assert L.lbac3_init(C.byref(p), phi0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)) == lbac.LBAC_EINVAL
+    assert L.lbac3_last_error(None)
+
+
+def test_3d_bad_sizes_and_nulls_rejected():
+    L = lbac.load()
+    h = C.c_void_p()
+    phi0 = np.zeros(8)
+    for dims in ((0, 4, 4), (4, 4, 0), (5000, 2, 2), (1024, 1024, 256)):
+        p = lbac.make_params3(2, 2, 2)
+        p.nx, p.ny, p.nz = dims
+        assert L.lbac3_init(C.byref(p), phi0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)) == lbac.LBAC_EINVAL
+    assert L.lbac3_init(None, None, C.byref(h)) == lbac.LBAC_EINVAL
+    assert L.lbac3_step(None, 1) == lbac.LBAC_EINVAL
+    assert L.lbac3_free(None) == lbac.LBAC_EINVAL
