@@ -198,13 +198,13 @@ def leg_3d(lbac, torch, W, n, steps):
     ms = ev0.elapsed_time(ev1) / steps
     m = sim.mass()
     bpn = sim.bytes_per_node()
-    strip = sim.get_strip()
+    launch = sim.get_launch()
     sim.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     nodes = n ** 3
     return dict(grid=n, steps=steps, ms_per_step=round(ms, 4), mlups=round(nodes / (ms * 1e-3) / 1e6, 1),
                 bytes_per_node=bpn, hbm_gbs_algorithmic=round(bpn * nodes / (ms * 1e-3) / 1e9, 1),
-                mass_drift=abs(m - phi0.sum()) / phi0.sum(), strip_z=strip)
+                mass_drift=abs(m - phi0.sum()) / phi0.sum(), launch=list(launch))
 
 
 def cpu_baseline(phi0, case, steps):

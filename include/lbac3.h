@@ -80,14 +80,22 @@ int lbac3_shape_error(lbac3_ctx* h, const double* ref, double* e1, double* e2);
 /* Steps taken since lbac3_init. */
 int lbac3_time(lbac3_ctx* h, int64_t* t);
 
-/* Launch shape: every block takes a 32 x 16 tile of columns (30 x 14 of them
- * updated, tiles overlapping by one column on each side) and marches
- * strip_z >= 1 planes.  Results do not depend on it (bitwise). */
-int lbac3_set_strip(lbac3_ctx* h, int32_t strip_z);
-int lbac3_get_strip(lbac3_ctx* h, int32_t* strip_z);
+/* Launch shape: every block takes a tile of 32 x tile_y columns (tile_y = 8
+ * or 16; the tiles overlap by one column on each side, so 30 x (tile_y - 2)
+ * of them are updated) and marches strip_z >= 1 planes.  variant 0: the
+ * update keeps its node's 19 pulled values in registers; 1: it re-reads them
+ * (cache hits), issued with the next plane's loads; 2: the next plane's loads
+ * are in flight during the update.  Results do not depend on the shape or
+ * variant (bitwise).  LBAC_EINVAL for other values. */
+#define LBAC3_KEEP 0
+#define LBAC3_REPULL 1
+#define LBAC3_PREFETCH 2
+int lbac3_set_launch(lbac3_ctx* h, int32_t tile_y, int32_t variant, int32_t strip_z);
+int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_y, int32_t* variant, int32_t* strip_z);
 
-/* Times strip heights 4 .. 128 over `steps` steps each (state unchanged)
- * and keeps the fastest; *us_per_step (may be NULL) gets its time. */
+/* Times every launch shape (tile_y, variant, strip_z from 4 to 128) over
+ * `steps` steps each (state unchanged) and keeps the fastest; *us_per_step
+ * (may be NULL) gets its time. */
 int lbac3_autotune(lbac3_ctx* h, int32_t steps, double* us_per_step);
 
 /* HBM bytes one step moves by design: read and write of the 19 stored

@@ -43,9 +43,8 @@ __host__ __device__ constexpr R w3(int q) {
     return q == 0 ? R(1.0 / 3.0) : (q <= 6 ? R(1.0 / 18.0) : R(1.0 / 36.0));
 }
 
-constexpr int kTX = 32, kTY = 16;                 // threads per tile (x, y)
-constexpr int kIX = kTX - 2, kIY = kTY - 2;       // columns updated per tile
-constexpr int kThreads = kTX * kTY;
+constexpr int kTX = 32;          // threads per tile along x (tile heights TY = 8 or 16)
+constexpr int kIX = kTX - 2;     // columns updated per tile along x
 
 struct Args3 {
     const void* src;
@@ -70,8 +69,15 @@ struct Args3 {
 // there, and the interior threads update the plane behind it from the psi
 // ring in LDS (three planes).  Loads, LDS writes and stores carry no branch;
 // stores of threads without an updated node are dropped.
-template <typename R>
-__global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 2) void step3_kernel(Args3 a) {
+// MODE 0: the update keeps its node's 19 pulled values in registers from the
+// iteration that loaded them.  MODE 1: the update re-reads them (cache hits),
+// issued together with the new plane's loads; fewer registers.  MODE 2: the
+// next plane's loads are issued before the update, so they are in flight
+// while it runs; the loop body then carries no branch at all (the two
+// pipeline-fill iterations compute an update whose stores are dropped).
+template <typename R, int TY, int MODE>
+__global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
+    constexpr int kTY = TY, kIY = TY - 2;
     __shared__ R ring[3][kTY][kTX];
     const int ntile = a.nbx * a.nby * a.nbz;
     const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
@@ -97,14 +103,28 @@ __global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 2) void step3_kernel
     const R fxv = R(a.vtab[L + gx]), fyv = R(a.vtab[L + a.nx + gy]);
     const R fxw = R(a.vtab[2 * L + gx]), fyw = R(a.vtab[2 * L + a.nx + gy]);
 
-    const R* src = static_cast<const R*>(a.src);
     const R* pold_plane = static_cast<const R*>(a.phi_old);
     R* dst = static_cast<R*>(a.dst);
     const int64_t zs = (int64_t)a.pitch * a.ny;  // elements per z plane
-    // pull sources: column gx - c_x, row gy - c_y (wrapped once per thread)
-    const int64_t xcol[3] = {wrap_idx(gx + 1, a.nx), gx, wrap_idx(gx - 1, a.nx)};  // index c_x + 1
-    const int64_t yoff[3] = {(int64_t)wrap_idx(gy + 1, a.ny) * a.pitch, (int64_t)gy * a.pitch,
-                             (int64_t)wrap_idx(gy - 1, a.ny) * a.pitch};
+    // Pull sources: column gx - c_x, row gy - c_y (wrapped once per thread), as
+    // 32-bit byte offsets from uniform plane bases (a plane is below 2 GiB).
+    const char* sb = static_cast<const char*>(a.src);
+    const uint32_t pb = (uint32_t)(a.plane_stride * (int64_t)sizeof(R));  // bytes between planes (< 2^31)
+    const uint32_t xcol[3] = {(uint32_t)wrap_idx(gx + 1, a.nx) * (uint32_t)sizeof(R), (uint32_t)gx * (uint32_t)sizeof(R),
+                              (uint32_t)wrap_idx(gx - 1, a.nx) * (uint32_t)sizeof(R)};  // index c_x + 1
+    const uint32_t rowb = (uint32_t)a.pitch * (uint32_t)sizeof(R);
+    const uint32_t yoff[3] = {(uint32_t)wrap_idx(gy + 1, a.ny) * rowb, (uint32_t)gy * rowb,
+                              (uint32_t)wrap_idx(gy - 1, a.ny) * rowb};
+    const uint32_t zsb = (uint32_t)zs * (uint32_t)sizeof(R);
+    // f_i(x) = f*_i(x - c_i) for the node of this column on plane zp (Eq. (9) streaming)
+    auto pull = [&](int zp, R (&v)[19]) __attribute__((always_inline)) {
+        const uint32_t zoff[3] = {(uint32_t)wrap_idx(zp + 1, a.nz) * zsb, (uint32_t)zp * zsb,
+                                  (uint32_t)wrap_idx(zp - 1, a.nz) * zsb};  // plane zp - c_z, index c_z + 1
+#pragma unroll
+        for (int q = 0; q < 19; ++q)
+            v[q] = *reinterpret_cast<const R*>(sb + (size_t)q * pb + (zoff[cz3(q) + 1] + yoff[cy3(q) + 1] + xcol[cx3(q) + 1]));
+    };
+    auto pold_at = [&](int zp) { return pold_plane[(int64_t)zp * zs + (int64_t)gy * a.pitch + gx]; };
 
     R fprev[19];
     R phiprev = R(0), poldprev = R(0);
@@ -115,101 +135,125 @@ __global__ __launch_bounds__(kThreads, sizeof(R) == 4 ? 4 : 2) void step3_kernel
     const int txm = max(tx - 1, 0), txp = min(tx + 1, kTX - 1);
     const int tym = max(ty - 1, 0), typ = min(ty + 1, kTY - 1);
 
+    // update of node (gx, gy, zc) from the psi ring, its pulled values fp,
+    // phi and phi(t - 1); stores dropped unless st
+    auto update = [&](int it, int zc, bool st, const R (&fp)[19], R phi, R poldv) __attribute__((always_inline)) {
+        const int sm = (it + 1) % 3, s0 = (it + 2) % 3, sp = it % 3;  // planes zc - 1, zc, zc + 1
+        // grad psi = sum_i w_i c_i psi(x + c_i) / c_s^2: faces weigh 1/6, edges 1/12
+        const R gxv = fmaR(ring[s0][ty][txp] - ring[s0][ty][txm], R(1.0 / 6.0),
+                           (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][tym][txp] - ring[s0][typ][txm])) +
+                            ((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sm][ty][txp] - ring[sp][ty][txm]))) *
+                               R(1.0 / 12.0));
+        const R gyv = fmaR(ring[s0][typ][tx] - ring[s0][tym][tx], R(1.0 / 6.0),
+                           (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][typ][txm] - ring[s0][tym][txp])) +
+                            ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sm][typ][tx] - ring[sp][tym][tx]))) *
+                               R(1.0 / 12.0));
+        const R gzv = fmaR(ring[sp][ty][tx] - ring[sm][ty][tx], R(1.0 / 6.0),
+                           (((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sp][ty][txm] - ring[sm][ty][txp])) +
+                            ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sp][tym][tx] - ring[sm][typ][tx]))) *
+                               R(1.0 / 12.0));
+        const R inv = Math<R>::rcp(Math<R>::sqrt(fmaR(gxv, gxv, fmaR(gyv, gyv, gzv * gzv))) + delta);
+        const R pcl = clip01(phi);
+        const R S = (pcl + delta) * (R(1) - pcl + delta) * s_scale;
+        const R fz = R(lbac::row_factor(a.vtab, a.nx + a.ny + zc));
+        const R fzv = R(lbac::row_factor(a.vtab, L + a.nx + a.ny + zc));
+        const R fzw = R(lbac::row_factor(a.vtab, 2 * L + a.nx + a.ny + zc));
+        const R ur = fxu * fyu * fz, vr = fxv * fyv * fzv, wr = fxw * fyw * fzw;
+        const R u = s_now * ur, v = s_now * vr, w = s_now * wr;
+        const R phio = first ? phi : poldv;
+        // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
+        const R Sn = R(1.0 / 3.0) * S * inv;
+        const R Gx = fmaR(Sn, gxv, fmaR(phi, u, -(phio * (s_old * ur))));
+        const R Gy = fmaR(Sn, gyv, fmaR(phi, v, -(phio * (s_old * vr))));
+        const R Gz = fmaR(Sn, gzv, fmaR(phi, w, -(phio * (s_old * wr))));
+        // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)];
+        // the rest population as the remainder keeps sum_i f*_i = phi exactly
+        const R A0 = omega * phi;
+        const R bx = R(3) * fmaR(A0, u, kforce * Gx);
+        const R by = R(3) * fmaR(A0, v, kforce * Gy);
+        const R bz = R(3) * fmaR(A0, w, kforce * Gz);
+        R out[19];
+        const R af = w3<R>(1) * A0, ae = w3<R>(7) * A0;
+        const R xf = w3<R>(1) * bx, yf = w3<R>(1) * by, zf = w3<R>(1) * bz;
+        const R xe = w3<R>(7) * bx, ye = w3<R>(7) * by, ze = w3<R>(7) * bz;
+        out[1] = fmaR(keep, fp[1], af + xf);
+        out[2] = fmaR(keep, fp[2], af - xf);
+        out[3] = fmaR(keep, fp[3], af + yf);
+        out[4] = fmaR(keep, fp[4], af - yf);
+        out[5] = fmaR(keep, fp[5], af + zf);
+        out[6] = fmaR(keep, fp[6], af - zf);
+        out[7] = fmaR(keep, fp[7], (ae + xe) + ye);
+        out[8] = fmaR(keep, fp[8], (ae - xe) - ye);
+        out[9] = fmaR(keep, fp[9], (ae + xe) - ye);
+        out[10] = fmaR(keep, fp[10], (ae - xe) + ye);
+        out[11] = fmaR(keep, fp[11], (ae + xe) + ze);
+        out[12] = fmaR(keep, fp[12], (ae - xe) - ze);
+        out[13] = fmaR(keep, fp[13], (ae + xe) - ze);
+        out[14] = fmaR(keep, fp[14], (ae - xe) + ze);
+        out[15] = fmaR(keep, fp[15], (ae + ye) + ze);
+        out[16] = fmaR(keep, fp[16], (ae - ye) - ze);
+        out[17] = fmaR(keep, fp[17], (ae + ye) - ze);
+        out[18] = fmaR(keep, fp[18], (ae - ye) + ze);
+        R rest = phi;
+#pragma unroll
+        for (int q = 1; q < 19; ++q) rest -= out[q];
+        out[0] = rest;
+        // threads without an updated node store nothing (dropped offsets)
+        const uint32_t node = (uint32_t)((int64_t)zc * zs + (int64_t)gy * a.pitch + gx);
+        const uint32_t b = st ? node * (uint32_t)sizeof(R) : kDropOffset;
+#pragma unroll
+        for (int q = 0; q < 19; ++q) bstore(out[q], plane_rsrc(dst + (size_t)q * a.plane_stride), b);
+        bstore(phi, plane_rsrc(a.phi_new), b);
+    };
+
     lds_barrier();
     const int iters = hz + 2;
+    R fn[19];
+    R pn = R(0);
+    if constexpr (MODE == 2) {
+        pull(wrap_idx(z0 - 1, a.nz), fn);
+        pn = pold_at(wrap_idx(z0 - 1, a.nz));
+    }
     for (int it = 0; it < iters; ++it) {
         const int zr = wrap_idx(z0 - 1 + it, a.nz);  // the plane entering
-        // ---- pull (Eq. (9) streaming), phi (Eq. (12)), psi (Eq. (13)) on plane zr
-        const int64_t zoff[3] = {(int64_t)wrap_idx(zr + 1, a.nz) * zs, (int64_t)zr * zs,
-                                 (int64_t)wrap_idx(zr - 1, a.nz) * zs};  // plane zr - c_z, index c_z + 1
+        const int zc = wrap_idx(zr - 1, a.nz);       // the plane updated (from the third iteration on)
+        // ---- pull, phi (Eq. (12)) and psi (Eq. (13)) on plane zr
         R f[19];
+        R pold;
+        if constexpr (MODE == 2) {
+#pragma unroll
+            for (int q = 0; q < 19; ++q) f[q] = fn[q];
+            pold = pn;
+        } else {
+            pull(zr, f);
+            pold = pold_at(zr);
+        }
         R s = R(0);
 #pragma unroll
-        for (int q = 0; q < 19; ++q) {
-            f[q] = src[q * a.plane_stride + zoff[cz3(q) + 1] + yoff[cy3(q) + 1] + xcol[cx3(q) + 1]];
-            s += f[q];
-        }
-        const R pold = pold_plane[(int64_t)zr * zs + (int64_t)gy * a.pitch + gx];
+        for (int q = 0; q < 19; ++q) s += f[q];
         const R pc = clip01(s);
         ring[it % 3][ty][tx] = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
+        if constexpr (MODE == 1) pull(zc, fprev);  // the update's own pulled values, before the barrier
+        if constexpr (MODE == 2) {
+            // the next plane (past the strip: the last plane again, not used)
+            const int zn = wrap_idx(z0 - 1 + min(it + 1, iters - 1), a.nz);
+            pull(zn, fn);
+            pn = pold_at(zn);
+        }
         lds_barrier();
-
-        // ---- update the plane behind (zc = zr - 1); the first two iterations
-        // fill the pipeline.  (Each iteration consumes its own loads at once, so
-        // a branch around the stores costs no load overlap here.)
-        const int zc = wrap_idx(zr - 1, a.nz);
-        if (it >= 2) {
-            const int sm = (it + 1) % 3, s0 = (it + 2) % 3, sp = it % 3;  // planes zc - 1, zc, zc + 1
-            // grad psi = sum_i w_i c_i psi(x + c_i) / c_s^2: faces weigh 1/6, edges 1/12
-            const R gxv = fmaR(ring[s0][ty][txp] - ring[s0][ty][txm], R(1.0 / 6.0),
-                               (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][tym][txp] - ring[s0][typ][txm])) +
-                                ((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sm][ty][txp] - ring[sp][ty][txm]))) *
-                                   R(1.0 / 12.0));
-            const R gyv = fmaR(ring[s0][typ][tx] - ring[s0][tym][tx], R(1.0 / 6.0),
-                               (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][typ][txm] - ring[s0][tym][txp])) +
-                                ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sm][typ][tx] - ring[sp][tym][tx]))) *
-                                   R(1.0 / 12.0));
-            const R gzv = fmaR(ring[sp][ty][tx] - ring[sm][ty][tx], R(1.0 / 6.0),
-                               (((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sp][ty][txm] - ring[sm][ty][txp])) +
-                                ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sp][tym][tx] - ring[sm][typ][tx]))) *
-                                   R(1.0 / 12.0));
-            const R inv = Math<R>::rcp(Math<R>::sqrt(fmaR(gxv, gxv, fmaR(gyv, gyv, gzv * gzv))) + delta);
-            const R phi = phiprev;
-            const R pcl = clip01(phi);
-            const R S = (pcl + delta) * (R(1) - pcl + delta) * s_scale;
-            const R fz = R(lbac::row_factor(a.vtab, a.nx + a.ny + zc));
-            const R fzv = R(lbac::row_factor(a.vtab, L + a.nx + a.ny + zc));
-            const R fzw = R(lbac::row_factor(a.vtab, 2 * L + a.nx + a.ny + zc));
-            const R ur = fxu * fyu * fz, vr = fxv * fyv * fzv, wr = fxw * fyw * fzw;
-            const R u = s_now * ur, v = s_now * vr, w = s_now * wr;
-            const R phio = first ? phi : poldprev;
-            // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
-            const R Sn = R(1.0 / 3.0) * S * inv;
-            const R Gx = fmaR(Sn, gxv, fmaR(phi, u, -(phio * (s_old * ur))));
-            const R Gy = fmaR(Sn, gyv, fmaR(phi, v, -(phio * (s_old * vr))));
-            const R Gz = fmaR(Sn, gzv, fmaR(phi, w, -(phio * (s_old * wr))));
-            // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)];
-            // the rest population as the remainder keeps sum_i f*_i = phi exactly
-            const R A0 = omega * phi;
-            const R bx = R(3) * fmaR(A0, u, kforce * Gx);
-            const R by = R(3) * fmaR(A0, v, kforce * Gy);
-            const R bz = R(3) * fmaR(A0, w, kforce * Gz);
-            R out[19];
-            const R af = w3<R>(1) * A0, ae = w3<R>(7) * A0;
-            const R xf = w3<R>(1) * bx, yf = w3<R>(1) * by, zf = w3<R>(1) * bz;
-            const R xe = w3<R>(7) * bx, ye = w3<R>(7) * by, ze = w3<R>(7) * bz;
-            out[1] = fmaR(keep, fprev[1], af + xf);
-            out[2] = fmaR(keep, fprev[2], af - xf);
-            out[3] = fmaR(keep, fprev[3], af + yf);
-            out[4] = fmaR(keep, fprev[4], af - yf);
-            out[5] = fmaR(keep, fprev[5], af + zf);
-            out[6] = fmaR(keep, fprev[6], af - zf);
-            out[7] = fmaR(keep, fprev[7], (ae + xe) + ye);
-            out[8] = fmaR(keep, fprev[8], (ae - xe) - ye);
-            out[9] = fmaR(keep, fprev[9], (ae + xe) - ye);
-            out[10] = fmaR(keep, fprev[10], (ae - xe) + ye);
-            out[11] = fmaR(keep, fprev[11], (ae + xe) + ze);
-            out[12] = fmaR(keep, fprev[12], (ae - xe) - ze);
-            out[13] = fmaR(keep, fprev[13], (ae + xe) - ze);
-            out[14] = fmaR(keep, fprev[14], (ae - xe) + ze);
-            out[15] = fmaR(keep, fprev[15], (ae + ye) + ze);
-            out[16] = fmaR(keep, fprev[16], (ae - ye) - ze);
-            out[17] = fmaR(keep, fprev[17], (ae + ye) - ze);
-            out[18] = fmaR(keep, fprev[18], (ae - ye) + ze);
-            R rest = phi;
-#pragma unroll
-            for (int q = 1; q < 19; ++q) rest -= out[q];
-            out[0] = rest;
-            // threads without an updated node store nothing (dropped offsets)
-            const uint32_t node = (uint32_t)((int64_t)zc * zs + (int64_t)gy * a.pitch + gx);
-            const uint32_t b = inter ? node * (uint32_t)sizeof(R) : kDropOffset;
-#pragma unroll
-            for (int q = 0; q < 19; ++q) bstore(out[q], plane_rsrc(dst + (size_t)q * a.plane_stride), b);
-            bstore(phi, plane_rsrc(a.phi_new), b);
+        // ---- update the plane behind (zc = zr - 1); the first two iterations fill the pipeline
+        if constexpr (MODE == 2) {
+            update(it, zc, inter && it >= 2, fprev, phiprev, poldprev);
+        } else {
+            // (each iteration consumes its own loads at once, so a branch around
+            // the stores costs no load overlap here)
+            if (it >= 2) update(it, zc, inter, fprev, phiprev, poldprev);
         }
         lds_barrier();  // the ring slot written next iteration was read above
+        if constexpr (MODE != 1) {
 #pragma unroll
-        for (int q = 0; q < 19; ++q) fprev[q] = f[q];
+            for (int q = 0; q < 19; ++q) fprev[q] = f[q];
+        }
         phiprev = s;
         poldprev = pold;
     }
@@ -275,12 +319,15 @@ __global__ __launch_bounds__(lbac::kRedThreads) void sum5_kernel(const double* _
     }
 }
 
+// One wavefront: lane l adds parts l, l + 64, ... in order, then a fixed
+// tree across the lanes.
 __global__ void sum_parts_kernel(const double* __restrict__ part, int nparts, double* __restrict__ out5) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    const int l = threadIdx.x;
     for (int c = 0; c < 5; ++c) {
         double s = 0.0;
-        for (int i = 0; i < nparts; ++i) s += part[5 * (int64_t)i + c];
-        out5[c] = s;
+        for (int i = l; i < nparts; i += 64) s += part[5 * (int64_t)i + c];
+        for (int off = 32; off > 0; off >>= 1) s += __shfl_down(s, off, 64);
+        if (l == 0) out5[c] = s;
     }
 }
 
@@ -314,6 +361,8 @@ struct lbac3_ctx {
     int cur = 0;
     int64_t t = 0;
     int strip_z = 32;
+    int tile_y = 16;     // tile height (8 or 16 rows of 32 columns)
+    int mode = 0;        // 0 keep, 1 re-pull, 2 prefetch (see step3_kernel)
     std::string err;
 };
 
@@ -429,7 +478,7 @@ lbac3::Args3 make_args3(const lbac3_ctx* h, int src, int32_t k) {
     a.nz = h->p.nz;
     a.strip_z = std::min(h->strip_z, h->p.nz);
     a.nbx = (h->p.nx + lbac3::kIX - 1) / lbac3::kIX;
-    a.nby = (h->p.ny + lbac3::kIY - 1) / lbac3::kIY;
+    a.nby = (h->p.ny + (h->tile_y - 2) - 1) / (h->tile_y - 2);
     a.nbz = (h->p.nz + a.strip_z - 1) / a.strip_z;
     a.n_xcd = 8;
     a.vtab = h->vtab;
@@ -443,13 +492,32 @@ lbac3::Args3 make_args3(const lbac3_ctx* h, int src, int32_t k) {
     return a;
 }
 
+template <typename R, int TY>
+void launch3_ty(const lbac3_ctx* h, const lbac3::Args3& a, dim3 grid) {
+    const dim3 block(lbac3::kTX * TY);
+    if (h->mode == 1)
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 1>), grid, block, 0, h->stream, a);
+    else if (h->mode == 2)
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 2>), grid, block, 0, h->stream, a);
+    else
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 0>), grid, block, 0, h->stream, a);
+}
+
+template <typename R>
+void launch3_t(const lbac3_ctx* h, const lbac3::Args3& a, dim3 grid) {
+    if (h->tile_y == 8)
+        launch3_ty<R, 8>(h, a, grid);
+    else
+        launch3_ty<R, 16>(h, a, grid);
+}
+
 hipError_t launch_step3(const lbac3_ctx* h, int src, int32_t k) {
     const lbac3::Args3 a = make_args3(h, src, k);
-    const dim3 grid(a.nbx * a.nby * a.nbz), block(lbac3::kThreads);
+    const dim3 grid(a.nbx * a.nby * a.nbz);
     if (h->p.precision == LBAC_F64)
-        hipLaunchKernelGGL(lbac3::step3_kernel<double>, grid, block, 0, h->stream, a);
+        launch3_t<double>(h, a, grid);
     else
-        hipLaunchKernelGGL(lbac3::step3_kernel<float>, grid, block, 0, h->stream, a);
+        launch3_t<float>(h, a, grid);
     return hipGetLastError();
 }
 
@@ -646,16 +714,22 @@ int lbac3_time(lbac3_ctx* h, int64_t* t) {
     return LBAC_OK;
 }
 
-int lbac3_set_strip(lbac3_ctx* h, int32_t strip_z) {
+int lbac3_set_launch(lbac3_ctx* h, int32_t tile_y, int32_t variant, int32_t strip_z) {
     if (!h) return LBAC_EINVAL;
+    if (tile_y != 8 && tile_y != 16) return fail3(h, LBAC_EINVAL, "tile_y must be 8 or 16");
+    if (variant < 0 || variant > 2) return fail3(h, LBAC_EINVAL, "variant must be 0, 1 or 2");
     if (strip_z < 1) return fail3(h, LBAC_EINVAL, "strip_z must be >= 1");
+    h->tile_y = tile_y;
+    h->mode = variant;
     h->strip_z = std::min(strip_z, h->p.nz);
     return LBAC_OK;
 }
 
-int lbac3_get_strip(lbac3_ctx* h, int32_t* strip_z) {
-    if (!h || !strip_z) return LBAC_EINVAL;
-    *strip_z = h->strip_z;
+int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_y, int32_t* variant, int32_t* strip_z) {
+    if (!h) return LBAC_EINVAL;
+    if (tile_y) *tile_y = h->tile_y;
+    if (variant) *variant = h->mode;
+    if (strip_z) *strip_z = h->strip_z;
     return LBAC_OK;
 }
 
@@ -665,30 +739,38 @@ int lbac3_autotune(lbac3_ctx* h, int32_t steps, double* us_per_step) {
     hipEvent_t e0, e1;
     HIP3(h, hipEventCreate(&e0));
     HIP3(h, hipEventCreate(&e1));
-    const int keep = h->strip_z;
-    int best_s = keep;
+    const int keep = h->strip_z, keep_ty = h->tile_y, keep_rp = h->mode;
+    int best_s = keep, best_ty = keep_ty, best_rp = keep_rp;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    for (int sz : {4, 8, 16, 32, 64, 128}) {
-        if (sz > h->p.nz && sz != 4) continue;
-        h->strip_z = std::min(sz, h->p.nz);
-        // repeated step from pop[cur] into the other buffer: the state is untouched
-        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step3(h, h->cur, 0);
-        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-        for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step3(h, h->cur, 0);
-        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        float ms = 0.f;
-        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-        if (e != hipSuccess) break;
-        if (ms < best) {
-            best = ms;
-            best_s = h->strip_z;
-        }
-    }
+    for (int ty : {8, 16})
+        for (int rp = 0; rp < 3; ++rp)
+            for (int sz : {4, 8, 16, 32, 64, 128}) {
+                if (sz > h->p.nz && sz != 4) continue;
+                h->tile_y = ty;
+                h->mode = rp;
+                h->strip_z = std::min(sz, h->p.nz);
+                // repeated step from pop[cur] into the other buffer: the state is untouched
+                for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step3(h, h->cur, 0);
+                if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+                for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step3(h, h->cur, 0);
+                if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float ms = 0.f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+                if (e != hipSuccess) break;
+                if (ms < best) {
+                    best = ms;
+                    best_s = h->strip_z;
+                    best_ty = ty;
+                    best_rp = rp;
+                }
+            }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->strip_z = e == hipSuccess ? best_s : keep;
+    h->tile_y = e == hipSuccess ? best_ty : keep_ty;
+    h->mode = e == hipSuccess ? best_rp : keep_rp;
     if (e != hipSuccess) return fail3(h, LBAC_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
     if (us_per_step) *us_per_step = 1000.0 * best / steps;
     return LBAC_OK;

@@ -70,7 +70,7 @@ EXPORTS = [
 # include/lbac3.h (the D3Q19 form)
 EXPORTS3 = [
     "lbac3_default_params", "lbac3_init", "lbac3_step", "lbac3_phi", "lbac3_mass", "lbac3_shape_error",
-    "lbac3_time", "lbac3_set_strip", "lbac3_get_strip", "lbac3_autotune", "lbac3_bytes_per_node",
+    "lbac3_time", "lbac3_set_launch", "lbac3_get_launch", "lbac3_autotune", "lbac3_bytes_per_node",
     "lbac3_last_error", "lbac3_free",
 ]
 VEL3 = {"zero": 0, "deformation": 1, "vortex_xy": 2, "uniform": 3}
@@ -156,8 +156,8 @@ def load():
     L.lbac3_mass.argtypes = [C.c_void_p, dp]
     L.lbac3_shape_error.argtypes = [C.c_void_p, dp, dp, dp]
     L.lbac3_time.argtypes = [C.c_void_p, P(C.c_int64)]
-    L.lbac3_set_strip.argtypes = [C.c_void_p, C.c_int32]
-    L.lbac3_get_strip.argtypes = [C.c_void_p, P(C.c_int32)]
+    L.lbac3_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
+    L.lbac3_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.lbac3_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac3_bytes_per_node.argtypes = [C.c_void_p, dp]
     L.lbac3_last_error.argtypes = [C.c_void_p]
@@ -548,13 +548,13 @@ class Simulation3:
         _check3(load().lbac3_time(self.h, C.byref(t)), self.h)
         return t.value
 
-    def set_strip(self, strip_z):
-        _check3(load().lbac3_set_strip(self.h, int(strip_z)), self.h)
+    def set_launch(self, tile_y, variant, strip_z):
+        _check3(load().lbac3_set_launch(self.h, int(tile_y), int(variant), int(strip_z)), self.h)
 
-    def get_strip(self):
-        v = C.c_int32()
-        _check3(load().lbac3_get_strip(self.h, C.byref(v)), self.h)
-        return v.value
+    def get_launch(self):
+        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
+        _check3(load().lbac3_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)), self.h)
+        return a.value, b.value, c.value
 
     def autotune(self, steps=8):
         us = C.c_double()

@@ -38,10 +38,10 @@ def assert_fp64(phi, ref, steps, eps, delta):
     assert np.max(np.abs(phi - ref)) <= steps * delta / eps
 
 
-def gpu(lb, case, phi0, steps, precision, strip=None):
+def gpu(lb, case, phi0, steps, precision, launch=None):
     sim = lb.Simulation3({**case, "precision": precision}, phi0)
-    if strip:
-        sim.set_strip(strip)
+    if launch:
+        sim.set_launch(*launch)
     sim.step(steps)
     return sim
 
@@ -73,12 +73,12 @@ def test_fp64_ragged_grids_and_strips(gpu_lib, dims):
         + 0.05 * rng.random((nz, ny, nx))
     ref = O3.run(oparams(c), phi0, 40)
     base = None
-    for strip in (1, 5, 32):
-        phi = gpu(gpu_lib, c, phi0, 40, "f64", strip=strip).phi()
+    for launch in ((16, 0, 1), (8, 1, 5), (16, 1, 32), (8, 0, 3), (16, 2, 2), (8, 2, 36)):
+        phi = gpu(gpu_lib, c, phi0, 40, "f64", launch=launch).phi()
         assert_fp64(phi, ref, 40, 1.2, 1e-10)
         if base is None:
             base = phi
-        assert np.array_equal(phi, base), strip
+        assert np.array_equal(phi, base), launch
 
 
 def test_fp32_parity_after_300_steps(gpu_lib):
@@ -110,6 +110,19 @@ def test_z_invariant_data_match_the_2d_form(gpu_lib):
         m = np.abs(ref) > 1e-8
         assert rel_l2(phi3[k][m], ref[m]) <= 1e-12
         assert np.max(np.abs(phi3[k] - ref)) <= 200 * 1e-10
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_launch_shapes_bitwise(gpu_lib, prec):
+    say("case: 3-D launch shapes", prec)
+    c = deformation(40)
+    phi0 = W.sphere(40, 1.0, R_frac=0.2)
+    base = None
+    for launch in ((16, 0, 32), (8, 0, 7), (16, 1, 4), (8, 1, 40), (16, 2, 16), (8, 2, 5)):
+        phi = gpu(gpu_lib, c, phi0, 12, prec, launch=launch).phi()
+        if base is None:
+            base = phi
+        assert np.array_equal(phi, base), launch
 
 
 def test_autotune_keeps_state(gpu_lib):
