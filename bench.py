@@ -178,16 +178,19 @@ def closure_leg(lbac, torch, case, phi0, steps, theta=0.02):
                 band_fraction=band / n, mac_per_band_node=5824, theta=theta)
 
 
-def leg_3d(lbac, torch, W, n, steps):
+def leg_3d(lbac, torch, W, n, steps, launch=None):
     """The D3Q19 form on an n^3 ball in the deformation field (FP32 storage),
-    launch shape autotuned; timed on the library's stream."""
+    launch shape autotuned (or given); timed on the library's stream."""
     case = dict(nx=n, ny=n, nz=n, eps=1.0, tau=0.8, delta=1e-10, vel="deformation", U=0.02,
                 period_T=3.0 * n / 0.02, precision="f32")
     phi0 = W.sphere(n, 1.0, R_frac=0.15)
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     sim = lbac.Simulation3(case, phi0, stream=stream.cuda_stream)
-    sim.autotune(4)
+    if launch:
+        sim.set_launch(*launch)
+    else:
+        sim.autotune(4)
     sim.step(4)
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
@@ -244,6 +247,8 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
+    ap.add_argument("--steps3d", type=int, default=200, help="timed steps of the D3Q19 leg")
+    ap.add_argument("--launch3d", default="", help="tile_x,tile_y,variant,strip_z,z_major of the D3Q19 leg (default: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
                          "scaling HBM byte counters) and exit")
@@ -307,7 +312,8 @@ def main():
     d3 = None
     if args.grid3d > 0:
         print("bench: 3-D form %d^3" % args.grid3d, file=sys.stderr, flush=True)
-        d3 = leg_3d(lbac, torch, W, args.grid3d, 200)
+        launch3d = tuple(int(v) for v in args.launch3d.split(",")) if args.launch3d else None
+        d3 = leg_3d(lbac, torch, W, args.grid3d, args.steps3d, launch=launch3d)
     cpu = None
     if args.cpu_steps > 0:
         print("bench: cpu baseline (%d oracle steps)" % args.cpu_steps, file=sys.stderr, flush=True)

@@ -80,20 +80,28 @@ int lbac3_shape_error(lbac3_ctx* h, const double* ref, double* e1, double* e2);
 /* Steps taken since lbac3_init. */
 int lbac3_time(lbac3_ctx* h, int64_t* t);
 
-/* Launch shape: every block takes a tile of 32 x tile_y columns (tile_y = 8
- * or 16; the tiles overlap by one column on each side, so 30 x (tile_y - 2)
- * of them are updated) and marches strip_z >= 1 planes.  variant 0: the
- * update keeps its node's 19 pulled values in registers; 1: it re-reads them
- * (cache hits), issued with the next plane's loads; 2: the next plane's loads
- * are in flight during the update.  Results do not depend on the shape or
- * variant (bitwise).  LBAC_EINVAL for other values. */
+/* Launch shape.  Every block updates a tile of tile_x x tile_y columns, one
+ * thread per column, and marches strip_z >= 1 planes; the one-column rim
+ * around the tile is pulled again by the block for its psi.  Tile shapes:
+ * 32 x 8, 32 x 16, 64 x 4, 64 x 8, 128 x 4, and with LBAC_F32 also 32 x 32,
+ * 64 x 16, 128 x 8.  variant LBAC3_KEEP (0): the update keeps its node's 19
+ * pulled values in registers; LBAC3_REPULL (1): it re-reads them (cache
+ * hits), issued with the next plane's loads; LBAC3_PREFETCH (2): the next
+ * plane's loads are in flight during the update.  z_major 0: blocks take the
+ * tiles with x fastest, then y, then the strip; 1: the strip index fastest.
+ * Even strips march up and odd strips down, so two neighbouring strips read
+ * the planes they share at the same time.  Results do not depend on the
+ * launch shape (bitwise).  LBAC_EINVAL for other values. */
 #define LBAC3_KEEP 0
 #define LBAC3_REPULL 1
 #define LBAC3_PREFETCH 2
-int lbac3_set_launch(lbac3_ctx* h, int32_t tile_y, int32_t variant, int32_t strip_z);
-int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_y, int32_t* variant, int32_t* strip_z);
+int lbac3_set_launch(lbac3_ctx* h, int32_t tile_x, int32_t tile_y, int32_t variant, int32_t strip_z,
+                     int32_t z_major);
+int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_x, int32_t* tile_y, int32_t* variant, int32_t* strip_z,
+                     int32_t* z_major);
 
-/* Times every launch shape (tile_y, variant, strip_z from 4 to 128) over
+/* Times every launch shape (tile, variant, strip_z among the powers of two
+ * from 4 to 128 and ceil(nz / k) for k = 1..16, z_major) over
  * `steps` steps each (state unchanged) and keeps the fastest; *us_per_step
  * (may be NULL) gets its time. */
 int lbac3_autotune(lbac3_ctx* h, int32_t steps, double* us_per_step);

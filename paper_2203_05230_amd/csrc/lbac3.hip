@@ -43,8 +43,6 @@ __host__ __device__ constexpr R w3(int q) {
     return q == 0 ? R(1.0 / 3.0) : (q <= 6 ? R(1.0 / 18.0) : R(1.0 / 36.0));
 }
 
-constexpr int kTX = 32;          // threads per tile along x (tile heights TY = 8 or 16)
-constexpr int kIX = kTX - 2;     // columns updated per tile along x
 
 struct Args3 {
     const void* src;
@@ -54,6 +52,7 @@ struct Args3 {
     int64_t plane_stride;  // elements between population planes
     int32_t pitch, nx, ny, nz;
     int32_t strip_z, nbx, nby, nbz, n_xcd;
+    int32_t z_major;       // 1: tile order with the strip index fastest
     const double* vtab;    // per component u, v, w: factors over x (nx), y (ny), z (nz)
     const int64_t* t_dev;
     int32_t k;             // step offset within a chunk of launches
@@ -61,33 +60,62 @@ struct Args3 {
     int32_t time_dep;      // 1: velocity scaled by cos(pi t / T)
 };
 
-// One step on the tile (bxi, byi) of columns and the strip bzi of planes at
-// time t.  A thread owns column (gx, gy) (the tile grown by one column on each
-// side, periodic); per iteration it pulls the 19 values of its column on the
-// newest plane r (Eq. (9) streaming) straight from global memory (neighbouring
-// columns and planes are cache hits), forms phi (Eq. (12)) and psi (Eq. (13))
-// there, and the interior threads update the plane behind it from the psi
-// ring in LDS (three planes).  Loads, LDS writes and stores carry no branch;
-// stores of threads without an updated node are dropped.
+// One step on the tile (bxi, byi) of TX x TY columns and the strip bzi of
+// planes at time t.  Thread (tx, ty) owns column (TX bxi + tx, TY byi + ty)
+// (periodic); per iteration it pulls the 19 values of its column on the
+// newest plane (Eq. (9) streaming) straight from global memory, forms phi
+// (Eq. (12)) and psi (Eq. (13)) there, and updates the plane behind it from a
+// psi ring in LDS (three planes of the tile grown by one column on each
+// side).  The 2 (TX + 2) + 2 TY rim columns of the grown tile are pulled, for
+// their psi only, by the first waves of the block (one column per lane).
+// Even strips march up and odd strips down, so two neighbouring strips pull
+// the planes they share at the same time (both at their start or both at
+// their end).  Loads, LDS writes and stores of the main loop carry no branch
+// but the uniform one around the rim pulls; stores of columns outside the
+// lattice are dropped.
 // MODE 0: the update keeps its node's 19 pulled values in registers from the
 // iteration that loaded them.  MODE 1: the update re-reads them (cache hits),
 // issued together with the new plane's loads; fewer registers.  MODE 2: the
 // next plane's loads are issued before the update, so they are in flight
-// while it runs; the loop body then carries no branch at all (the two
-// pipeline-fill iterations compute an update whose stores are dropped).
-template <typename R, int TY, int MODE>
-__global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
-    constexpr int kTY = TY, kIY = TY - 2;
-    __shared__ R ring[3][kTY][kTX];
+// while it runs (the two pipeline-fill iterations compute an update whose
+// stores are dropped).
+template <typename R, int TX, int TY, int MODE>
+__global__ __launch_bounds__(TX * TY) void step3_kernel(Args3 a) {
+    constexpr int kTX = TX;
+    constexpr int kW = kTX + 2, kH = TY + 2;       // ring plane: the tile grown by one column
+    constexpr int kRim = 2 * kW + 2 * TY;          // rim columns of the grown tile
+    constexpr int kRimWaves = (kRim + 63) / 64;    // waves that pull them
+    __shared__ R ring[3][kH * kW];
     const int ntile = a.nbx * a.nby * a.nbz;
     const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
-    const int bxi = tile % a.nbx, byi = (tile / a.nbx) % a.nby, bzi = tile / (a.nbx * a.nby);
+    int bxi, byi, bzi;
+    if (a.z_major) {
+        bzi = tile % a.nbz;
+        bxi = (tile / a.nbz) % a.nbx;
+        byi = tile / (a.nbz * a.nbx);
+    } else {
+        bxi = tile % a.nbx;
+        byi = (tile / a.nbx) % a.nby;
+        bzi = tile / (a.nbx * a.nby);
+    }
     const int tx = threadIdx.x % kTX, ty = threadIdx.x / kTX;
-    const int ux = bxi * kIX - 1 + tx, uy = byi * kIY - 1 + ty;  // unwrapped column
+    const int ux = bxi * kTX + tx, uy = byi * TY + ty;  // unwrapped column
     const int gx = wrap_idx(ux, a.nx), gy = wrap_idx(uy, a.ny);
-    const bool inter = tx >= 1 && tx <= kIX && ty >= 1 && ty <= kIY && ux < a.nx && uy < a.ny;
+    const bool inter = ux < a.nx && uy < a.ny;
+    const int own = (ty + 1) * kW + (tx + 1);  // ring slot of the own column
+    // rim column of this lane (lanes past the rim repeat the last one)
+    const bool rim_wave = (int)(threadIdx.x / 64) < kRimWaves;  // uniform
+    const int rk = min((int)threadIdx.x, kRim - 1);
+    const int rx = rk < kW ? rk - 1 : (rk < 2 * kW ? rk - kW - 1 : (rk < 2 * kW + TY ? -1 : kTX));
+    const int ry = rk < kW ? -1 : (rk < 2 * kW ? TY : (rk < 2 * kW + TY ? rk - 2 * kW : rk - 2 * kW - TY));
+    const int rslot = (ry + 1) * kW + (rx + 1);
+    const int rgx = wrap_idx(bxi * kTX + rx, a.nx), rgy = wrap_idx(byi * TY + ry, a.ny);
     const int z0 = bzi * a.strip_z;
     const int hz = min(a.strip_z, a.nz - z0);
+    const bool down = (bzi & 1) != 0;
+    // plane entering at iteration i (from one below the strip up, or from one
+    // above it down); the plane updated at iteration i is the one of i - 1
+    auto plane_at = [&](int i) { return wrap_idx(down ? z0 + hz - i : z0 - 1 + i, a.nz); };
     const int64_t t = a.t_dev[0] + a.k;
 
     const bool first = (t == 0);
@@ -110,48 +138,61 @@ __global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
     // 32-bit byte offsets from uniform plane bases (a plane is below 2 GiB).
     const char* sb = static_cast<const char*>(a.src);
     const uint32_t pb = (uint32_t)(a.plane_stride * (int64_t)sizeof(R));  // bytes between planes (< 2^31)
-    const uint32_t xcol[3] = {(uint32_t)wrap_idx(gx + 1, a.nx) * (uint32_t)sizeof(R), (uint32_t)gx * (uint32_t)sizeof(R),
-                              (uint32_t)wrap_idx(gx - 1, a.nx) * (uint32_t)sizeof(R)};  // index c_x + 1
     const uint32_t rowb = (uint32_t)a.pitch * (uint32_t)sizeof(R);
-    const uint32_t yoff[3] = {(uint32_t)wrap_idx(gy + 1, a.ny) * rowb, (uint32_t)gy * rowb,
-                              (uint32_t)wrap_idx(gy - 1, a.ny) * rowb};
     const uint32_t zsb = (uint32_t)zs * (uint32_t)sizeof(R);
-    // f_i(x) = f*_i(x - c_i) for the node of this column on plane zp (Eq. (9) streaming)
-    auto pull = [&](int zp, R (&v)[19]) __attribute__((always_inline)) {
+    struct Col {
+        uint32_t x[3], y[3];  // index c + 1
+    };
+    auto col_of = [&](int cx, int cy) {
+        Col c;
+        c.x[0] = (uint32_t)wrap_idx(cx + 1, a.nx) * (uint32_t)sizeof(R);
+        c.x[1] = (uint32_t)cx * (uint32_t)sizeof(R);
+        c.x[2] = (uint32_t)wrap_idx(cx - 1, a.nx) * (uint32_t)sizeof(R);
+        c.y[0] = (uint32_t)wrap_idx(cy + 1, a.ny) * rowb;
+        c.y[1] = (uint32_t)cy * rowb;
+        c.y[2] = (uint32_t)wrap_idx(cy - 1, a.ny) * rowb;
+        return c;
+    };
+    const Col oc = col_of(gx, gy), rc = col_of(rgx, rgy);
+    // f_i(x) = f*_i(x - c_i) for the node of column c on plane zp (Eq. (9) streaming)
+    auto pull = [&](const Col& c, int zp, R (&v)[19]) __attribute__((always_inline)) {
         const uint32_t zoff[3] = {(uint32_t)wrap_idx(zp + 1, a.nz) * zsb, (uint32_t)zp * zsb,
                                   (uint32_t)wrap_idx(zp - 1, a.nz) * zsb};  // plane zp - c_z, index c_z + 1
 #pragma unroll
         for (int q = 0; q < 19; ++q)
-            v[q] = *reinterpret_cast<const R*>(sb + (size_t)q * pb + (zoff[cz3(q) + 1] + yoff[cy3(q) + 1] + xcol[cx3(q) + 1]));
+            v[q] = *reinterpret_cast<const R*>(sb + (size_t)q * pb + (zoff[cz3(q) + 1] + c.y[cy3(q) + 1] + c.x[cx3(q) + 1]));
     };
     auto pold_at = [&](int zp) { return pold_plane[(int64_t)zp * zs + (int64_t)gy * a.pitch + gx]; };
+    auto psi_of = [&](R phi) {
+        const R pc = clip01(phi);
+        return psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
+    };
 
     R fprev[19];
     R phiprev = R(0), poldprev = R(0);
 #pragma unroll
     for (int q = 0; q < 19; ++q) fprev[q] = R(0);
-    // clamped neighbour columns in the ring (threads on the tile's rim read
-    // themselves; their results are not stored)
-    const int txm = max(tx - 1, 0), txp = min(tx + 1, kTX - 1);
-    const int tym = max(ty - 1, 0), typ = min(ty + 1, kTY - 1);
 
     // update of node (gx, gy, zc) from the psi ring, its pulled values fp,
     // phi and phi(t - 1); stores dropped unless st
     auto update = [&](int it, int zc, bool st, const R (&fp)[19], R phi, R poldv) __attribute__((always_inline)) {
-        const int sm = (it + 1) % 3, s0 = (it + 2) % 3, sp = it % 3;  // planes zc - 1, zc, zc + 1
+        // ring planes of zc - 1, zc, zc + 1 (the plane entered two iterations
+        // ago, one ago, now; the other way round marching down)
+        const R* r2 = ring[(it + 1) % 3];
+        const R* r0 = ring[it % 3];
+        const R* pm = down ? r0 : r2;
+        const R* pc = ring[(it + 2) % 3];
+        const R* pp = down ? r2 : r0;
+        const int c = own, e = own + 1, w = own - 1, n = own + kW, s = own - kW;
         // grad psi = sum_i w_i c_i psi(x + c_i) / c_s^2: faces weigh 1/6, edges 1/12
-        const R gxv = fmaR(ring[s0][ty][txp] - ring[s0][ty][txm], R(1.0 / 6.0),
-                           (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][tym][txp] - ring[s0][typ][txm])) +
-                            ((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sm][ty][txp] - ring[sp][ty][txm]))) *
+        const R gxv = fmaR(pc[e] - pc[w], R(1.0 / 6.0),
+                           (((pc[n + 1] - pc[s - 1]) + (pc[s + 1] - pc[n - 1])) + ((pp[e] - pm[w]) + (pm[e] - pp[w]))) *
                                R(1.0 / 12.0));
-        const R gyv = fmaR(ring[s0][typ][tx] - ring[s0][tym][tx], R(1.0 / 6.0),
-                           (((ring[s0][typ][txp] - ring[s0][tym][txm]) + (ring[s0][typ][txm] - ring[s0][tym][txp])) +
-                            ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sm][typ][tx] - ring[sp][tym][tx]))) *
+        const R gyv = fmaR(pc[n] - pc[s], R(1.0 / 6.0),
+                           (((pc[n + 1] - pc[s - 1]) + (pc[n - 1] - pc[s + 1])) + ((pp[n] - pm[s]) + (pm[n] - pp[s]))) *
                                R(1.0 / 12.0));
-        const R gzv = fmaR(ring[sp][ty][tx] - ring[sm][ty][tx], R(1.0 / 6.0),
-                           (((ring[sp][ty][txp] - ring[sm][ty][txm]) + (ring[sp][ty][txm] - ring[sm][ty][txp])) +
-                            ((ring[sp][typ][tx] - ring[sm][tym][tx]) + (ring[sp][tym][tx] - ring[sm][typ][tx]))) *
-                               R(1.0 / 12.0));
+        const R gzv = fmaR(pp[c] - pm[c], R(1.0 / 6.0),
+                           (((pp[e] - pm[w]) + (pp[w] - pm[e])) + ((pp[n] - pm[s]) + (pp[s] - pm[n]))) * R(1.0 / 12.0));
         const R inv = Math<R>::rcp(Math<R>::sqrt(fmaR(gxv, gxv, fmaR(gyv, gyv, gzv * gzv))) + delta);
         const R pcl = clip01(phi);
         const R S = (pcl + delta) * (R(1) - pcl + delta) * s_scale;
@@ -159,19 +200,19 @@ __global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
         const R fzv = R(lbac::row_factor(a.vtab, L + a.nx + a.ny + zc));
         const R fzw = R(lbac::row_factor(a.vtab, 2 * L + a.nx + a.ny + zc));
         const R ur = fxu * fyu * fz, vr = fxv * fyv * fzv, wr = fxw * fyw * fzw;
-        const R u = s_now * ur, v = s_now * vr, w = s_now * wr;
+        const R u = s_now * ur, v = s_now * vr, wv = s_now * wr;
         const R phio = first ? phi : poldv;
         // bracket of Eq. (11): d_t(phi u) by explicit Euler + c_s^2 S n
         const R Sn = R(1.0 / 3.0) * S * inv;
         const R Gx = fmaR(Sn, gxv, fmaR(phi, u, -(phio * (s_old * ur))));
         const R Gy = fmaR(Sn, gyv, fmaR(phi, v, -(phio * (s_old * vr))));
-        const R Gz = fmaR(Sn, gzv, fmaR(phi, w, -(phio * (s_old * wr))));
+        const R Gz = fmaR(Sn, gzv, fmaR(phi, wv, -(phio * (s_old * wr))));
         // Eq. (9)-(11): f*_i = (1 - 1/tau) f_i + w_i [phi/tau + 3 c_i.(phi u/tau + (1 - 1/(2 tau)) G)];
         // the rest population as the remainder keeps sum_i f*_i = phi exactly
         const R A0 = omega * phi;
         const R bx = R(3) * fmaR(A0, u, kforce * Gx);
         const R by = R(3) * fmaR(A0, v, kforce * Gy);
-        const R bz = R(3) * fmaR(A0, w, kforce * Gz);
+        const R bz = R(3) * fmaR(A0, wv, kforce * Gz);
         R out[19];
         const R af = w3<R>(1) * A0, ae = w3<R>(7) * A0;
         const R xf = w3<R>(1) * bx, yf = w3<R>(1) * by, zf = w3<R>(1) * bz;
@@ -198,7 +239,7 @@ __global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
 #pragma unroll
         for (int q = 1; q < 19; ++q) rest -= out[q];
         out[0] = rest;
-        // threads without an updated node store nothing (dropped offsets)
+        // columns outside the lattice store nothing (dropped offsets)
         const uint32_t node = (uint32_t)((int64_t)zc * zs + (int64_t)gy * a.pitch + gx);
         const uint32_t b = st ? node * (uint32_t)sizeof(R) : kDropOffset;
 #pragma unroll
@@ -211,13 +252,13 @@ __global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
     R fn[19];
     R pn = R(0);
     if constexpr (MODE == 2) {
-        pull(wrap_idx(z0 - 1, a.nz), fn);
-        pn = pold_at(wrap_idx(z0 - 1, a.nz));
+        pull(oc, plane_at(0), fn);
+        pn = pold_at(plane_at(0));
     }
     for (int it = 0; it < iters; ++it) {
-        const int zr = wrap_idx(z0 - 1 + it, a.nz);  // the plane entering
-        const int zc = wrap_idx(zr - 1, a.nz);       // the plane updated (from the third iteration on)
-        // ---- pull, phi (Eq. (12)) and psi (Eq. (13)) on plane zr
+        const int zr = plane_at(it);      // the plane entering
+        const int zc = plane_at(it - 1);  // the plane updated (from the third iteration on)
+        // ---- pull, phi (Eq. (12)) and psi (Eq. (13)) on plane zr: own column, then the rim
         R f[19];
         R pold;
         if constexpr (MODE == 2) {
@@ -225,28 +266,33 @@ __global__ __launch_bounds__(kTX * TY) void step3_kernel(Args3 a) {
             for (int q = 0; q < 19; ++q) f[q] = fn[q];
             pold = pn;
         } else {
-            pull(zr, f);
+            pull(oc, zr, f);
             pold = pold_at(zr);
+        }
+        if (rim_wave) {
+            R g[19];
+            pull(rc, zr, g);
+            R sg = R(0);
+#pragma unroll
+            for (int q = 0; q < 19; ++q) sg += g[q];
+            ring[it % 3][rslot] = psi_of(sg);
         }
         R s = R(0);
 #pragma unroll
         for (int q = 0; q < 19; ++q) s += f[q];
-        const R pc = clip01(s);
-        ring[it % 3][ty][tx] = psi_scale * (Math<R>::log2(pc + delta) - Math<R>::log2(R(1) - pc + delta));
-        if constexpr (MODE == 1) pull(zc, fprev);  // the update's own pulled values, before the barrier
+        ring[it % 3][own] = psi_of(s);
+        if constexpr (MODE == 1) pull(oc, zc, fprev);  // the update's own pulled values, before the barrier
         if constexpr (MODE == 2) {
             // the next plane (past the strip: the last plane again, not used)
-            const int zn = wrap_idx(z0 - 1 + min(it + 1, iters - 1), a.nz);
-            pull(zn, fn);
+            const int zn = plane_at(min(it + 1, iters - 1));
+            pull(oc, zn, fn);
             pn = pold_at(zn);
         }
         lds_barrier();
-        // ---- update the plane behind (zc = zr - 1); the first two iterations fill the pipeline
+        // ---- update the plane behind (zc); the first two iterations fill the pipeline
         if constexpr (MODE == 2) {
             update(it, zc, inter && it >= 2, fprev, phiprev, poldprev);
         } else {
-            // (each iteration consumes its own loads at once, so a branch around
-            // the stores costs no load overlap here)
             if (it >= 2) update(it, zc, inter, fprev, phiprev, poldprev);
         }
         lds_barrier();  // the ring slot written next iteration was read above
@@ -361,8 +407,10 @@ struct lbac3_ctx {
     int cur = 0;
     int64_t t = 0;
     int strip_z = 32;
-    int tile_y = 16;     // tile height (8 or 16 rows of 32 columns)
+    int tile_x = 32;     // tile shape in columns (one of kShapes)
+    int tile_y = 16;
     int mode = 0;        // 0 keep, 1 re-pull, 2 prefetch (see step3_kernel)
+    int z_major = 0;     // tile order: 0 x fastest, 1 strip fastest
     std::string err;
 };
 
@@ -477,10 +525,11 @@ lbac3::Args3 make_args3(const lbac3_ctx* h, int src, int32_t k) {
     a.ny = h->p.ny;
     a.nz = h->p.nz;
     a.strip_z = std::min(h->strip_z, h->p.nz);
-    a.nbx = (h->p.nx + lbac3::kIX - 1) / lbac3::kIX;
-    a.nby = (h->p.ny + (h->tile_y - 2) - 1) / (h->tile_y - 2);
+    a.nbx = (h->p.nx + h->tile_x - 1) / h->tile_x;
+    a.nby = (h->p.ny + h->tile_y - 1) / h->tile_y;
     a.nbz = (h->p.nz + a.strip_z - 1) / a.strip_z;
     a.n_xcd = 8;
+    a.z_major = h->z_major;
     a.vtab = h->vtab;
     a.t_dev = h->t_dev;
     a.k = k;
@@ -492,23 +541,41 @@ lbac3::Args3 make_args3(const lbac3_ctx* h, int src, int32_t k) {
     return a;
 }
 
-template <typename R, int TY>
-void launch3_ty(const lbac3_ctx* h, const lbac3::Args3& a, dim3 grid) {
-    const dim3 block(lbac3::kTX * TY);
+template <typename R, int TX, int TY>
+void launch3_shape(const lbac3_ctx* h, const lbac3::Args3& a, dim3 grid) {
+    const dim3 block(TX * TY);
     if (h->mode == 1)
-        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 1>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TX, TY, 1>), grid, block, 0, h->stream, a);
     else if (h->mode == 2)
-        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 2>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TX, TY, 2>), grid, block, 0, h->stream, a);
     else
-        hipLaunchKernelGGL((lbac3::step3_kernel<R, TY, 0>), grid, block, 0, h->stream, a);
+        hipLaunchKernelGGL((lbac3::step3_kernel<R, TX, TY, 0>), grid, block, 0, h->stream, a);
+}
+
+// Tile shapes (columns along x and y).  Blocks of 1024 threads need at most
+// 128 registers per lane, which the FP64 update exceeds: those shapes are
+// FP32 only.
+constexpr int kShapes[][2] = {{32, 8}, {32, 16}, {64, 4}, {64, 8}, {128, 4}, {32, 32}, {64, 16}, {128, 8}};
+
+bool tile_ok(const lbac3_ctx* h, int tile_x, int tile_y) {
+    for (const auto& sh : kShapes)
+        if (sh[0] == tile_x && sh[1] == tile_y) return tile_x * tile_y <= 512 || h->p.precision == LBAC_F32;
+    return false;
 }
 
 template <typename R>
 void launch3_t(const lbac3_ctx* h, const lbac3::Args3& a, dim3 grid) {
-    if (h->tile_y == 8)
-        launch3_ty<R, 8>(h, a, grid);
-    else
-        launch3_ty<R, 16>(h, a, grid);
+    const int tx = h->tile_x, ty = h->tile_y;
+    if (tx == 32 && ty == 8) launch3_shape<R, 32, 8>(h, a, grid);
+    else if (tx == 32 && ty == 16) launch3_shape<R, 32, 16>(h, a, grid);
+    else if (tx == 64 && ty == 4) launch3_shape<R, 64, 4>(h, a, grid);
+    else if (tx == 64 && ty == 8) launch3_shape<R, 64, 8>(h, a, grid);
+    else if (tx == 128 && ty == 4) launch3_shape<R, 128, 4>(h, a, grid);
+    else if constexpr (sizeof(R) == 4) {
+        if (tx == 32 && ty == 32) launch3_shape<R, 32, 32>(h, a, grid);
+        else if (tx == 64 && ty == 16) launch3_shape<R, 64, 16>(h, a, grid);
+        else if (tx == 128 && ty == 8) launch3_shape<R, 128, 8>(h, a, grid);
+    }
 }
 
 hipError_t launch_step3(const lbac3_ctx* h, int src, int32_t k) {
@@ -714,22 +781,30 @@ int lbac3_time(lbac3_ctx* h, int64_t* t) {
     return LBAC_OK;
 }
 
-int lbac3_set_launch(lbac3_ctx* h, int32_t tile_y, int32_t variant, int32_t strip_z) {
+int lbac3_set_launch(lbac3_ctx* h, int32_t tile_x, int32_t tile_y, int32_t variant, int32_t strip_z,
+                     int32_t z_major) {
     if (!h) return LBAC_EINVAL;
-    if (tile_y != 8 && tile_y != 16) return fail3(h, LBAC_EINVAL, "tile_y must be 8 or 16");
+    if (z_major != 0 && z_major != 1) return fail3(h, LBAC_EINVAL, "z_major must be 0 or 1");
+    if (!tile_ok(h, tile_x, tile_y))
+        return fail3(h, LBAC_EINVAL, "tile shape must be 32x8, 32x16, 64x4, 64x8, 128x4 (or, with FP32, 32x32, 64x16, 128x8)");
     if (variant < 0 || variant > 2) return fail3(h, LBAC_EINVAL, "variant must be 0, 1 or 2");
     if (strip_z < 1) return fail3(h, LBAC_EINVAL, "strip_z must be >= 1");
+    h->tile_x = tile_x;
     h->tile_y = tile_y;
     h->mode = variant;
     h->strip_z = std::min(strip_z, h->p.nz);
+    h->z_major = z_major;
     return LBAC_OK;
 }
 
-int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_y, int32_t* variant, int32_t* strip_z) {
+int lbac3_get_launch(lbac3_ctx* h, int32_t* tile_x, int32_t* tile_y, int32_t* variant, int32_t* strip_z,
+                     int32_t* z_major) {
     if (!h) return LBAC_EINVAL;
+    if (tile_x) *tile_x = h->tile_x;
     if (tile_y) *tile_y = h->tile_y;
     if (variant) *variant = h->mode;
     if (strip_z) *strip_z = h->strip_z;
+    if (z_major) *z_major = h->z_major;
     return LBAC_OK;
 }
 
@@ -739,38 +814,57 @@ int lbac3_autotune(lbac3_ctx* h, int32_t steps, double* us_per_step) {
     hipEvent_t e0, e1;
     HIP3(h, hipEventCreate(&e0));
     HIP3(h, hipEventCreate(&e1));
-    const int keep = h->strip_z, keep_ty = h->tile_y, keep_rp = h->mode;
-    int best_s = keep, best_ty = keep_ty, best_rp = keep_rp;
+    const int keep = h->strip_z, keep_tx = h->tile_x, keep_ty = h->tile_y, keep_rp = h->mode, keep_zm = h->z_major;
+    int best_s = keep, best_tx = keep_tx, best_ty = keep_ty, best_rp = keep_rp, best_zm = keep_zm;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    for (int ty : {8, 16})
+    // strips: powers of two, and nz split into k equal parts (so that a grid
+    // that fits the device at once can march long strips in step)
+    std::vector<int> strips;
+    for (int sz = 4; sz <= 128; sz *= 2) strips.push_back(std::min(sz, h->p.nz));
+    for (int k = 1; k <= 16; ++k) strips.push_back((h->p.nz + k - 1) / k);
+    std::sort(strips.begin(), strips.end());
+    strips.erase(std::unique(strips.begin(), strips.end()), strips.end());
+    struct Shape {
+        int tx, ty, rp, sz, zm;
+    };
+    std::vector<Shape> shapes;
+    for (const auto& sh : kShapes)
         for (int rp = 0; rp < 3; ++rp)
-            for (int sz : {4, 8, 16, 32, 64, 128}) {
-                if (sz > h->p.nz && sz != 4) continue;
-                h->tile_y = ty;
-                h->mode = rp;
-                h->strip_z = std::min(sz, h->p.nz);
-                // repeated step from pop[cur] into the other buffer: the state is untouched
-                for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step3(h, h->cur, 0);
-                if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-                for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step3(h, h->cur, 0);
-                if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
-                if (e == hipSuccess) e = hipEventSynchronize(e1);
-                float ms = 0.f;
-                if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
-                if (e != hipSuccess) break;
-                if (ms < best) {
-                    best = ms;
-                    best_s = h->strip_z;
-                    best_ty = ty;
-                    best_rp = rp;
-                }
-            }
+            for (int sz : strips)
+                for (int zm = 0; zm < 2; ++zm)
+                    if (tile_ok(h, sh[0], sh[1]) && !(zm == 1 && sz == h->p.nz)) shapes.push_back({sh[0], sh[1], rp, sz, zm});
+    for (const Shape& c : shapes) {
+        h->tile_x = c.tx;
+        h->tile_y = c.ty;
+        h->mode = c.rp;
+        h->strip_z = c.sz;
+        h->z_major = c.zm;
+        // repeated step from pop[cur] into the other buffer: the state is untouched
+        for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step3(h, h->cur, 0);
+        if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
+        for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step3(h, h->cur, 0);
+        if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
+        if (e == hipSuccess) e = hipEventSynchronize(e1);
+        float ms = 0.f;
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+        if (e != hipSuccess) break;
+        if (ms < best) {
+            best = ms;
+            best_s = c.sz;
+            best_tx = c.tx;
+            best_ty = c.ty;
+            best_rp = c.rp;
+            best_zm = c.zm;
+        }
+    }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->strip_z = e == hipSuccess ? best_s : keep;
+    h->tile_x = e == hipSuccess ? best_tx : keep_tx;
     h->tile_y = e == hipSuccess ? best_ty : keep_ty;
     h->mode = e == hipSuccess ? best_rp : keep_rp;
+    h->z_major = e == hipSuccess ? best_zm : keep_zm;
     if (e != hipSuccess) return fail3(h, LBAC_EDEVICE, std::string("autotune: ") + hipGetErrorString(e));
     if (us_per_step) *us_per_step = 1000.0 * best / steps;
     return LBAC_OK;

@@ -156,8 +156,8 @@ def load():
     L.lbac3_mass.argtypes = [C.c_void_p, dp]
     L.lbac3_shape_error.argtypes = [C.c_void_p, dp, dp, dp]
     L.lbac3_time.argtypes = [C.c_void_p, P(C.c_int64)]
-    L.lbac3_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32]
-    L.lbac3_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
+    L.lbac3_set_launch.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_int32, C.c_int32]
+    L.lbac3_get_launch.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32), P(C.c_int32)]
     L.lbac3_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac3_bytes_per_node.argtypes = [C.c_void_p, dp]
     L.lbac3_last_error.argtypes = [C.c_void_p]
@@ -548,13 +548,14 @@ class Simulation3:
         _check3(load().lbac3_time(self.h, C.byref(t)), self.h)
         return t.value
 
-    def set_launch(self, tile_y, variant, strip_z):
-        _check3(load().lbac3_set_launch(self.h, int(tile_y), int(variant), int(strip_z)), self.h)
+    def set_launch(self, tile_x, tile_y, variant, strip_z, z_major=0):
+        _check3(load().lbac3_set_launch(self.h, int(tile_x), int(tile_y), int(variant), int(strip_z), int(z_major)),
+                self.h)
 
     def get_launch(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        _check3(load().lbac3_get_launch(self.h, C.byref(a), C.byref(b), C.byref(c)), self.h)
-        return a.value, b.value, c.value
+        v = [C.c_int32() for _ in range(5)]
+        _check3(load().lbac3_get_launch(self.h, *[C.byref(x) for x in v]), self.h)
+        return tuple(x.value for x in v)
 
     def autotune(self, steps=8):
         us = C.c_double()

@@ -73,7 +73,8 @@ def test_fp64_ragged_grids_and_strips(gpu_lib, dims):
         + 0.05 * rng.random((nz, ny, nx))
     ref = O3.run(oparams(c), phi0, 40)
     base = None
-    for launch in ((16, 0, 1), (8, 1, 5), (16, 1, 32), (8, 0, 3), (16, 2, 2), (8, 2, 36)):
+    for launch in ((32, 16, 0, 1), (32, 8, 1, 5, 1), (64, 4, 1, 32), (32, 8, 0, 3, 1), (128, 4, 2, 2), (64, 8, 2, 36),
+                   (32, 16, 2, 3, 1)):
         phi = gpu(gpu_lib, c, phi0, 40, "f64", launch=launch).phi()
         assert_fp64(phi, ref, 40, 1.2, 1e-10)
         if base is None:
@@ -112,17 +113,53 @@ def test_z_invariant_data_match_the_2d_form(gpu_lib):
         assert np.max(np.abs(phi3[k] - ref)) <= 200 * 1e-10
 
 
+SHAPES = {
+    # (tile_x, tile_y, variant, strip_z, z_major); odd strips march down
+    "f64": ((32, 16, 0, 32, 0), (32, 8, 0, 7, 1), (64, 4, 1, 4, 0), (64, 8, 1, 40, 0), (128, 4, 2, 16, 1),
+            (32, 8, 2, 5, 0), (32, 16, 1, 3, 1)),
+    "f32": ((32, 16, 0, 32, 0), (32, 8, 0, 7, 1), (64, 4, 1, 4, 0), (64, 8, 1, 40, 0), (128, 4, 2, 16, 1),
+            (32, 8, 2, 5, 0), (32, 32, 0, 14, 1), (32, 32, 1, 9, 0), (64, 16, 2, 20, 1), (128, 8, 1, 40, 1),
+            (128, 8, 0, 6, 0)),
+}
+
+
 @pytest.mark.parametrize("prec", ["f32", "f64"])
 def test_launch_shapes_bitwise(gpu_lib, prec):
     say("case: 3-D launch shapes", prec)
     c = deformation(40)
     phi0 = W.sphere(40, 1.0, R_frac=0.2)
     base = None
-    for launch in ((16, 0, 32), (8, 0, 7), (16, 1, 4), (8, 1, 40), (16, 2, 16), (8, 2, 5)):
+    for launch in SHAPES[prec]:
         phi = gpu(gpu_lib, c, phi0, 12, prec, launch=launch).phi()
         if base is None:
             base = phi
         assert np.array_equal(phi, base), launch
+
+
+def test_fp32_tall_tiles_match_oracle(gpu_lib):
+    """1024-thread tiles (FP32 only) on a grid that leaves ragged tiles in x
+    and y and strips marching both ways."""
+    say("case: 3-D FP32 1024-column tiles, 45x70x33")
+    c = dict(nx=45, ny=70, nz=33, eps=1.0, tau=0.8, delta=1e-10, vel="deformation", U=0.02, period_T=800.0)
+    phi0 = W.sphere(70, 1.0, R_frac=0.25)[:33, :70, :45]
+    ref = O3.run(oparams(c), phi0, 60)
+    for launch in ((32, 32, 1, 5, 1), (64, 16, 2, 11, 0), (128, 8, 0, 7, 1)):
+        err = rel_l2(gpu(gpu_lib, c, phi0, 60, "f32", launch=launch).phi(), ref)
+        say("  launch", launch, "FP32 rel L2 %.3e" % err)
+        assert err <= 1e-5
+
+
+def test_launch_shape_errors(gpu_lib):
+    c = deformation(16)
+    phi0 = W.sphere(16, 1.0, R_frac=0.2)
+    s64 = gpu_lib.Simulation3({**c, "precision": "f64"}, phi0)
+    for bad in ((32, 32, 0, 8), (128, 8, 0, 8), (64, 16, 0, 8),  # 1024-thread tiles need FP32
+                (32, 16, 3, 8), (32, 16, 0, 8, 2), (32, 12, 0, 8), (48, 8, 0, 8), (32, 16, 0, 0)):
+        with pytest.raises(gpu_lib.LbacError):
+            s64.set_launch(*bad)
+    s64.set_launch(64, 8, 2, 5, 1)
+    assert s64.get_launch() == (64, 8, 2, 5, 1)
+    s64.close()
 
 
 def test_autotune_keeps_state(gpu_lib):
