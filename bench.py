@@ -9,8 +9,9 @@ at the return time t = T.
 
 Prints ONE JSON line: MLUPS (whole job), the step kernel's achieved HBM
 bandwidth against the 8 TB/s peak (algorithmic bytes: every stored value
-read and written once per step), the L2 shape error, the same run with the
-16-bit shifted storage forms, and the CPU oracle timed on a bounded sample.
+read and written once per launch; the two-step kernel takes two steps per
+launch), the L2 shape error, the same run with the 16-bit shifted storage
+forms, and the CPU oracle timed on a bounded sample.
 """
 import argparse
 import hashlib
@@ -92,7 +93,8 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     # practical ceiling: the same bytes moved in the step's access pattern by a plain copy
     copy_us = sim.copy_ceiling(20)
     out = dict(ms_total=ms, wall_s=wall, launch=list(launch), e1=e1, e2=e2, mass_drift=abs(m1 - m0) / m0,
-               bytes_per_node=sim.bytes_per_node(), t_end=sim.time(), copy_us=copy_us)
+               bytes_per_node=sim.bytes_per_node(), steps_per_launch=sim.steps_per_launch(), t_end=sim.time(),
+               copy_us=copy_us)
     sim.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     return out
@@ -247,6 +249,8 @@ def main():
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
+    ap.add_argument("--one-step-steps", type=int, default=512,
+                    help="steps of the one-step kernel timed for comparison when the two-step kernel runs (0: skip)")
     ap.add_argument("--steps3d", type=int, default=200, help="timed steps of the D3Q19 leg")
     ap.add_argument("--launch3d", default="", help="tile_x,tile_y,variant,strip_z,z_major of the D3Q19 leg (default: autotune)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -288,16 +292,32 @@ def main():
     nodes = n * n
     ms_per_step = main_run["ms_total"] / args.steps
     mlups = nodes * args.steps / (main_run["ms_total"] * 1e-3) / 1e6
+    # the dominant kernel: one launch reads and writes the stored state once
+    # and takes steps_per_launch steps (an odd count ends with a one-step launch)
+    spl = main_run["steps_per_launch"]
+    launches = args.steps // spl + args.steps % spl
+    launch_ms = main_run["ms_total"] / launches
     alg_bytes = main_run["bytes_per_node"] * nodes
-    achieved = alg_bytes / (ms_per_step * 1e-3) / 1e9
+    achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(alg_bytes)
+    one_step = None
+    if spl > 1 and args.one_step_steps > 0:
+        # the same launch shape with the one-step kernel, for comparison
+        print("bench: one-step kernel", file=sys.stderr, flush=True)
+        lb = main_run["launch"]
+        r1 = run_form(lbac, torch, case, phi0, args.precision, args.one_step_steps, 0, launch=(lb[0], lb[1], 2))
+        ms1 = r1["ms_total"] / args.one_step_steps
+        one_step = dict(launch=r1["launch"], steps=args.one_step_steps, ms_per_step=round(ms1, 4),
+                        mlups=round(nodes / (ms1 * 1e-3) / 1e6, 1),
+                        achieved_gbs=round(r1["bytes_per_node"] * nodes / (ms1 * 1e-3) / 1e9, 1))
     forms = {}
     for f in [s for s in args.forms.split(",") if s]:
         print("bench: form %s" % f, file=sys.stderr, flush=True)
         r = run_form(lbac, torch, case, phi0, f, args.steps, args.warmup, autotune=True)
         fm = nodes * args.steps / (r["ms_total"] * 1e-3) / 1e6
         forms[f] = dict(mlups=round(fm, 1), ms_per_step=round(r["ms_total"] / args.steps, 4),
-                        hbm_gbs=round(r["bytes_per_node"] * nodes / (r["ms_total"] / args.steps * 1e-3) / 1e9, 1),
+                        hbm_gbs=round(r["bytes_per_node"] / r["steps_per_launch"] * nodes
+                                      / (r["ms_total"] / args.steps * 1e-3) / 1e9, 1),
                         bytes_per_node=r["bytes_per_node"], e2=r["e2"], e1=r["e1"], mass_drift=r["mass_drift"],
                         e2_vs_plain=r["e2"] / main_run["e2"] if main_run["e2"] > 0 else None,
                         launch=r["launch"])
@@ -338,8 +358,12 @@ def main():
                      "frac": round(achieved / HBM_PEAK_GBS, 4),
                      "traffic": None if traffic is None else round(traffic, 0),
                      "algorithmic_bytes_per_launch": alg_bytes,
+                     "steps_per_launch": spl,
+                     "launch_ms": round(launch_ms, 4),
+                     "bytes_per_node_per_step": main_run["bytes_per_node"] / spl,
                      "pattern_copy_gbs": round(alg_bytes / (main_run["copy_us"] * 1e-6) / 1e9, 1),
-                     "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / ms_per_step, 4)},
+                     "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / launch_ms, 4)},
+        "one_step_kernel": one_step,
         "shape_error": {"t": main_run["t_end"], "e2": main_run["e2"], "e1": main_run["e1"],
                         "mass_drift": main_run["mass_drift"]},
         "wall_s": round(main_run["wall_s"], 3),

@@ -147,12 +147,19 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
  * bx aligned columns and shares rows through LDS, with the next row's loads
  * in flight while a row is processed; LBAC_KERNEL_BLOCK_DEEP: the same with
  * two rows in flight; LBAC_KERNEL_WAVE: every wavefront owns a 60-column
- * tile held in registers, bx / 64 wavefronts per block.  strip_h: rows each
- * tile marches (>= 1).  Results do not depend on the shape or variant
- * (bitwise).  LBAC_EINVAL for unsupported values. */
+ * tile held in registers, bx / 64 wavefronts per block;
+ * LBAC_KERNEL_FUSED2 (LBAC_F32 storage only): one launch takes two steps,
+ * the populations between them kept in LDS (the block layout, with the
+ * first step computed on the tile grown by two columns and rows on each
+ * side), so HBM is read and written once per two steps; an odd step count
+ * ends with one one-step launch, and with the closure on every step is a
+ * one-step launch.  strip_h: rows each tile marches (>= 1).  Results do not
+ * depend on the shape or variant (bitwise).  LBAC_EINVAL for unsupported
+ * values. */
 #define LBAC_KERNEL_BLOCK 0
 #define LBAC_KERNEL_WAVE 1
 #define LBAC_KERNEL_BLOCK_DEEP 2
+#define LBAC_KERNEL_FUSED2 3
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
 int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
@@ -179,16 +186,20 @@ int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk);
  * parameters. */
 int lbac_set_closure(lbac_ctx* h, const float* params, float theta);
 
-/* HBM bytes one step moves by design (read + write of the stored state). */
+/* HBM bytes per node one launch of the step kernel moves by design: the
+ * stored state read and written once.  A launch takes
+ * lbac_steps_per_launch steps (2 with LBAC_KERNEL_FUSED2 and FP32 storage
+ * while the closure is off, else 1), so a step moves this divided by that. */
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
+int lbac_steps_per_launch(lbac_ctx* h, int32_t* steps);
 
 /* Practical bandwidth ceiling of the step: a plain copy of the stored state
  * into the context's second buffer with the step kernel's tiling (256-column
  * tiles marching strips of rows, the same tile order) and access order but
  * none of its arithmetic.  Times `launches` (>= 1) launches at strip heights
  * 8, 16, 32 and 64 and gives the fastest mean in *us_per_launch.  Moves the
- * same bytes per node as a step (lbac_bytes_per_node).  The state is
- * unchanged.  Synchronises. */
+ * same bytes per node as a launch of the step kernel (lbac_bytes_per_node).
+ * The state is unchanged.  Synchronises. */
 int lbac_copy_ceiling(lbac_ctx* h, int32_t launches, double* us_per_launch);
 
 /* hipStream_t of the context. */

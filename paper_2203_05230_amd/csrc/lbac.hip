@@ -212,19 +212,21 @@ hipError_t launch_step_bx(StepArgs a, int variant, int bx, hipStream_t s) {
 }
 
 template <typename R, int ST>
-hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a) {
+hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant) {
     if (h->p.model == LBAC_MODEL_CONVENTIONAL)
-        return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, h->variant, h->bx, h->stream);
-    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, h->variant, h->bx, h->stream);
+        return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, variant, h->bx, h->stream);
+    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, variant, h->bx, h->stream);
 }
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
+    // one-step launches of the two-step variant use the deep block kernel
+    const int var1 = h->variant == LBAC_KERNEL_FUSED2 ? LBAC_KERNEL_BLOCK_DEEP : h->variant;
     if (h->closure) {
         // FP32 plain storage.  The block variants write the band masks; then the
         // band list is rebuilt and the correction pass adds the network's flux
         // correction at the listed nodes.
-        const int variant = h->variant == LBAC_KERNEL_WAVE ? LBAC_KERNEL_BLOCK : h->variant;
+        const int variant = var1 == LBAC_KERNEL_WAVE ? LBAC_KERNEL_BLOCK : var1;
         const hipError_t e = h->p.model == LBAC_MODEL_CONVENTIONAL
                                  ? launch_step_bx<float, ST_PLAIN, MODEL_CONVENTIONAL>(a, variant, h->bx, h->stream)
                                  : launch_step_bx<float, ST_PLAIN, MODEL_IMPROVED>(a, variant, h->bx, h->stream);
@@ -239,14 +241,68 @@ hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     }
     switch (h->p.precision) {
     case LBAC_F64:
-        return launch_step_m<double, ST_PLAIN>(h, a);
+        return launch_step_m<double, ST_PLAIN>(h, a, var1);
     case LBAC_F32:
-        return launch_step_m<float, ST_PLAIN>(h, a);
+        return launch_step_m<float, ST_PLAIN>(h, a, var1);
     case LBAC_F32_F16STORE:
-        return launch_step_m<float, ST_F16>(h, a);
+        return launch_step_m<float, ST_F16>(h, a, var1);
     default:
-        return launch_step_m<float, ST_BF16>(h, a);
+        return launch_step_m<float, ST_BF16>(h, a, var1);
     }
+}
+
+// Whether the next launches take two steps each (the fused variant, FP32
+// storage, no closure).
+bool fused(const lbac_ctx* h) {
+    return h->variant == LBAC_KERNEL_FUSED2 && !h->closure && h->p.precision == LBAC_F32;
+}
+
+template <int MODEL>
+hipError_t launch_step2_m(StepArgs a, int bx, hipStream_t s) {
+    a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
+    a.n_xcd = kXcds;
+    a.nbx = (a.nx + bx - 1) / bx;
+    const dim3 grid(a.nbx * a.nby);
+    switch (bx) {
+    case 64:
+        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 64, 2>), grid, dim3(block_threads<64>()), 0, s, a);
+        break;
+    case 128:
+        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 128, 2>), grid, dim3(block_threads<128>()), 0, s, a);
+        break;
+    default:
+        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 256, 2>), grid, dim3(block_threads<256>()), 0, s, a);
+        break;
+    }
+    return hipGetLastError();
+}
+
+// Steps k and k + 1 of the current run in one launch, from pop[src] into pop[1 - src].
+hipError_t launch_step2(const lbac_ctx* h, int src, int32_t k) {
+    const StepArgs a = make_args(h, src, k);
+    if (h->p.model == LBAC_MODEL_CONVENTIONAL) return launch_step2_m<MODEL_CONVENTIONAL>(a, h->bx, h->stream);
+    return launch_step2_m<MODEL_IMPROVED>(a, h->bx, h->stream);
+}
+
+// Queues `n` steps starting at offset k0 of the current run from pop[src]:
+// pairs of steps in fused launches where the variant allows, single steps
+// otherwise.  *flips gets the number of launches (buffer swaps).
+hipError_t launch_steps(const lbac_ctx* h, int src, int64_t k0, int64_t n, int64_t* flips) {
+    int64_t f = 0;
+    hipError_t e = hipSuccess;
+    for (int64_t k = 0; k < n && e == hipSuccess;) {
+        const int cur = src ^ (int)(f & 1);
+        if (fused(h) && n - k >= 2) {
+            e = launch_step2(h, cur, (int32_t)(k0 + k));
+            k += 2;
+        } else {
+            e = launch_step(h, cur, (int32_t)(k0 + k));
+            k += 1;
+        }
+        ++f;
+    }
+    *flips = f;
+    return e;
 }
 
 template <typename R, int ST>
@@ -422,8 +478,8 @@ int capture_graph(lbac_ctx* h, int parity) {
         h->gexec[parity] = nullptr;
     }
     HIPCHK(h, hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = hipSuccess;
-    for (int k = 0; k < h->graph_chunk && e == hipSuccess; ++k) e = launch_step(h, parity ^ (k & 1), k);
+    int64_t flips = 0;
+    hipError_t e = launch_steps(h, parity, 0, h->graph_chunk, &flips);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, (int64_t)h->graph_chunk);
         e = hipGetLastError();
@@ -440,6 +496,7 @@ int capture_graph(lbac_ctx* h, int parity) {
     if (e != hipSuccess) return fail(h, LBAC_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
     h->gexec[parity] = ge;
     h->gexec_chunk[parity] = h->graph_chunk;
+    h->gexec_flips[parity] = (int)(flips & 1);
     return LBAC_OK;
 }
 
@@ -499,16 +556,18 @@ int lbac_step(lbac_ctx* h, int64_t n) {
             int rc = capture_graph(h, h->cur);
             if (rc != LBAC_OK) return rc;
             HIPCHK(h, hipGraphLaunch(h->gexec[h->cur], h->stream));
-            done += h->graph_chunk;  // chunk is even: the state is back in pop[cur]
+            done += h->graph_chunk;
             h->t += h->graph_chunk;
+            h->cur ^= h->gexec_flips[h->cur];  // parity of the chunk's launches
         }
     }
     const int64_t r = n - done;
-    for (int64_t k = 0; k < r; ++k) HIPCHK(h, launch_step(h, h->cur ^ (int)(k & 1), (int32_t)k));
     if (r > 0) {
+        int64_t flips = 0;
+        HIPCHK(h, launch_steps(h, h->cur, 0, r, &flips));
         hipLaunchKernelGGL(advance_kernel, dim3(1), dim3(64), 0, h->stream, h->t_dev, r);
         HIPCHK(h, hipGetLastError());
-        h->cur ^= (int)(r & 1);
+        h->cur ^= (int)(flips & 1);
         h->t += r;
     }
     return LBAC_OK;
@@ -624,8 +683,11 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
 
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (!h) return LBAC_EINVAL;
-    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE && variant != LBAC_KERNEL_BLOCK_DEEP)
+    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE && variant != LBAC_KERNEL_BLOCK_DEEP &&
+        variant != LBAC_KERNEL_FUSED2)
         return fail(h, LBAC_EINVAL, "unknown kernel variant");
+    if (variant == LBAC_KERNEL_FUSED2 && h->p.precision != LBAC_F32)
+        return fail(h, LBAC_EINVAL, "the two-step variant needs LBAC_F32 storage");
     if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
@@ -655,7 +717,8 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    for (int var = LBAC_KERNEL_BLOCK; var <= LBAC_KERNEL_BLOCK_DEEP && e == hipSuccess; ++var)
+    const int last_var = h->p.precision == LBAC_F32 && !h->closure ? LBAC_KERNEL_FUSED2 : LBAC_KERNEL_BLOCK_DEEP;
+    for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
         for (int sh : hs) {
@@ -663,15 +726,19 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
             h->variant = var;
             h->bx = bx;
             h->strip_h = std::min(sh, h->p.ny);
-            // repeated step from pop[cur] into the scratch buffer: the state is untouched
-            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = launch_step(h, h->cur, 0);
+            // repeated launches from pop[cur] into the scratch buffer: the state
+            // is untouched; a two-step launch counts as two steps
+            const bool two = fused(h);
+            auto one = [&]() { return two ? launch_step2(h, h->cur, 0) : launch_step(h, h->cur, 0); };
+            for (int w = 0; w < 2 && e == hipSuccess; ++w) e = one();
             if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
-            for (int s = 0; s < steps && e == hipSuccess; ++s) e = launch_step(h, h->cur, 0);
+            for (int s = 0; s < steps && e == hipSuccess; ++s) e = one();
             if (e == hipSuccess) e = hipEventRecord(e1, h->stream);
             if (e == hipSuccess) e = hipEventSynchronize(e1);
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
+            if (two) ms *= 0.5f;
             if (ms < best) {
                 best = ms;
                 best_v = var;
@@ -784,8 +851,14 @@ int lbac_copy_ceiling(lbac_ctx* h, int32_t launches, double* us_per_launch) {
 
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes) {
     if (!h || !bytes) return LBAC_EINVAL;
-    // read and write of every stored value once per step
+    // read and write of every stored value once per launch
     *bytes = 2.0 * (h->nplanes * h->elem_bytes + (h->storage == ST_PLAIN ? 0 : 4));
+    return LBAC_OK;
+}
+
+int lbac_steps_per_launch(lbac_ctx* h, int32_t* steps) {
+    if (!h || !steps) return LBAC_EINVAL;
+    *steps = fused(h) ? 2 : 1;
     return LBAC_OK;
 }
 

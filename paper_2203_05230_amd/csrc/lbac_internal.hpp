@@ -57,6 +57,7 @@ struct lbac_ctx {
     int graph_chunk = 0;
     hipGraphExec_t gexec[2] = {nullptr, nullptr};
     int gexec_chunk[2] = {0, 0};
+    int gexec_flips[2] = {0, 0};  // parity of the launches in each graph
     bool in_batch = false;   // owned by a batch: lbac_free refuses it
     // learned closure (FP32 plain storage only)
     bool closure = false;

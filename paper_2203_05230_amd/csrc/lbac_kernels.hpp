@@ -77,6 +77,16 @@ __device__ __forceinline__ int wrap_idx(int a, int n) {
     return r < 0 ? r + n : r;
 }
 
+// Tile order shared by the launch kernels: workgroups are dispatched
+// round-robin over the XCDs, so XCD (g mod n_xcd) is given one contiguous
+// row-major range of block tiles; horizontally adjacent tiles then share an
+// L2 and run together.
+__device__ __forceinline__ int xcd_tile(int g, int ntile, int n_xcd) {
+    const int xcd = g % n_xcd, k = g / n_xcd;
+    const int per = ntile / n_xcd, extra = ntile % n_xcd;
+    return xcd * per + min(xcd, extra) + k;
+}
+
 // Workgroup barrier that orders LDS only: in-flight global loads of the next
 // row are not waited for, so they overlap the arithmetic of this row.
 __device__ __forceinline__ void lds_barrier() {
@@ -615,6 +625,202 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 }
 
 // ---------------------------------------------------------------------------
+// Two steps per pass over HBM (FP32 storage).
+//
+// The block owns BX aligned columns [x0, x0 + BX) and marches a strip as the
+// block variant does, with two stages chained in one pipeline.  Stage A takes
+// step t from the populations in HBM on the tile grown by two columns on each
+// side (it loads four halo columns on each side); its post-collision
+// populations f*(t) go to an LDS ring instead of HBM.  Stage B, three rows
+// behind, pulls from that ring, takes step t + 1 on the BX own columns and
+// stores f*(t + 1).  Each stage does exactly the arithmetic of one step of
+// the block variant on every node, with the same helpers and summation
+// orders, so two steps of this kernel equal two launches of the one-step
+// kernels bit for bit.  The HBM traffic per step is halved; the strip's
+// first and last four rows and the halo columns are loaded and stage A is
+// computed there by both neighbours.
+//
+// Rows at iteration it (dir = +1 up the strip, -1 down it): row R enters
+// ring A; stage A forms phi and psi on R - dir and updates R - 2 dir into
+// ring B; stage B forms phi(t + 1) and psi on R - 4 dir and updates R - 5 dir.
+// Two LDS barriers per iteration, as in the one-step kernel.
+template <int BX>
+struct Tile2Lds {
+    float ra[3][9][BX + 8];  // f*(t - 1), last three rows; index j <-> column x0 - 4 + j
+    float sa[3][BX + 6];     // psi(t) on the last three rows of stage A; j <-> x0 - 3 + j
+    float rb[3][9][BX + 4];  // f*(t) from stage A, last three rows; j <-> x0 - 2 + j
+    float sb[3][BX + 2];     // psi(t + 1); j <-> x0 - 1 + j
+};
+
+template <int MODEL, int BX, int PF>
+__device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
+                                               Tile2Lds<BX>& lds) {
+    auto& ra = lds.ra;
+    auto& sa = lds.sa;
+    auto& rb = lds.rb;
+    auto& sb = lds.sb;
+    const int l = threadIdx.x;
+    const bool colw = l < BX;  // a column thread
+    const int h = l - BX;      // lane of the halo wavefront
+    const int x0 = bxi * BX;
+    const int w = min(BX, a.nx - x0);
+    const int ys = syi * a.strip_h;
+    const int hh = min(a.strip_h, a.ny - ys);
+    const bool act = colw && l < w;  // owns column x0 + l
+    // Column of this thread, relative to x0: a column thread its own (idle
+    // ones of a narrow last tile: the tile's last column, a duplicate); halo
+    // lanes 0..7 the columns -4..-1 and w..w+3; the other halo lanes
+    // duplicate a column thread.  Duplicates load and write the same values
+    // as the owner and do no stage work.
+    const int cxo = colw ? min(l, w - 1) : (h < 4 ? h - 4 : (h < 8 ? w + h - 4 : min(h - 8, w - 1)));
+    const bool pa = act || (!colw && h >= 1 && h <= 6);  // stage A phi/psi: columns -3..w+2
+    const bool ua = act || (!colw && h >= 2 && h <= 5);  // stage A update: columns -2..w+1
+    const bool pb = act || (!colw && (h == 3 || h == 4));  // stage B phi/psi: columns -1..w
+    const int gcol = wrap_idx(x0 + cxo, a.nx);
+    const int jA = cxo + 4, jSA = cxo + 3, jB = cxo + 2, jSB = cxo + 1;
+    const Io<float, ST_PLAIN> io(a);
+    lds_barrier();  // the LDS may still be read by a previous tile of this block
+
+    const NodeConst<float> kA(a, t), kB(a, t + 1);
+    const float Ax = float(a.vtab[gcol]), Bx = float(a.vtab[a.nx + gcol]);
+
+    float fprevA[9], fcurA[9], fprevB[9], fcurB[9], oA[9], oB[9];
+    float phiprevA = 0.f, phicurA = 0.f, phiprevB = 0.f, phicurB = 0.f, phi_out = 0.f;
+    float PA2 = 0.f, PA1 = 0.f, PA0 = 0.f;             // stored sum at t - 1 (own column), rows R - 2, R - 1, R
+    float PB3 = 0.f, PB2 = 0.f, PB1 = 0.f, PB0 = 0.f;  // sum of stage A's output, rows R - 5 .. R - 2
+#pragma unroll
+    for (int q = 0; q < 9; ++q) fprevA[q] = fcurA[q] = fprevB[q] = fcurB[q] = oA[q] = oB[q] = 0.f;
+
+    const int iters = hh + 9;
+    const int dir = down ? -1 : 1;
+    auto raw_row = [&](int it) { return down ? ys + hh + 3 - it : ys - 4 + it; };
+    // lattice row loaded at iteration it (the last iteration repeats the last
+    // input row; what it forms is not used)
+    auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, iters - 2)), a.ny); };
+    auto body = [&](const int it, float(&nv)[9]) __attribute__((always_inline)) {
+        const int Rr = raw_row(it);
+        const int slot = it % 3, slot1 = (it + 2) % 3, slot2 = (it + 1) % 3;
+        // ---- row R into ring A
+        {
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                ra[slot][q][jA] = nv[q];
+                s += nv[q];
+            }
+            PA0 = s;
+        }
+        io.load(row_of(it + PF) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
+        lds_barrier();
+
+        // ---- phi (Eq. (12)) and psi (Eq. (13)): stage A on R - dir from ring A,
+        // stage B on R - 4 dir from ring B
+        if (it >= 2 && pa) {
+            const int sn = down ? slot2 : slot, ss = down ? slot : slot2;  // rows R - dir +- 1
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int sl = cy(q) == 1 ? ss : (cy(q) == 0 ? slot1 : sn);
+                fcurA[q] = ra[sl][q][jA - cx(q)];
+                s += fcurA[q];
+            }
+            phicurA = s;
+            sa[slot][jSA] = normal_source<float, MODEL>(s, kA);
+        }
+        if (it >= 7 && pb) {
+            // ring B holds rows R - 5 dir (slot it), R - 4 dir (it + 1), R - 3 dir (it + 2)
+            const int sc = slot2, sn = down ? slot : slot1, ss = down ? slot1 : slot;
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int sl = cy(q) == 1 ? ss : (cy(q) == 0 ? sc : sn);
+                fcurB[q] = rb[sl][q][jB - cx(q)];
+                s += fcurB[q];
+            }
+            phicurB = s;
+            sb[slot][jSB] = normal_source<float, MODEL>(s, kB);
+        }
+        lds_barrier();
+
+        // psi rows around the updated row (centre slot it + 2; the newest row
+        // is one step ahead of it in the march direction)
+        const int s0 = (it + 2) % 3;
+        const int sm = down ? it % 3 : (it + 1) % 3;
+        const int sp = down ? (it + 1) % 3 : it % 3;
+        // ---- stage A: update row R - 2 dir at t into ring B
+        if (it >= 4 && ua) {
+            const int y = wrap_idx(Rr - 2 * dir, a.ny);
+            const int j = jSA;
+            float gx, gy, Gx, Gy;
+            iso_gradient(sa[s0][j + 1], sa[s0][j - 1], sa[sp][j], sa[sm][j], sa[sp][j + 1], sa[sp][j - 1],
+                         sa[sm][j + 1], sa[sm][j - 1], gx, gy);
+            const float phi = phiprevA;
+            const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
+            const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
+            flux_bracket<float, MODEL>(gx, gy, phi, kA.first ? phi : PA2, kA.s_now * uxr, kA.s_now * uyr,
+                                       kA.s_old * uxr, kA.s_old * uyr, kA, Gx, Gy);
+            collide(fprevA, phi, kA.s_now * uxr, kA.s_now * uyr, Gx, Gy, kA, oA);
+            float s = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                rb[slot][q][jB] = oA[q];
+                s += oA[q];
+            }
+            PB0 = s;
+        }
+        // ---- stage B: update row R - 5 dir at t + 1 into HBM
+        const bool st = act && it >= 9;
+        const int yB = min(max(Rr - 5 * dir, 0), a.ny - 1);
+        if (st) {
+            const int j = jSB;
+            float gx, gy, Gx, Gy;
+            iso_gradient(sb[s0][j + 1], sb[s0][j - 1], sb[sp][j], sb[sm][j], sb[sp][j + 1], sb[sp][j - 1],
+                         sb[sm][j + 1], sb[sm][j - 1], gx, gy);
+            const float phi = phiprevB;
+            const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + yB));
+            const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + yB));
+            flux_bracket<float, MODEL>(gx, gy, phi, kB.first ? phi : PB3, kB.s_now * uxr, kB.s_now * uyr,
+                                       kB.s_old * uxr, kB.s_old * uyr, kB, Gx, Gy);
+            collide(fprevB, phi, kB.s_now * uxr, kB.s_now * uyr, Gx, Gy, kB, oB);
+            phi_out = phi;
+        }
+        io.store(st, (uint32_t)yB * (uint32_t)a.pitch + (uint32_t)(x0 + l), oB, phi_out);
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            fprevA[q] = fcurA[q];
+            fprevB[q] = fcurB[q];
+        }
+        phiprevA = phicurA;
+        phiprevB = phicurB;
+        PA2 = PA1;
+        PA1 = PA0;
+        PB3 = PB2;
+        PB2 = PB1;
+        PB1 = PB0;
+    };
+    float na[9], nb[9];
+    io.load(row_of(0) * (uint32_t)a.pitch + (uint32_t)gcol, na);
+    if constexpr (PF == 1) {
+        for (int it = 0; it < iters; ++it) body(it, na);
+    } else {
+        io.load(row_of(1) * (uint32_t)a.pitch + (uint32_t)gcol, nb);
+        for (int it = 0; it < iters; it += 2) {
+            body(it, na);
+            if (it + 1 < iters) body(it + 1, nb);
+        }
+    }
+}
+
+template <int MODEL, int BX, int PF>
+__global__ __launch_bounds__(block_threads<BX>()) void step2_kernel_lds(StepArgs a) {
+    __shared__ Tile2Lds<BX> lds;
+    const int ntile = a.nbx * a.nby;
+    const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
+    const int bxi = tile % a.nbx, syi = tile / a.nbx;
+    step2_tile_lds<MODEL, BX, PF>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+}
+
+// ---------------------------------------------------------------------------
 // The step on one tile, one wavefront per tile.
 //
 // A wavefront owns kTileW = 60 output columns and marches a strip of
@@ -954,15 +1160,6 @@ __device__ __forceinline__ void step_wave(const StepArgs& a, int bxi, int syi, i
         step_wave_dir<R, ST, MODEL, 1>(a, bxi, syi, t);
 }
 
-// Tile order shared by the launch kernels: workgroups are dispatched
-// round-robin over the XCDs, so XCD (g mod n_xcd) is given one contiguous
-// row-major range of block tiles; horizontally adjacent tiles then share an
-// L2 and run together.
-__device__ __forceinline__ int xcd_tile(int g, int ntile, int n_xcd) {
-    const int xcd = g % n_xcd, k = g / n_xcd;
-    const int per = ntile / n_xcd, extra = ntile % n_xcd;
-    return xcd * per + min(xcd, extra) + k;
-}
 
 // One launch = one step.  WPB wavefronts per block take WPB horizontally
 // adjacent tiles.

@@ -58,6 +58,7 @@ EXPORTS = [
     "lbac_default_params", "lbac_init", "lbac_init_device", "lbac_free", "lbac_step", "lbac_phi",
     "lbac_phi_device", "lbac_mass", "lbac_shape_error", "lbac_time", "lbac_get_state", "lbac_set_state",
     "lbac_set_launch", "lbac_get_launch", "lbac_autotune", "lbac_set_graph_chunk", "lbac_bytes_per_node",
+    "lbac_steps_per_launch",
     "lbac_copy_ceiling", "lbac_set_closure",
     "lbac_stream", "lbac_strerror", "lbac_last_error",
     "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
@@ -114,6 +115,7 @@ def load():
     L.lbac_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac_set_graph_chunk.argtypes = [C.c_void_p, C.c_int32]
     L.lbac_bytes_per_node.argtypes = [C.c_void_p, dp]
+    L.lbac_steps_per_launch.argtypes = [C.c_void_p, P(C.c_int32)]
     L.lbac_set_closure.argtypes = [C.c_void_p, P(C.c_float), C.c_float]
     L.lbac_stream.argtypes = [C.c_void_p]
     L.lbac_stream.restype = C.c_void_p
@@ -296,7 +298,9 @@ class Simulation:
         _check(load().lbac_set_state(self.h, buf.ctypes.data_as(C.c_void_p), buf.size), self.h)
 
     def set_launch(self, bx, strip_h, variant=0):
-        """variant 0: block-wide tiles through LDS; 1: one tile per wavefront in registers."""
+        """variant 0: block-wide tiles through LDS; 1: one tile per wavefront in
+        registers; 2: block-wide with two rows of loads in flight; 3: two steps
+        per launch (FP32 storage)."""
         _check(load().lbac_set_launch(self.h, int(variant), int(bx), int(strip_h)), self.h)
 
     def get_launch(self):
@@ -326,6 +330,11 @@ class Simulation:
         b = C.c_double()
         _check(load().lbac_bytes_per_node(self.h, C.byref(b)), self.h)
         return b.value
+
+    def steps_per_launch(self):
+        n = C.c_int32()
+        _check(load().lbac_steps_per_launch(self.h, C.byref(n)), self.h)
+        return n.value
 
     def copy_ceiling(self, launches=20):
         """Mean microseconds of a plain copy of the state in the step's access pattern."""

@@ -139,7 +139,9 @@ def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib):
     phi0 = W.circle(n, 1.0)
     w = closure_params(5, 0.05)
     base = None
-    for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8)):
+    # (the two-step variant runs one-step launches while the closure is on)
+    for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8), ((128, 16, 3), 0),
+                          ((256, 32, 3), 6)):
         sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
         sim.set_launch(*launch)
         if graph:
