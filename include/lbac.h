@@ -163,8 +163,10 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
 int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
-/* Times every supported launch shape over `steps` steps each (state is left
- * unchanged) and keeps the fastest; *us_per_step (may be NULL) gets its time. */
+/* Times every supported launch shape (variant; bx; strip_h among the powers
+ * of two from 8 to 512 and ceil(ny / k) for k = 1..32) over `steps` launches
+ * each (state is left unchanged) and keeps the fastest per step;
+ * *us_per_step (may be NULL) gets its time per step. */
 int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step);
 
 /* Graph replay: when chunk > 0 (even), lbac_step replays a captured HIP

@@ -709,7 +709,13 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     if (!h || steps < 1) return LBAC_EINVAL;
     DeviceGuard g(h->device);
     const int bxs[3] = {64, 128, 256};
-    const int hs[7] = {8, 16, 32, 64, 128, 256, 512};
+    // strip heights: powers of two, and ny split into k equal strips (so that a
+    // grid whose tiles all fit on the device at once marches long strips in step)
+    std::vector<int> hs;
+    for (int sh = 8; sh <= 512; sh *= 2) hs.push_back(std::min(sh, h->p.ny));
+    for (int k = 1; k <= 32; ++k) hs.push_back((h->p.ny + k - 1) / k);
+    std::sort(hs.begin(), hs.end());
+    hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
     hipEvent_t e0, e1;
     HIPCHK(h, hipEventCreate(&e0));
     HIPCHK(h, hipEventCreate(&e1));
@@ -722,7 +728,6 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
         for (int sh : hs) {
-            if (sh > h->p.ny && sh != hs[0]) continue;
             h->variant = var;
             h->bx = bx;
             h->strip_h = std::min(sh, h->p.ny);

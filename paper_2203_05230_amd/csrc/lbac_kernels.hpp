@@ -644,21 +644,28 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // ring A; stage A forms phi and psi on R - dir and updates R - 2 dir into
 // ring B; stage B forms phi(t + 1) and psi on R - 4 dir and updates R - 5 dir.
 // Two LDS barriers per iteration, as in the one-step kernel.
+// LDS rings.  A pull f_i(x, c) = f*_i(x - c_i) needs another thread's column
+// only for the six populations with c_x != 0, and each of those only from one
+// row: the centre row (populations 1 and 3), the row behind it in the march
+// direction (the "old" pair: 5, 6 marching up, 8, 7 marching down) or the row
+// ahead (the "new" pair).  So the rings hold, per pair, as many rows as the
+// pull is late; the three populations with c_x = 0 stay in the thread's
+// registers.  Pairs are stored c_x = +1 first.
 template <int BX>
 struct Tile2Lds {
-    float ra[3][9][BX + 8];  // f*(t - 1), last three rows; index j <-> column x0 - 4 + j
-    float sa[3][BX + 6];     // psi(t) on the last three rows of stage A; j <-> x0 - 3 + j
-    float rb[3][9][BX + 4];  // f*(t) from stage A, last three rows; j <-> x0 - 2 + j
-    float sb[3][BX + 2];     // psi(t + 1); j <-> x0 - 1 + j
+    float rao[3][2][BX + 8];  // f*(t - 1), old pair, rows R - 2 dir .. R; index j <-> column x0 - 4 + j
+    float ram[2][2][BX + 8];  // f*(t - 1), populations 1 and 3, rows R - dir, R
+    float ran[2][BX + 8];     // f*(t - 1), new pair, row R
+    float sa[3][BX + 6];      // psi(t) on the last three rows of stage A; j <-> x0 - 3 + j
+    float rbo[3][2][BX + 4];  // f*(t) from stage A, old pair, three rows; j <-> x0 - 2 + j
+    float rbm[2][2][BX + 4];  // f*(t), populations 1 and 3, two rows
+    float rbn[2][BX + 4];     // f*(t), new pair, one row
+    float sb[3][BX + 2];      // psi(t + 1); j <-> x0 - 1 + j
 };
 
 template <int MODEL, int BX, int PF>
 __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
                                                Tile2Lds<BX>& lds) {
-    auto& ra = lds.ra;
-    auto& sa = lds.sa;
-    auto& rb = lds.rb;
-    auto& sb = lds.sb;
     const int l = threadIdx.x;
     const bool colw = l < BX;  // a column thread
     const int h = l - BX;      // lane of the halo wavefront
@@ -688,6 +695,9 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
     float phiprevA = 0.f, phicurA = 0.f, phiprevB = 0.f, phicurB = 0.f, phi_out = 0.f;
     float PA2 = 0.f, PA1 = 0.f, PA0 = 0.f;             // stored sum at t - 1 (own column), rows R - 2, R - 1, R
     float PB3 = 0.f, PB2 = 0.f, PB1 = 0.f, PB0 = 0.f;  // sum of stage A's output, rows R - 5 .. R - 2
+    // own-column values of the c_x = 0 populations, by age in iterations
+    float a0_1 = 0.f, ao_1 = 0.f, ao_2 = 0.f;               // ring A input: population 0, old-row one
+    float b0_1 = 0.f, b0_2 = 0.f, bo_1 = 0.f, bo_2 = 0.f, bo_3 = 0.f, bn_1 = 0.f;  // stage A output
 #pragma unroll
     for (int q = 0; q < 9; ++q) fprevA[q] = fcurA[q] = fprevB[q] = fcurB[q] = oA[q] = oB[q] = 0.f;
 
@@ -699,16 +709,23 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
     auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, iters - 2)), a.ny); };
     auto body = [&](const int it, float(&nv)[9]) __attribute__((always_inline)) {
         const int Rr = raw_row(it);
-        const int slot = it % 3, slot1 = (it + 2) % 3, slot2 = (it + 1) % 3;
-        // ---- row R into ring A
+        const int s3 = it % 3, s2 = it & 1;
+        // ---- row R into ring A (the c_x = 0 populations stay in registers)
+        float an0, ano, ann;
         {
             float s = 0.f;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                ra[slot][q][jA] = nv[q];
-                s += nv[q];
-            }
+            for (int q = 0; q < 9; ++q) s += nv[q];
             PA0 = s;
+            lds.rao[s3][0][jA] = down ? nv[8] : nv[5];
+            lds.rao[s3][1][jA] = down ? nv[7] : nv[6];
+            lds.ram[s2][0][jA] = nv[1];
+            lds.ram[s2][1][jA] = nv[3];
+            lds.ran[0][jA] = down ? nv[5] : nv[8];
+            lds.ran[1][jA] = down ? nv[6] : nv[7];
+            an0 = nv[0];
+            ano = down ? nv[4] : nv[2];
+            ann = down ? nv[2] : nv[4];
         }
         io.load(row_of(it + PF) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
         lds_barrier();
@@ -716,29 +733,50 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
         // ---- phi (Eq. (12)) and psi (Eq. (13)): stage A on R - dir from ring A,
         // stage B on R - 4 dir from ring B
         if (it >= 2 && pa) {
-            const int sn = down ? slot2 : slot, ss = down ? slot : slot2;  // rows R - dir +- 1
+            const int so = (it + 1) % 3;  // row loaded two iterations ago
+            const float o0 = lds.rao[so][0][jA - 1], o1 = lds.rao[so][1][jA + 1];
+            const float n0 = lds.ran[0][jA - 1], n1 = lds.ran[1][jA + 1];
+            float f[9];
+            f[0] = a0_1;
+            f[1] = lds.ram[s2 ^ 1][0][jA - 1];
+            f[2] = down ? ann : ao_2;
+            f[3] = lds.ram[s2 ^ 1][1][jA + 1];
+            f[4] = down ? ao_2 : ann;
+            f[5] = down ? n0 : o0;
+            f[6] = down ? n1 : o1;
+            f[7] = down ? o1 : n1;
+            f[8] = down ? o0 : n0;
             float s = 0.f;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                const int sl = cy(q) == 1 ? ss : (cy(q) == 0 ? slot1 : sn);
-                fcurA[q] = ra[sl][q][jA - cx(q)];
-                s += fcurA[q];
+                fcurA[q] = f[q];
+                s += f[q];
             }
             phicurA = s;
-            sa[slot][jSA] = normal_source<float, MODEL>(s, kA);
+            lds.sa[s3][jSA] = normal_source<float, MODEL>(s, kA);
         }
         if (it >= 7 && pb) {
-            // ring B holds rows R - 5 dir (slot it), R - 4 dir (it + 1), R - 3 dir (it + 2)
-            const int sc = slot2, sn = down ? slot : slot1, ss = down ? slot1 : slot;
+            // ring B: new pair written one iteration ago, populations 1, 3 two, old pair three
+            const float o0 = lds.rbo[s3][0][jB - 1], o1 = lds.rbo[s3][1][jB + 1];
+            const float n0 = lds.rbn[0][jB - 1], n1 = lds.rbn[1][jB + 1];
+            float f[9];
+            f[0] = b0_2;
+            f[1] = lds.rbm[s2][0][jB - 1];
+            f[2] = down ? bn_1 : bo_3;
+            f[3] = lds.rbm[s2][1][jB + 1];
+            f[4] = down ? bo_3 : bn_1;
+            f[5] = down ? n0 : o0;
+            f[6] = down ? n1 : o1;
+            f[7] = down ? o1 : n1;
+            f[8] = down ? o0 : n0;
             float s = 0.f;
 #pragma unroll
             for (int q = 0; q < 9; ++q) {
-                const int sl = cy(q) == 1 ? ss : (cy(q) == 0 ? sc : sn);
-                fcurB[q] = rb[sl][q][jB - cx(q)];
-                s += fcurB[q];
+                fcurB[q] = f[q];
+                s += f[q];
             }
             phicurB = s;
-            sb[slot][jSB] = normal_source<float, MODEL>(s, kB);
+            lds.sb[s3][jSB] = normal_source<float, MODEL>(s, kB);
         }
         lds_barrier();
 
@@ -752,8 +790,8 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
             const int y = wrap_idx(Rr - 2 * dir, a.ny);
             const int j = jSA;
             float gx, gy, Gx, Gy;
-            iso_gradient(sa[s0][j + 1], sa[s0][j - 1], sa[sp][j], sa[sm][j], sa[sp][j + 1], sa[sp][j - 1],
-                         sa[sm][j + 1], sa[sm][j - 1], gx, gy);
+            iso_gradient(lds.sa[s0][j + 1], lds.sa[s0][j - 1], lds.sa[sp][j], lds.sa[sm][j], lds.sa[sp][j + 1],
+                         lds.sa[sp][j - 1], lds.sa[sm][j + 1], lds.sa[sm][j - 1], gx, gy);
             const float phi = phiprevA;
             const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
             const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
@@ -762,11 +800,14 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
             collide(fprevA, phi, kA.s_now * uxr, kA.s_now * uyr, Gx, Gy, kA, oA);
             float s = 0.f;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                rb[slot][q][jB] = oA[q];
-                s += oA[q];
-            }
+            for (int q = 0; q < 9; ++q) s += oA[q];
             PB0 = s;
+            lds.rbo[s3][0][jB] = down ? oA[8] : oA[5];
+            lds.rbo[s3][1][jB] = down ? oA[7] : oA[6];
+            lds.rbm[s2][0][jB] = oA[1];
+            lds.rbm[s2][1][jB] = oA[3];
+            lds.rbn[0][jB] = down ? oA[5] : oA[8];
+            lds.rbn[1][jB] = down ? oA[6] : oA[7];
         }
         // ---- stage B: update row R - 5 dir at t + 1 into HBM
         const bool st = act && it >= 9;
@@ -774,8 +815,8 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
         if (st) {
             const int j = jSB;
             float gx, gy, Gx, Gy;
-            iso_gradient(sb[s0][j + 1], sb[s0][j - 1], sb[sp][j], sb[sm][j], sb[sp][j + 1], sb[sp][j - 1],
-                         sb[sm][j + 1], sb[sm][j - 1], gx, gy);
+            iso_gradient(lds.sb[s0][j + 1], lds.sb[s0][j - 1], lds.sb[sp][j], lds.sb[sm][j], lds.sb[sp][j + 1],
+                         lds.sb[sp][j - 1], lds.sb[sm][j + 1], lds.sb[sm][j - 1], gx, gy);
             const float phi = phiprevB;
             const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + yB));
             const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + yB));
@@ -797,6 +838,16 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
         PB3 = PB2;
         PB2 = PB1;
         PB1 = PB0;
+        a0_1 = an0;
+        ao_2 = ao_1;
+        ao_1 = ano;
+        // stage A's output of this iteration (stale where no update ran: not used)
+        b0_2 = b0_1;
+        b0_1 = oA[0];
+        bo_3 = bo_2;
+        bo_2 = bo_1;
+        bo_1 = down ? oA[4] : oA[2];
+        bn_1 = down ? oA[2] : oA[4];
     };
     float na[9], nb[9];
     io.load(row_of(0) * (uint32_t)a.pitch + (uint32_t)gcol, na);
