@@ -148,18 +148,19 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
  * in flight while a row is processed; LBAC_KERNEL_BLOCK_DEEP: the same with
  * two rows in flight; LBAC_KERNEL_WAVE: every wavefront owns a 60-column
  * tile held in registers, bx / 64 wavefronts per block;
- * LBAC_KERNEL_FUSED2 (LBAC_F32 storage only): one launch takes two steps,
- * the populations between them kept in LDS (the block layout, with the
- * first step computed on the tile grown by two columns and rows on each
- * side), so HBM is read and written once per two steps; an odd step count
- * ends with one one-step launch, and with the closure on every step is a
- * one-step launch.  strip_h: rows each tile marches (>= 1).  Results do not
- * depend on the shape or variant (bitwise).  LBAC_EINVAL for unsupported
- * values. */
+ * LBAC_KERNEL_FUSED2 and LBAC_KERNEL_FUSED3 (LBAC_F32 storage only): one
+ * launch takes S = 2 or 3 steps, the populations between them kept in LDS
+ * (the block layout; step k of S is computed on the tile grown by
+ * 2 (S - 1 - k) columns and rows on each side), so HBM is read and written
+ * once per S steps; a step count that is not a multiple of S ends with
+ * one-step launches, and with the closure on every step is a one-step
+ * launch.  strip_h: rows each tile marches (>= 1).  Results do not depend on
+ * the shape or variant (bitwise).  LBAC_EINVAL for unsupported values. */
 #define LBAC_KERNEL_BLOCK 0
 #define LBAC_KERNEL_WAVE 1
 #define LBAC_KERNEL_BLOCK_DEEP 2
 #define LBAC_KERNEL_FUSED2 3
+#define LBAC_KERNEL_FUSED3 4
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
 int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
@@ -190,8 +191,9 @@ int lbac_set_closure(lbac_ctx* h, const float* params, float theta);
 
 /* HBM bytes per node one launch of the step kernel moves by design: the
  * stored state read and written once.  A launch takes
- * lbac_steps_per_launch steps (2 with LBAC_KERNEL_FUSED2 and FP32 storage
- * while the closure is off, else 1), so a step moves this divided by that. */
+ * lbac_steps_per_launch steps (2 or 3 with LBAC_KERNEL_FUSED2 or _FUSED3
+ * and FP32 storage while the closure is off, else 1), so a step moves this
+ * divided by that. */
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
 int lbac_steps_per_launch(lbac_ctx* h, int32_t* steps);
 

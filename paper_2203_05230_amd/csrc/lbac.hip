@@ -220,8 +220,9 @@ hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant) {
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
-    // one-step launches of the two-step variant use the deep block kernel
-    const int var1 = h->variant == LBAC_KERNEL_FUSED2 ? LBAC_KERNEL_BLOCK_DEEP : h->variant;
+    // one-step launches of the S-step variants use the deep block kernel
+    const int var1 =
+        h->variant == LBAC_KERNEL_FUSED2 || h->variant == LBAC_KERNEL_FUSED3 ? LBAC_KERNEL_BLOCK_DEEP : h->variant;
     if (h->closure) {
         // FP32 plain storage.  The block variants write the band masks; then the
         // band list is rebuilt and the correction pass adds the network's flux
@@ -251,50 +252,56 @@ hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     }
 }
 
-// Whether the next launches take two steps each (the fused variant, FP32
-// storage, no closure).
-bool fused(const lbac_ctx* h) {
-    return h->variant == LBAC_KERNEL_FUSED2 && !h->closure && h->p.precision == LBAC_F32;
+// Steps one launch takes: S with the S-step variants (FP32 storage, closure
+// off), else 1.
+int launch_steps_of(const lbac_ctx* h) {
+    if (h->closure || h->p.precision != LBAC_F32) return 1;
+    return h->variant == LBAC_KERNEL_FUSED2 ? 2 : (h->variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
 }
 
-template <int MODEL>
-hipError_t launch_step2_m(StepArgs a, int bx, hipStream_t s) {
+template <int MODEL, int S>
+hipError_t launch_stepS_m(StepArgs a, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
     a.nbx = (a.nx + bx - 1) / bx;
     const dim3 grid(a.nbx * a.nby);
     switch (bx) {
     case 64:
-        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 64, 2>), grid, dim3(block_threads<64>()), 0, s, a);
+        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 64, S>), grid, dim3(block_threads<64>()), 0, s, a);
         break;
     case 128:
-        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 128, 2>), grid, dim3(block_threads<128>()), 0, s, a);
+        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 128, S>), grid, dim3(block_threads<128>()), 0, s, a);
         break;
     default:
-        hipLaunchKernelGGL((step2_kernel_lds<MODEL, 256, 2>), grid, dim3(block_threads<256>()), 0, s, a);
+        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 256, S>), grid, dim3(block_threads<256>()), 0, s, a);
         break;
     }
     return hipGetLastError();
 }
 
-// Steps k and k + 1 of the current run in one launch, from pop[src] into pop[1 - src].
-hipError_t launch_step2(const lbac_ctx* h, int src, int32_t k) {
+// Steps k .. k + S - 1 of the current run in one launch, from pop[src] into pop[1 - src].
+hipError_t launch_stepS(const lbac_ctx* h, int src, int32_t k, int S) {
     const StepArgs a = make_args(h, src, k);
-    if (h->p.model == LBAC_MODEL_CONVENTIONAL) return launch_step2_m<MODEL_CONVENTIONAL>(a, h->bx, h->stream);
-    return launch_step2_m<MODEL_IMPROVED>(a, h->bx, h->stream);
+    const bool conv = h->p.model == LBAC_MODEL_CONVENTIONAL;
+    if (S == 3)
+        return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 3>(a, h->bx, h->stream)
+                    : launch_stepS_m<MODEL_IMPROVED, 3>(a, h->bx, h->stream);
+    return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 2>(a, h->bx, h->stream)
+                : launch_stepS_m<MODEL_IMPROVED, 2>(a, h->bx, h->stream);
 }
 
 // Queues `n` steps starting at offset k0 of the current run from pop[src]:
-// pairs of steps in fused launches where the variant allows, single steps
-// otherwise.  *flips gets the number of launches (buffer swaps).
+// S steps per launch where the variant allows, single steps for the rest.
+// *flips gets the number of launches (buffer swaps).
 hipError_t launch_steps(const lbac_ctx* h, int src, int64_t k0, int64_t n, int64_t* flips) {
     int64_t f = 0;
     hipError_t e = hipSuccess;
+    const int S = launch_steps_of(h);
     for (int64_t k = 0; k < n && e == hipSuccess;) {
         const int cur = src ^ (int)(f & 1);
-        if (fused(h) && n - k >= 2) {
-            e = launch_step2(h, cur, (int32_t)(k0 + k));
-            k += 2;
+        if (S > 1 && n - k >= S) {
+            e = launch_stepS(h, cur, (int32_t)(k0 + k), S);
+            k += S;
         } else {
             e = launch_step(h, cur, (int32_t)(k0 + k));
             k += 1;
@@ -683,11 +690,9 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
 
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (!h) return LBAC_EINVAL;
-    if (variant != LBAC_KERNEL_BLOCK && variant != LBAC_KERNEL_WAVE && variant != LBAC_KERNEL_BLOCK_DEEP &&
-        variant != LBAC_KERNEL_FUSED2)
-        return fail(h, LBAC_EINVAL, "unknown kernel variant");
-    if (variant == LBAC_KERNEL_FUSED2 && h->p.precision != LBAC_F32)
-        return fail(h, LBAC_EINVAL, "the two-step variant needs LBAC_F32 storage");
+    if (variant < LBAC_KERNEL_BLOCK || variant > LBAC_KERNEL_FUSED3) return fail(h, LBAC_EINVAL, "unknown kernel variant");
+    if ((variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3) && h->p.precision != LBAC_F32)
+        return fail(h, LBAC_EINVAL, "the multi-step variants need LBAC_F32 storage");
     if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
@@ -723,7 +728,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    const int last_var = h->p.precision == LBAC_F32 && !h->closure ? LBAC_KERNEL_FUSED2 : LBAC_KERNEL_BLOCK_DEEP;
+    const int last_var = h->p.precision == LBAC_F32 && !h->closure ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
     for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
@@ -732,9 +737,9 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
             h->bx = bx;
             h->strip_h = std::min(sh, h->p.ny);
             // repeated launches from pop[cur] into the scratch buffer: the state
-            // is untouched; a two-step launch counts as two steps
-            const bool two = fused(h);
-            auto one = [&]() { return two ? launch_step2(h, h->cur, 0) : launch_step(h, h->cur, 0); };
+            // is untouched; an S-step launch counts as S steps
+            const int S = launch_steps_of(h);
+            auto one = [&]() { return S > 1 ? launch_stepS(h, h->cur, 0, S) : launch_step(h, h->cur, 0); };
             for (int w = 0; w < 2 && e == hipSuccess; ++w) e = one();
             if (e == hipSuccess) e = hipEventRecord(e0, h->stream);
             for (int s = 0; s < steps && e == hipSuccess; ++s) e = one();
@@ -743,7 +748,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
             float ms = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
             if (e != hipSuccess) break;
-            if (two) ms *= 0.5f;
+            ms /= (float)S;
             if (ms < best) {
                 best = ms;
                 best_v = var;
@@ -863,7 +868,7 @@ int lbac_bytes_per_node(lbac_ctx* h, double* bytes) {
 
 int lbac_steps_per_launch(lbac_ctx* h, int32_t* steps) {
     if (!h || !steps) return LBAC_EINVAL;
-    *steps = fused(h) ? 2 : 1;
+    *steps = launch_steps_of(h);
     return LBAC_OK;
 }
 

@@ -234,6 +234,7 @@ template <typename R>
 struct NodeConst {
     R eps, delta, psi_scale, s_scale, omega, kforce, keep, s_now, s_old;
     bool first;
+    __device__ __forceinline__ NodeConst() {}
     __device__ __forceinline__ NodeConst(const StepArgs& a, int64_t t) {
         first = (t == 0);
         s_now = R(time_factor(a.period_T, t));
@@ -625,47 +626,45 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 }
 
 // ---------------------------------------------------------------------------
-// Two steps per pass over HBM (FP32 storage).
+// S steps per pass over HBM (FP32 storage; S = 2 or 3).
 //
 // The block owns BX aligned columns [x0, x0 + BX) and marches a strip as the
-// block variant does, with two stages chained in one pipeline.  Stage A takes
-// step t from the populations in HBM on the tile grown by two columns on each
-// side (it loads four halo columns on each side); its post-collision
-// populations f*(t) go to an LDS ring instead of HBM.  Stage B, three rows
-// behind, pulls from that ring, takes step t + 1 on the BX own columns and
-// stores f*(t + 1).  Each stage does exactly the arithmetic of one step of
-// the block variant on every node, with the same helpers and summation
-// orders, so two steps of this kernel equal two launches of the one-step
-// kernels bit for bit.  The HBM traffic per step is halved; the strip's
-// first and last four rows and the halo columns are loaded and stage A is
-// computed there by both neighbours.
+// block variant does, with S stages chained in one pipeline.  Stage 0 takes
+// step t from the populations in HBM; stage k takes step t + k from the
+// post-collision populations of stage k - 1, which stay in an LDS ring, and
+// runs three rows behind it; stage S - 1 stores to HBM.  Stage k works on the
+// tile grown by 2 (S - 1 - k) columns on each side (so the block loads 2 S
+// halo columns on each side), and the strip's first and last 2 S rows are
+// loaded and computed by both neighbouring strips.  Each stage does exactly
+// the arithmetic of one step of the block variant on every node, with the
+// same helpers and summation orders, so S steps of this kernel equal S
+// launches of the one-step kernels bit for bit, while HBM is read and
+// written once per S steps.
 //
 // Rows at iteration it (dir = +1 up the strip, -1 down it): row R enters
-// ring A; stage A forms phi and psi on R - dir and updates R - 2 dir into
-// ring B; stage B forms phi(t + 1) and psi on R - 4 dir and updates R - 5 dir.
-// Two LDS barriers per iteration, as in the one-step kernel.
-// LDS rings.  A pull f_i(x, c) = f*_i(x - c_i) needs another thread's column
-// only for the six populations with c_x != 0, and each of those only from one
+// stage 0's ring; stage k forms phi and psi on R - (3k + 1) dir and updates
+// R - (3k + 2) dir.  Two LDS barriers per iteration, as in the one-step
+// kernel.
+//
+// Rings.  A pull f_i(x, c) = f*_i(x - c_i) needs another thread's column only
+// for the six populations with c_x != 0, and each of those only from one
 // row: the centre row (populations 1 and 3), the row behind it in the march
 // direction (the "old" pair: 5, 6 marching up, 8, 7 marching down) or the row
 // ahead (the "new" pair).  So the rings hold, per pair, as many rows as the
 // pull is late; the three populations with c_x = 0 stay in the thread's
-// registers.  Pairs are stored c_x = +1 first.
-template <int BX>
-struct Tile2Lds {
-    float rao[3][2][BX + 8];  // f*(t - 1), old pair, rows R - 2 dir .. R; index j <-> column x0 - 4 + j
-    float ram[2][2][BX + 8];  // f*(t - 1), populations 1 and 3, rows R - dir, R
-    float ran[2][BX + 8];     // f*(t - 1), new pair, row R
-    float sa[3][BX + 6];      // psi(t) on the last three rows of stage A; j <-> x0 - 3 + j
-    float rbo[3][2][BX + 4];  // f*(t) from stage A, old pair, three rows; j <-> x0 - 2 + j
-    float rbm[2][2][BX + 4];  // f*(t), populations 1 and 3, two rows
-    float rbn[2][BX + 4];     // f*(t), new pair, one row
-    float sb[3][BX + 2];      // psi(t + 1); j <-> x0 - 1 + j
+// registers.  Pairs are stored c_x = +1 first.  Index j <-> column x0 - 2S + j.
+template <int BX, int S>
+struct TileSLds {
+    static constexpr int W = BX + 4 * S;
+    float ro[S][3][2][W];  // input of stage k: old pair, three rows
+    float rm[S][2][2][W];  // populations 1 and 3, two rows
+    float rn[S][2][W];     // new pair, one row
+    float ps[S][3][W];     // psi of stage k on its last three rows
 };
 
-template <int MODEL, int BX, int PF>
-__device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
-                                               Tile2Lds<BX>& lds) {
+template <int MODEL, int BX, int S>
+__device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
+                                               TileSLds<BX, S>& lds) {
     const int l = threadIdx.x;
     const bool colw = l < BX;  // a column thread
     const int h = l - BX;      // lane of the halo wavefront
@@ -676,199 +675,176 @@ __device__ __forceinline__ void step2_tile_lds(const StepArgs& a, int bxi, int s
     const bool act = colw && l < w;  // owns column x0 + l
     // Column of this thread, relative to x0: a column thread its own (idle
     // ones of a narrow last tile: the tile's last column, a duplicate); halo
-    // lanes 0..7 the columns -4..-1 and w..w+3; the other halo lanes
+    // lanes 0..4S-1 the columns -2S..-1 and w..w+2S-1; the other halo lanes
     // duplicate a column thread.  Duplicates load and write the same values
     // as the owner and do no stage work.
-    const int cxo = colw ? min(l, w - 1) : (h < 4 ? h - 4 : (h < 8 ? w + h - 4 : min(h - 8, w - 1)));
-    const bool pa = act || (!colw && h >= 1 && h <= 6);  // stage A phi/psi: columns -3..w+2
-    const bool ua = act || (!colw && h >= 2 && h <= 5);  // stage A update: columns -2..w+1
-    const bool pb = act || (!colw && (h == 3 || h == 4));  // stage B phi/psi: columns -1..w
+    const int cxo = colw ? min(l, w - 1) : (h < 2 * S ? h - 2 * S : (h < 4 * S ? w + h - 2 * S : min(h - 4 * S, w - 1)));
+    // stage k forms phi/psi on columns -(2(S-k)-1) .. w+2(S-k)-2 and updates
+    // -(2(S-k)-2) .. w+2(S-k)-3
+    bool pk[S], uk[S];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        pk[k] = act || (!colw && h >= 2 * k + 1 && h <= 4 * S - 2 * k - 2);
+        uk[k] = act || (!colw && h >= 2 * k + 2 && h <= 4 * S - 2 * k - 3);
+    }
     const int gcol = wrap_idx(x0 + cxo, a.nx);
-    const int jA = cxo + 4, jSA = cxo + 3, jB = cxo + 2, jSB = cxo + 1;
+    const int j = cxo + 2 * S;
     const Io<float, ST_PLAIN> io(a);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
-    const NodeConst<float> kA(a, t), kB(a, t + 1);
     const float Ax = float(a.vtab[gcol]), Bx = float(a.vtab[a.nx + gcol]);
-
-    float fprevA[9], fcurA[9], fprevB[9], fcurB[9], oA[9], oB[9];
-    float phiprevA = 0.f, phicurA = 0.f, phiprevB = 0.f, phicurB = 0.f, phi_out = 0.f;
-    float PA2 = 0.f, PA1 = 0.f, PA0 = 0.f;             // stored sum at t - 1 (own column), rows R - 2, R - 1, R
-    float PB3 = 0.f, PB2 = 0.f, PB1 = 0.f, PB0 = 0.f;  // sum of stage A's output, rows R - 5 .. R - 2
-    // own-column values of the c_x = 0 populations, by age in iterations
-    float a0_1 = 0.f, ao_1 = 0.f, ao_2 = 0.f;               // ring A input: population 0, old-row one
-    float b0_1 = 0.f, b0_2 = 0.f, bo_1 = 0.f, bo_2 = 0.f, bo_3 = 0.f, bn_1 = 0.f;  // stage A output
+    NodeConst<float> kcs[S];  // stage k at time t + k
 #pragma unroll
-    for (int q = 0; q < 9; ++q) fprevA[q] = fcurA[q] = fprevB[q] = fcurB[q] = oA[q] = oB[q] = 0.f;
+    for (int k = 0; k < S; ++k) kcs[k] = NodeConst<float>(a, t + k);
+    float fprev[S][9], fcur[S][9], ob[9];
+    float phiprev[S], phicur[S];
+    float phi_out = 0.f;
+    // Histories, index = age in iterations (0: this iteration).  P[k]: the sum
+    // of stage k's input populations at the own node (phi(t + k - 1) as the
+    // one-step kernel forms it); z0, zo, zn: the own column's c_x = 0 inputs
+    // of stage k (population 0, the old-row one, the new-row one).
+    float P[S][4], z0[S][4], zo[S][4], zn[S][4];
+#pragma unroll
+    for (int k = 0; k < S; ++k) {
+        phiprev[k] = phicur[k] = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fprev[k][q] = fcur[k][q] = 0.f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) P[k][d] = z0[k][d] = zo[k][d] = zn[k][d] = 0.f;
+    }
+#pragma unroll
+    for (int q = 0; q < 9; ++q) ob[q] = 0.f;
 
-    const int iters = hh + 9;
+    const int iters = hh + 5 * S - 1;
     const int dir = down ? -1 : 1;
-    auto raw_row = [&](int it) { return down ? ys + hh + 3 - it : ys - 4 + it; };
-    // lattice row loaded at iteration it (the last iteration repeats the last
-    // input row; what it forms is not used)
-    auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, iters - 2)), a.ny); };
+    auto raw_row = [&](int it) { return down ? ys + hh + 2 * S - 1 - it : ys - 2 * S + it; };
+    // lattice row loaded at iteration it (iterations past the last input row
+    // repeat it; what they form is not used)
+    auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, hh + 4 * S - 1)), a.ny); };
+    // a stage's input into its ring and histories (v: populations at the own column)
+    auto put = [&](int k, int s3, int s2, const float(&v)[9]) __attribute__((always_inline)) {
+        float s = 0.f;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) s += v[q];
+        P[k][0] = s;
+        lds.ro[k][s3][0][j] = down ? v[8] : v[5];
+        lds.ro[k][s3][1][j] = down ? v[7] : v[6];
+        lds.rm[k][s2][0][j] = v[1];
+        lds.rm[k][s2][1][j] = v[3];
+        lds.rn[k][0][j] = down ? v[5] : v[8];
+        lds.rn[k][1][j] = down ? v[6] : v[7];
+        z0[k][0] = v[0];
+        zo[k][0] = down ? v[4] : v[2];
+        zn[k][0] = down ? v[2] : v[4];
+    };
     auto body = [&](const int it, float(&nv)[9]) __attribute__((always_inline)) {
         const int Rr = raw_row(it);
         const int s3 = it % 3, s2 = it & 1;
-        // ---- row R into ring A (the c_x = 0 populations stay in registers)
-        float an0, ano, ann;
-        {
-            float s = 0.f;
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s += nv[q];
-            PA0 = s;
-            lds.rao[s3][0][jA] = down ? nv[8] : nv[5];
-            lds.rao[s3][1][jA] = down ? nv[7] : nv[6];
-            lds.ram[s2][0][jA] = nv[1];
-            lds.ram[s2][1][jA] = nv[3];
-            lds.ran[0][jA] = down ? nv[5] : nv[8];
-            lds.ran[1][jA] = down ? nv[6] : nv[7];
-            an0 = nv[0];
-            ano = down ? nv[4] : nv[2];
-            ann = down ? nv[2] : nv[4];
-        }
-        io.load(row_of(it + PF) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
+        // ---- row R into stage 0's ring
+        put(0, s3, s2, nv);
+        io.load(row_of(it + 2) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
         lds_barrier();
 
-        // ---- phi (Eq. (12)) and psi (Eq. (13)): stage A on R - dir from ring A,
-        // stage B on R - 4 dir from ring B
-        if (it >= 2 && pa) {
-            const int so = (it + 1) % 3;  // row loaded two iterations ago
-            const float o0 = lds.rao[so][0][jA - 1], o1 = lds.rao[so][1][jA + 1];
-            const float n0 = lds.ran[0][jA - 1], n1 = lds.ran[1][jA + 1];
-            float f[9];
-            f[0] = a0_1;
-            f[1] = lds.ram[s2 ^ 1][0][jA - 1];
-            f[2] = down ? ann : ao_2;
-            f[3] = lds.ram[s2 ^ 1][1][jA + 1];
-            f[4] = down ? ao_2 : ann;
-            f[5] = down ? n0 : o0;
-            f[6] = down ? n1 : o1;
-            f[7] = down ? o1 : n1;
-            f[8] = down ? o0 : n0;
-            float s = 0.f;
+        // ---- phi (Eq. (12)) and psi (Eq. (13)) of every stage.  Stage 0 reads
+        // rows entered 0 (new pair), 1 (populations 1, 3) and 2 (old pair)
+        // iterations ago; a later stage's input rows were written 1, 2 and 3
+        // iterations ago.
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                fcurA[q] = f[q];
-                s += f[q];
-            }
-            phicurA = s;
-            lds.sa[s3][jSA] = normal_source<float, MODEL>(s, kA);
-        }
-        if (it >= 7 && pb) {
-            // ring B: new pair written one iteration ago, populations 1, 3 two, old pair three
-            const float o0 = lds.rbo[s3][0][jB - 1], o1 = lds.rbo[s3][1][jB + 1];
-            const float n0 = lds.rbn[0][jB - 1], n1 = lds.rbn[1][jB + 1];
-            float f[9];
-            f[0] = b0_2;
-            f[1] = lds.rbm[s2][0][jB - 1];
-            f[2] = down ? bn_1 : bo_3;
-            f[3] = lds.rbm[s2][1][jB + 1];
-            f[4] = down ? bo_3 : bn_1;
-            f[5] = down ? n0 : o0;
-            f[6] = down ? n1 : o1;
-            f[7] = down ? o1 : n1;
-            f[8] = down ? o0 : n0;
-            float s = 0.f;
+        for (int k = 0; k < S; ++k) {
+            const int lag = k == 0 ? 0 : 1;
+            if (it >= 5 * k + 2 && pk[k]) {
+                const int so = (it + 1 + 2 * lag) % 3;  // old pair: it - 2 - lag
+                const int sm = (it + 1 + lag) & 1;      // populations 1, 3: it - 1 - lag
+                const float o0 = lds.ro[k][so][0][j - 1], o1 = lds.ro[k][so][1][j + 1];
+                const float n0 = lds.rn[k][0][j - 1], n1 = lds.rn[k][1][j + 1];
+                const float zo_ = zo[k][2 + lag], zn_ = zn[k][lag];
+                float f[9];
+                f[0] = z0[k][1 + lag];
+                f[1] = lds.rm[k][sm][0][j - 1];
+                f[2] = down ? zn_ : zo_;
+                f[3] = lds.rm[k][sm][1][j + 1];
+                f[4] = down ? zo_ : zn_;
+                f[5] = down ? n0 : o0;
+                f[6] = down ? n1 : o1;
+                f[7] = down ? o1 : n1;
+                f[8] = down ? o0 : n0;
+                float s = 0.f;
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                fcurB[q] = f[q];
-                s += f[q];
+                for (int q = 0; q < 9; ++q) {
+                    fcur[k][q] = f[q];
+                    s += f[q];
+                }
+                phicur[k] = s;
+                lds.ps[k][s3][j] = normal_source<float, MODEL>(s, kcs[k]);
             }
-            phicurB = s;
-            lds.sb[s3][jSB] = normal_source<float, MODEL>(s, kB);
         }
         lds_barrier();
 
-        // psi rows around the updated row (centre slot it + 2; the newest row
+        // psi rows around an updated row (centre slot it + 2; the newest row
         // is one step ahead of it in the march direction)
-        const int s0 = (it + 2) % 3;
-        const int sm = down ? it % 3 : (it + 1) % 3;
-        const int sp = down ? (it + 1) % 3 : it % 3;
-        // ---- stage A: update row R - 2 dir at t into ring B
-        if (it >= 4 && ua) {
-            const int y = wrap_idx(Rr - 2 * dir, a.ny);
-            const int j = jSA;
-            float gx, gy, Gx, Gy;
-            iso_gradient(lds.sa[s0][j + 1], lds.sa[s0][j - 1], lds.sa[sp][j], lds.sa[sm][j], lds.sa[sp][j + 1],
-                         lds.sa[sp][j - 1], lds.sa[sm][j + 1], lds.sa[sm][j - 1], gx, gy);
-            const float phi = phiprevA;
-            const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
-            const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
-            flux_bracket<float, MODEL>(gx, gy, phi, kA.first ? phi : PA2, kA.s_now * uxr, kA.s_now * uyr,
-                                       kA.s_old * uxr, kA.s_old * uyr, kA, Gx, Gy);
-            collide(fprevA, phi, kA.s_now * uxr, kA.s_now * uyr, Gx, Gy, kA, oA);
-            float s = 0.f;
+        const int c0 = (it + 2) % 3;
+        const int cm = down ? it % 3 : (it + 1) % 3;
+        const int cp = down ? (it + 1) % 3 : it % 3;
+        // ---- updates: stage k on row R - (3k + 2) dir at t + k; the last stage into HBM
+        const bool st = act && it >= 5 * S - 1;
+        const int yl = min(max(Rr - (3 * S - 1) * dir, 0), a.ny - 1);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) s += oA[q];
-            PB0 = s;
-            lds.rbo[s3][0][jB] = down ? oA[8] : oA[5];
-            lds.rbo[s3][1][jB] = down ? oA[7] : oA[6];
-            lds.rbm[s2][0][jB] = oA[1];
-            lds.rbm[s2][1][jB] = oA[3];
-            lds.rbn[0][jB] = down ? oA[5] : oA[8];
-            lds.rbn[1][jB] = down ? oA[6] : oA[7];
+        for (int k = 0; k < S; ++k) {
+            const bool last = k == S - 1;
+            if (last ? st : (it >= 5 * k + 4 && uk[k])) {
+                const NodeConst<float>& kc = kcs[k];
+                const int y = last ? yl : wrap_idx(Rr - (3 * k + 2) * dir, a.ny);
+                const float(&ps)[3][TileSLds<BX, S>::W] = lds.ps[k];
+                float gx, gy, Gx, Gy;
+                iso_gradient(ps[c0][j + 1], ps[c0][j - 1], ps[cp][j], ps[cm][j], ps[cp][j + 1], ps[cp][j - 1],
+                             ps[cm][j + 1], ps[cm][j - 1], gx, gy);
+                const float phi = phiprev[k];
+                const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
+                const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
+                const float phio = P[k][k == 0 ? 2 : 3];
+                flux_bracket<float, MODEL>(gx, gy, phi, kc.first ? phi : phio, kc.s_now * uxr, kc.s_now * uyr,
+                                           kc.s_old * uxr, kc.s_old * uyr, kc, Gx, Gy);
+                collide(fprev[k], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
+                if (last)
+                    phi_out = phi;
+                else
+                    put(k + 1, s3, s2, ob);
+            }
         }
-        // ---- stage B: update row R - 5 dir at t + 1 into HBM
-        const bool st = act && it >= 9;
-        const int yB = min(max(Rr - 5 * dir, 0), a.ny - 1);
-        if (st) {
-            const int j = jSB;
-            float gx, gy, Gx, Gy;
-            iso_gradient(lds.sb[s0][j + 1], lds.sb[s0][j - 1], lds.sb[sp][j], lds.sb[sm][j], lds.sb[sp][j + 1],
-                         lds.sb[sp][j - 1], lds.sb[sm][j + 1], lds.sb[sm][j - 1], gx, gy);
-            const float phi = phiprevB;
-            const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + yB));
-            const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + yB));
-            flux_bracket<float, MODEL>(gx, gy, phi, kB.first ? phi : PB3, kB.s_now * uxr, kB.s_now * uyr,
-                                       kB.s_old * uxr, kB.s_old * uyr, kB, Gx, Gy);
-            collide(fprevB, phi, kB.s_now * uxr, kB.s_now * uyr, Gx, Gy, kB, oB);
-            phi_out = phi;
-        }
-        io.store(st, (uint32_t)yB * (uint32_t)a.pitch + (uint32_t)(x0 + l), oB, phi_out);
+        io.store(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + l), ob, phi_out);
+        // ---- age everything by one iteration
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            fprevA[q] = fcurA[q];
-            fprevB[q] = fcurB[q];
+        for (int k = 0; k < S; ++k) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fprev[k][q] = fcur[k][q];
+            phiprev[k] = phicur[k];
+#pragma unroll
+            for (int d = 3; d > 0; --d) {
+                P[k][d] = P[k][d - 1];
+                z0[k][d] = z0[k][d - 1];
+                zo[k][d] = zo[k][d - 1];
+                zn[k][d] = zn[k][d - 1];
+            }
         }
-        phiprevA = phicurA;
-        phiprevB = phicurB;
-        PA2 = PA1;
-        PA1 = PA0;
-        PB3 = PB2;
-        PB2 = PB1;
-        PB1 = PB0;
-        a0_1 = an0;
-        ao_2 = ao_1;
-        ao_1 = ano;
-        // stage A's output of this iteration (stale where no update ran: not used)
-        b0_2 = b0_1;
-        b0_1 = oA[0];
-        bo_3 = bo_2;
-        bo_2 = bo_1;
-        bo_1 = down ? oA[4] : oA[2];
-        bn_1 = down ? oA[2] : oA[4];
     };
+    // two rows of loads in flight: row r + 2 is loaded while row r is processed,
+    // into the register set row r came in
     float na[9], nb[9];
     io.load(row_of(0) * (uint32_t)a.pitch + (uint32_t)gcol, na);
-    if constexpr (PF == 1) {
-        for (int it = 0; it < iters; ++it) body(it, na);
-    } else {
-        io.load(row_of(1) * (uint32_t)a.pitch + (uint32_t)gcol, nb);
-        for (int it = 0; it < iters; it += 2) {
-            body(it, na);
-            if (it + 1 < iters) body(it + 1, nb);
-        }
+    io.load(row_of(1) * (uint32_t)a.pitch + (uint32_t)gcol, nb);
+    for (int it = 0; it < iters; it += 2) {
+        body(it, na);
+        if (it + 1 < iters) body(it + 1, nb);
     }
 }
 
-template <int MODEL, int BX, int PF>
-__global__ __launch_bounds__(block_threads<BX>()) void step2_kernel_lds(StepArgs a) {
-    __shared__ Tile2Lds<BX> lds;
+template <int MODEL, int BX, int S>
+__global__ __launch_bounds__(block_threads<BX>()) void stepS_kernel_lds(StepArgs a) {
+    __shared__ TileSLds<BX, S> lds;
     const int ntile = a.nbx * a.nby;
     const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
     const int bxi = tile % a.nbx, syi = tile / a.nbx;
-    step2_tile_lds<MODEL, BX, PF>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+    stepS_tile_lds<MODEL, BX, S>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
 }
 
 // ---------------------------------------------------------------------------

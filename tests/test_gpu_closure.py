@@ -141,7 +141,7 @@ def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib):
     base = None
     # (the two-step variant runs one-step launches while the closure is on)
     for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8), ((128, 16, 3), 0),
-                          ((256, 32, 3), 6)):
+                          ((256, 32, 3), 6), ((64, 16, 4), 0)):
         sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
         sim.set_launch(*launch)
         if graph:

@@ -1,8 +1,8 @@
-"""The two-step variant (LBAC_KERNEL_FUSED2): one launch takes two steps with
-the populations between them kept in LDS.  Each of its two stages does the
-one-step kernels' arithmetic on every node, so it must agree with them bit for
-bit, for every grid, launch shape, step count and graph chunking; and with the
-FP64 oracle to the FP32 bound."""
+"""The multi-step variants (LBAC_KERNEL_FUSED2 / _FUSED3): one launch takes S =
+2 or 3 steps with the populations between them kept in LDS.  Each of the S
+stages does the one-step kernels' arithmetic on every node, so they must agree
+with them bit for bit, for every grid, launch shape, step count and graph
+chunking; and with the FP64 oracle to the FP32 bound."""
 import sys
 
 import numpy as np
@@ -13,7 +13,8 @@ from paper_2203_05230_amd import workloads as W
 
 pytestmark = pytest.mark.gpu
 
-FUSED2 = 3
+FUSED2, FUSED3 = 3, 4
+VARIANTS = [FUSED2, FUSED3]
 
 
 def say(*a):
@@ -31,34 +32,37 @@ def run(lb, case, phi0, steps, launch, graph=0, chunks=None):
     return sim
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("model", ["improved", "conventional"])
-def test_bitwise_equal_to_one_step_kernels(gpu_lib, model):
-    say("case: two-step variant vs block variant,", model)
+def test_bitwise_equal_to_one_step_kernels(gpu_lib, model, variant):
+    say("case: multi-step variant", variant, "vs block variant,", model)
     case = {**W.single_vortex_case(320, U=0.05, period_T=100.0), "model": model}
     phi0 = W.circle(320, 1.0)
     base = run(gpu_lib, case, phi0, 13, (256, 64, 0)).phi()
-    for launch in ((256, 64, FUSED2), (64, 5, FUSED2), (128, 320, FUSED2), (256, 1, FUSED2), (64, 17, FUSED2),
-                   (128, 2, FUSED2), (256, 3, FUSED2)):
-        phi = run(gpu_lib, case, phi0, 13, launch).phi()
-        assert np.array_equal(phi, base), launch
+    for bx, strip in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17), (128, 2), (256, 3)):
+        phi = run(gpu_lib, case, phi0, 13, (bx, strip, variant)).phi()
+        assert np.array_equal(phi, base), (bx, strip, variant)
 
 
+@pytest.mark.parametrize("variant", VARIANTS)
 @pytest.mark.parametrize("nx,ny", [(100, 37), (65, 130), (1, 64), (64, 1), (3, 5), (300, 70), (257, 9)])
-def test_ragged_and_degenerate_grids(gpu_lib, nx, ny):
-    say("case: two-step variant, ragged grid", nx, ny)
+def test_ragged_and_degenerate_grids(gpu_lib, nx, ny, variant):
+    say("case: multi-step variant", variant, "ragged grid", nx, ny)
     case = dict(nx=nx, ny=ny, eps=1.0, tau=0.8, delta=1e-10, vel="uniform", ux=0.03, uy=-0.02)
     rng = np.random.default_rng(nx * 1000 + ny)
     phi0 = W.circle(max(nx, ny), 1.5, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
     base = run(gpu_lib, case, phi0, 11, (64, 7, 0)).phi()
-    for launch in ((64, 7, FUSED2), (128, 4, FUSED2), (256, 1, FUSED2), (64, 64, FUSED2), (256, 2, FUSED2)):
-        phi = run(gpu_lib, case, phi0, 11, launch).phi()
-        assert np.array_equal(phi, base), launch
+    for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2)):
+        phi = run(gpu_lib, case, phi0, 11, (bx, strip, variant)).phi()
+        assert np.array_equal(phi, base), (bx, strip, variant)
 
 
-def test_step_counts_and_graph_chunks(gpu_lib):
-    """Odd counts end with a one-step launch; graph chunks of 6 steps hold an
-    odd number of launches, so the buffers swap parity across replays."""
-    say("case: two-step variant, step counts and graph replay")
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_step_counts_and_graph_chunks(gpu_lib, variant):
+    """Counts that are not multiples of S end with one-step launches; graph
+    chunks may hold an odd number of launches, so the buffers swap parity
+    across replays."""
+    say("case: multi-step variant", variant, "step counts and graph replay")
     import torch
 
     case = W.single_vortex_case(96, U=0.05, period_T=100.0)
@@ -66,7 +70,7 @@ def test_step_counts_and_graph_chunks(gpu_lib):
     chunks = [1, 2, 3, 8, 5, 6, 12, 7, 1]
     ref = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
     ref.set_launch(128, 16, 0)
-    sims = [run(gpu_lib, case, phi0, 0, (128, 16, FUSED2), graph=g, chunks=[0]) for g in (0, 6, 8, 4)]
+    sims = [run(gpu_lib, case, phi0, 0, (128, 16, variant), graph=g, chunks=[0]) for g in (0, 6, 8, 4)]
     for n in chunks:
         ref.step(n)
         for s in sims:
@@ -82,27 +86,29 @@ def test_step_counts_and_graph_chunks(gpu_lib):
     assert all(v == ref.mass() for v in m)
 
 
-def test_fp32_parity_with_oracle(gpu_lib):
-    say("case: two-step variant vs FP64 oracle, 128x128, 1001 steps")
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_fp32_parity_with_oracle(gpu_lib, variant):
+    say("case: multi-step variant", variant, "vs FP64 oracle, 128x128, 1001 steps")
     case = W.single_vortex_case(128, eps=1.0, U=0.02, period_T=2000.0)
     phi0 = W.circle(128, 1.0)
     p = O.Params(128, 128, eps=1.0, tau=0.8, delta=1e-10, vel_kind=O.VEL_VORTEX, U=0.02, period_T=2000.0)
     ref = O.run(p, phi0, 1001)
-    sim = run(gpu_lib, case, phi0, 1001, (128, 32, FUSED2))
+    sim = run(gpu_lib, case, phi0, 1001, (128, 32, variant))
     err = float(np.linalg.norm(sim.phi() - ref) / np.linalg.norm(ref))
     say("  rel L2 %.3e" % err)
     assert err <= 1e-5
 
 
-def test_checkpoint_resume_in_the_middle(gpu_lib):
-    say("case: two-step variant, checkpoint and resume")
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_checkpoint_resume_in_the_middle(gpu_lib, variant):
+    say("case: multi-step variant", variant, "checkpoint and resume")
     case = W.single_vortex_case(80, U=0.05, period_T=100.0)
     phi0 = W.circle(80, 1.0)
-    a = run(gpu_lib, case, phi0, 9, (64, 8, FUSED2))
+    a = run(gpu_lib, case, phi0, 9, (64, 8, variant))
     blob = a.get_state()
     a.step(10)
     b = gpu_lib.Simulation({**case, "precision": "f32"}, W.circle(80, 2.0))
-    b.set_launch(64, 8, FUSED2)
+    b.set_launch(64, 8, variant)
     b.set_state(blob)
     b.step(10)
     assert b.time() == a.time() == 19
@@ -113,6 +119,19 @@ def test_checkpoint_resume_in_the_middle(gpu_lib):
 def test_needs_fp32_storage(gpu_lib, prec):
     case = W.single_vortex_case(32)
     sim = gpu_lib.Simulation({**case, "precision": prec}, W.circle(32, 1.0))
+    for variant in VARIANTS:
+        with pytest.raises(gpu_lib.LbacError):
+            sim.set_launch(128, 16, variant)
     with pytest.raises(gpu_lib.LbacError):
-        sim.set_launch(128, 16, FUSED2)
+        sim.set_launch(128, 16, 5)
+    sim.close()
+
+
+@pytest.mark.parametrize("variant,steps", [(FUSED2, 2), (FUSED3, 3), (0, 1)])
+def test_steps_per_launch(gpu_lib, variant, steps):
+    case = W.single_vortex_case(32)
+    sim = gpu_lib.Simulation({**case, "precision": "f32"}, W.circle(32, 1.0))
+    sim.set_launch(64, 8, variant)
+    assert sim.steps_per_launch() == steps
+    assert sim.bytes_per_node() == 72.0
     sim.close()
