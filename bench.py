@@ -27,7 +27,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# FP32 vector issue peak without packed instructions (which this build does
+# not use): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T operations/s,
+# i.e. 614.4 G wave64 VALU instructions/s
+ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
+# FP operations per node-update of the method: ~140 plus one log, one square
+# root and one reciprocal
+OPS_PER_NODE_UPDATE = 143.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_f32_8192_hbm_counters.txt")
+SQ_FILE = os.path.join(ROOT, "profiles", "step_f32_8192_sq_counters.txt")
 
 
 def kernel_source_hash():
@@ -38,21 +47,38 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(bytes_per_launch_alg):
-    """HBM bytes per step-kernel launch from the committed rocprofv3 counter
-    summary, if it was taken on the current kernel source; else None."""
+def _counter_summary(path, key, launch):
+    """A value from a committed rocprofv3 counter summary, if the summary was
+    taken on the current kernel source with the same kernel variant and tile
+    width (the strip height, which the autotuner may pick differently within
+    its timing noise, changes the figures by a few tenths of a percent);
+    else None."""
     try:
         kv = {}
-        with open(COUNTERS_FILE) as fh:
+        with open(path) as fh:
             for line in fh:
                 if ":" in line:
                     k, v = line.split(":", 1)
                     kv[k.strip()] = v.strip()
         if kv.get("kernel_source_sha") != kernel_source_hash():
             return None
-        return float(kv["hbm_bytes_per_launch"])
+        bx, _, variant = (int(v) for v in kv["launch"].split(","))
+        if launch is None or (bx, variant) != (int(launch[0]), int(launch[2])):
+            return None
+        return float(kv[key])
     except (OSError, KeyError, ValueError):
         return None
+
+
+def measured_traffic(launch):
+    """HBM bytes per step-kernel launch (FETCH_SIZE and WRITE_SIZE, scaled by a
+    plain copy's readings), or None."""
+    return _counter_summary(COUNTERS_FILE, "hbm_bytes_per_launch", launch)
+
+
+def measured_valu_instructions(launch):
+    """SQ_INSTS_VALU (wave instructions) per step-kernel launch, or None."""
+    return _counter_summary(SQ_FILE, "valu_instructions_per_launch", launch)
 
 
 def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False):
@@ -299,7 +325,17 @@ def main():
     launch_ms = main_run["ms_total"] / launches
     alg_bytes = main_run["bytes_per_node"] * nodes
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
-    traffic = measured_traffic(alg_bytes)
+    traffic = measured_traffic(main_run["launch"])
+    # the other resource: FP32 vector issue.  Algorithmic operations per launch
+    # against the issue peak, and (from the committed SQ counters) the share of
+    # the launch the VALU instructions occupy
+    alu_ops = OPS_PER_NODE_UPDATE * spl * nodes
+    alu_achieved = alu_ops / (launch_ms * 1e-3) / 1e12
+    valu = measured_valu_instructions(main_run["launch"])
+    valu_issue_frac = None if valu is None else valu / VALU_ISSUE_PER_S / (launch_ms * 1e-3)
+    copy_gbs = alg_bytes / (main_run["copy_us"] * 1e-6) / 1e9
+    hbm_practical_frac = None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9 / copy_gbs
+    alu_bound = valu_issue_frac is not None and hbm_practical_frac is not None and valu_issue_frac > hbm_practical_frac
     one_step = None
     if spl > 1 and args.one_step_steps > 0:
         # the same launch shape with the one-step kernel, for comparison
@@ -354,15 +390,23 @@ def main():
         "config": {"workload": "single vortex %dx%d, eps=%g, tau=0.8, U=0.02, period T=%g steps, %s storage"
                                % (n, n, args.eps, args.period, args.precision),
                    "grid": n, "precision": args.precision, "launch": main_run["launch"]},
-        "roofline": {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": round(achieved / HBM_PEAK_GBS, 4),
-                     "traffic": None if traffic is None else round(traffic, 0),
-                     "algorithmic_bytes_per_launch": alg_bytes,
-                     "steps_per_launch": spl,
-                     "launch_ms": round(launch_ms, 4),
-                     "bytes_per_node_per_step": main_run["bytes_per_node"] / spl,
-                     "pattern_copy_gbs": round(alg_bytes / (main_run["copy_us"] * 1e-6) / 1e9, 1),
-                     "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / launch_ms, 4)},
+        "roofline": dict(
+            ({"bound": "alu", "achieved": round(alu_achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
+              "frac": round(alu_achieved / ALU_PEAK_TOPS, 4)} if alu_bound else
+             {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+              "frac": round(achieved / HBM_PEAK_GBS, 4)}),
+            traffic=None if traffic is None else round(traffic, 0),
+            steps_per_launch=spl, launch_ms=round(launch_ms, 4),
+            hbm={"achieved_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                 "algorithmic_bytes_per_launch": alg_bytes,
+                 "bytes_per_node_per_step": main_run["bytes_per_node"] / spl,
+                 "pattern_copy_gbs": round(copy_gbs, 1),
+                 "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / launch_ms, 4),
+                 "measured_frac_of_pattern_copy": None if hbm_practical_frac is None else round(hbm_practical_frac, 4)},
+            alu={"ops_per_node_update": OPS_PER_NODE_UPDATE, "achieved_tops": round(alu_achieved, 2),
+                 "peak_tops": round(ALU_PEAK_TOPS, 2), "frac": round(alu_achieved / ALU_PEAK_TOPS, 4),
+                 "valu_instructions_per_launch": valu,
+                 "valu_issue_frac": None if valu_issue_frac is None else round(valu_issue_frac, 4)}),
         "one_step_kernel": one_step,
         "shape_error": {"t": main_run["t_end"], "e2": main_run["e2"], "e1": main_run["e1"],
                         "mass_drift": main_run["mass_drift"]},
