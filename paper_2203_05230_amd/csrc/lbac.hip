@@ -212,25 +212,27 @@ hipError_t launch_step_bx(StepArgs a, int variant, int bx, hipStream_t s) {
 }
 
 template <typename R, int ST>
-hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant) {
+hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant, int bx) {
     if (h->p.model == LBAC_MODEL_CONVENTIONAL)
-        return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, variant, h->bx, h->stream);
-    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, variant, h->bx, h->stream);
+        return launch_step_bx<R, ST, MODEL_CONVENTIONAL>(a, variant, bx, h->stream);
+    return launch_step_bx<R, ST, MODEL_IMPROVED>(a, variant, bx, h->stream);
 }
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
-    // one-step launches of the S-step variants use the deep block kernel
+    // one-step launches of the S-step variants use the deep block kernel, at a
+    // tile width it has (192 and 320 exist for the S-step kernels only)
     const int var1 =
         h->variant == LBAC_KERNEL_FUSED2 || h->variant == LBAC_KERNEL_FUSED3 ? LBAC_KERNEL_BLOCK_DEEP : h->variant;
+    const int bx1 = h->bx == 192 || h->bx == 320 ? 256 : h->bx;
     if (h->closure) {
         // FP32 plain storage.  The block variants write the band masks; then the
         // band list is rebuilt and the correction pass adds the network's flux
         // correction at the listed nodes.
         const int variant = var1 == LBAC_KERNEL_WAVE ? LBAC_KERNEL_BLOCK : var1;
         const hipError_t e = h->p.model == LBAC_MODEL_CONVENTIONAL
-                                 ? launch_step_bx<float, ST_PLAIN, MODEL_CONVENTIONAL>(a, variant, h->bx, h->stream)
-                                 : launch_step_bx<float, ST_PLAIN, MODEL_IMPROVED>(a, variant, h->bx, h->stream);
+                                 ? launch_step_bx<float, ST_PLAIN, MODEL_CONVENTIONAL>(a, variant, bx1, h->stream)
+                                 : launch_step_bx<float, ST_PLAIN, MODEL_IMPROVED>(a, variant, bx1, h->stream);
         if (e != hipSuccess) return e;
         const int64_t nwords = (int64_t)h->p.ny * h->cl_words;
         hipLaunchKernelGGL(closure_reset_kernel, dim3(1), dim3(64), 0, h->stream, h->cl_count);
@@ -242,13 +244,13 @@ hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     }
     switch (h->p.precision) {
     case LBAC_F64:
-        return launch_step_m<double, ST_PLAIN>(h, a, var1);
+        return launch_step_m<double, ST_PLAIN>(h, a, var1, bx1);
     case LBAC_F32:
-        return launch_step_m<float, ST_PLAIN>(h, a, var1);
+        return launch_step_m<float, ST_PLAIN>(h, a, var1, bx1);
     case LBAC_F32_F16STORE:
-        return launch_step_m<float, ST_F16>(h, a, var1);
+        return launch_step_m<float, ST_F16>(h, a, var1, bx1);
     default:
-        return launch_step_m<float, ST_BF16>(h, a, var1);
+        return launch_step_m<float, ST_BF16>(h, a, var1, bx1);
     }
 }
 
@@ -271,6 +273,12 @@ hipError_t launch_stepS_m(StepArgs a, int bx, hipStream_t s) {
         break;
     case 128:
         hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 128, S>), grid, dim3(block_threads<128>()), 0, s, a);
+        break;
+    case 192:
+        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 192, S>), grid, dim3(block_threads<192>()), 0, s, a);
+        break;
+    case 320:
+        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 320, S>), grid, dim3(block_threads<320>()), 0, s, a);
         break;
     default:
         hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 256, S>), grid, dim3(block_threads<256>()), 0, s, a);
@@ -693,7 +701,9 @@ int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (variant < LBAC_KERNEL_BLOCK || variant > LBAC_KERNEL_FUSED3) return fail(h, LBAC_EINVAL, "unknown kernel variant");
     if ((variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3) && h->p.precision != LBAC_F32)
         return fail(h, LBAC_EINVAL, "the multi-step variants need LBAC_F32 storage");
-    if (bx != 64 && bx != 128 && bx != 256) return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256");
+    const bool multi = variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3;
+    if (bx != 64 && bx != 128 && bx != 256 && !(multi && (bx == 192 || bx == 320)))
+        return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256 (or 192, 320 with the multi-step variants)");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
     h->bx = bx;
@@ -713,7 +723,7 @@ int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h
 int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     if (!h || steps < 1) return LBAC_EINVAL;
     DeviceGuard g(h->device);
-    const int bxs[3] = {64, 128, 256};
+    const int bxs[5] = {64, 128, 192, 256, 320};
     // strip heights: powers of two, and ny split into k equal strips (so that a
     // grid whose tiles all fit on the device at once marches long strips in step)
     std::vector<int> hs;
@@ -732,6 +742,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
+        if ((bx == 192 || bx == 320) && var != LBAC_KERNEL_FUSED2 && var != LBAC_KERNEL_FUSED3) continue;
         for (int sh : hs) {
             h->variant = var;
             h->bx = bx;

@@ -29,6 +29,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 namespace lbac {
 
 // ---------------------------------------------------------------------------
@@ -696,8 +698,10 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     NodeConst<float> kcs[S];  // stage k at time t + k
 #pragma unroll
     for (int k = 0; k < S; ++k) kcs[k] = NodeConst<float>(a, t + k);
-    float fprev[S][9], fcur[S][9], ob[9];
-    float phiprev[S], phicur[S];
+    // pulled populations and phi of stage k, ping-pong by iteration parity:
+    // the pull of iteration it fills half it & 1, the update of iteration
+    // it + 1 reads it
+    float fp[S][2][9], ph[S][2], ob[9];
     float phi_out = 0.f;
     // Histories, index = age in iterations (0: this iteration).  P[k]: the sum
     // of stage k's input populations at the own node (phi(t + k - 1) as the
@@ -706,9 +710,12 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     float P[S][4], z0[S][4], zo[S][4], zn[S][4];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        phiprev[k] = phicur[k] = 0.f;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) fprev[k][q] = fcur[k][q] = 0.f;
+        for (int b = 0; b < 2; ++b) {
+            ph[k][b] = 0.f;
+#pragma unroll
+            for (int q = 0; q < 9; ++q) fp[k][b][q] = 0.f;
+        }
 #pragma unroll
         for (int d = 0; d < 4; ++d) P[k][d] = z0[k][d] = zo[k][d] = zn[k][d] = 0.f;
     }
@@ -737,9 +744,10 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
         zo[k][0] = down ? v[4] : v[2];
         zn[k][0] = down ? v[2] : v[4];
     };
-    auto body = [&](const int it, float(&nv)[9]) __attribute__((always_inline)) {
+    auto body = [&](const int it, float(&nv)[9], auto parity) __attribute__((always_inline)) {
+        constexpr int B = decltype(parity)::value;  // it & 1
         const int Rr = raw_row(it);
-        const int s3 = it % 3, s2 = it & 1;
+        const int s3 = it % 3, s2 = B;
         // ---- row R into stage 0's ring
         put(0, s3, s2, nv);
         io.load(row_of(it + 2) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
@@ -754,11 +762,11 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
             const int lag = k == 0 ? 0 : 1;
             if (it >= 5 * k + 2 && pk[k]) {
                 const int so = (it + 1 + 2 * lag) % 3;  // old pair: it - 2 - lag
-                const int sm = (it + 1 + lag) & 1;      // populations 1, 3: it - 1 - lag
+                const int sm = B ^ 1 ^ lag;             // populations 1, 3: it - 1 - lag
                 const float o0 = lds.ro[k][so][0][j - 1], o1 = lds.ro[k][so][1][j + 1];
                 const float n0 = lds.rn[k][0][j - 1], n1 = lds.rn[k][1][j + 1];
                 const float zo_ = zo[k][2 + lag], zn_ = zn[k][lag];
-                float f[9];
+                float(&f)[9] = fp[k][B];
                 f[0] = z0[k][1 + lag];
                 f[1] = lds.rm[k][sm][0][j - 1];
                 f[2] = down ? zn_ : zo_;
@@ -770,11 +778,8 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                 f[8] = down ? o0 : n0;
                 float s = 0.f;
 #pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    fcur[k][q] = f[q];
-                    s += f[q];
-                }
-                phicur[k] = s;
+                for (int q = 0; q < 9; ++q) s += f[q];
+                ph[k][B] = s;
                 lds.ps[k][s3][j] = normal_source<float, MODEL>(s, kcs[k]);
             }
         }
@@ -798,13 +803,13 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                 float gx, gy, Gx, Gy;
                 iso_gradient(ps[c0][j + 1], ps[c0][j - 1], ps[cp][j], ps[cm][j], ps[cp][j + 1], ps[cp][j - 1],
                              ps[cm][j + 1], ps[cm][j - 1], gx, gy);
-                const float phi = phiprev[k];
+                const float phi = ph[k][B ^ 1];
                 const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
                 const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
                 const float phio = P[k][k == 0 ? 2 : 3];
                 flux_bracket<float, MODEL>(gx, gy, phi, kc.first ? phi : phio, kc.s_now * uxr, kc.s_now * uyr,
                                            kc.s_old * uxr, kc.s_old * uyr, kc, Gx, Gy);
-                collide(fprev[k], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
+                collide(fp[k][B ^ 1], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
                 if (last)
                     phi_out = phi;
                 else
@@ -812,12 +817,9 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
             }
         }
         io.store(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + l), ob, phi_out);
-        // ---- age everything by one iteration
+        // ---- age the histories by one iteration
 #pragma unroll
         for (int k = 0; k < S; ++k) {
-#pragma unroll
-            for (int q = 0; q < 9; ++q) fprev[k][q] = fcur[k][q];
-            phiprev[k] = phicur[k];
 #pragma unroll
             for (int d = 3; d > 0; --d) {
                 P[k][d] = P[k][d - 1];
@@ -833,8 +835,8 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     io.load(row_of(0) * (uint32_t)a.pitch + (uint32_t)gcol, na);
     io.load(row_of(1) * (uint32_t)a.pitch + (uint32_t)gcol, nb);
     for (int it = 0; it < iters; it += 2) {
-        body(it, na);
-        if (it + 1 < iters) body(it + 1, nb);
+        body(it, na, std::integral_constant<int, 0>{});
+        if (it + 1 < iters) body(it + 1, nb, std::integral_constant<int, 1>{});
     }
 }
 

@@ -39,7 +39,8 @@ def test_bitwise_equal_to_one_step_kernels(gpu_lib, model, variant):
     case = {**W.single_vortex_case(320, U=0.05, period_T=100.0), "model": model}
     phi0 = W.circle(320, 1.0)
     base = run(gpu_lib, case, phi0, 13, (256, 64, 0)).phi()
-    for bx, strip in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17), (128, 2), (256, 3)):
+    for bx, strip in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17), (128, 2), (256, 3), (192, 40), (320, 7),
+                      (192, 1), (320, 320)):
         phi = run(gpu_lib, case, phi0, 13, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -52,7 +53,7 @@ def test_ragged_and_degenerate_grids(gpu_lib, nx, ny, variant):
     rng = np.random.default_rng(nx * 1000 + ny)
     phi0 = W.circle(max(nx, ny), 1.5, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
     base = run(gpu_lib, case, phi0, 11, (64, 7, 0)).phi()
-    for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2)):
+    for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2), (192, 3), (320, 5)):
         phi = run(gpu_lib, case, phi0, 11, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -125,6 +126,24 @@ def test_needs_fp32_storage(gpu_lib, prec):
     with pytest.raises(gpu_lib.LbacError):
         sim.set_launch(128, 16, 5)
     sim.close()
+
+
+def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
+    """192- and 320-column tiles exist for the multi-step kernels; the
+    one-step launches such a context makes (a remainder, or with the closure
+    on) use 256-column tiles, bit for bit the same."""
+    case = W.single_vortex_case(200, U=0.05, period_T=100.0)
+    phi0 = W.circle(200, 1.0)
+    sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+    for variant in (0, 1, 2):
+        for bx in (192, 320):
+            with pytest.raises(gpu_lib.LbacError):
+                sim.set_launch(bx, 16, variant)
+    sim.close()
+    base = run(gpu_lib, case, phi0, 7, (256, 16, 0)).phi()
+    for bx in (192, 320):
+        for variant in VARIANTS:
+            assert np.array_equal(run(gpu_lib, case, phi0, 7, (bx, 16, variant)).phi(), base), (bx, variant)
 
 
 @pytest.mark.parametrize("variant,steps", [(FUSED2, 2), (FUSED3, 3), (0, 1)])
