@@ -212,10 +212,13 @@ void* lbac_stream(lbac_ctx* h);
 /* ---- batched form --------------------------------------------------------
  * Many independent lattices (instances) of uneven sizes and parameters
  * advanced together by ONE persistent kernel launch, replayed from a captured
- * HIP graph.  Work is split into (instance, 60-column block, strip) items
- * assigned to resident workgroups longest-first; an item waits for its eight
- * neighbours of the previous step through per-item progress counters (no
- * grid-wide barrier), so instances retire independently.  Every instance uses
+ * HIP graph.  Work is split into (instance, 128-column block, strip) items
+ * assigned to resident workgroups longest-first.  An item takes three steps
+ * per pass (the populations between them kept in LDS, as with
+ * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes) and
+ * waits for its eight neighbours of the previous pass through per-item
+ * progress counters (no grid-wide barrier), so instances retire
+ * independently.  Every instance uses
  * FP32 collide and storage and the improved model; results are bitwise those
  * of lbac_step on the same instance.  Requires the GPU to itself (all
  * workgroups resident); a wait that exceeds the time-out makes every
@@ -240,7 +243,7 @@ int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
 int lbac_batch_count(lbac_batch* b, int32_t* count);
 
-/* Strip height (rows per item, >= 2) and workgroup count (0: the occupancy
+/* Strip height (rows per item, >= 8) and workgroup count (0: the occupancy
  * limit, which is also the maximum). */
 int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups);
 int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, int32_t* max_workgroups);
@@ -251,7 +254,7 @@ int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, i
 int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms);
 
 /* Time-out of one dependency wait (default 20 s).  test_stall != 0 makes
- * every wait ask for a step that never completes, so that the time-out path
+ * every wait ask for a pass that never completes, so that the time-out path
  * can be tested: each workgroup exits after `seconds`. */
 int lbac_batch_set_timeout(lbac_batch* b, double seconds, int32_t test_stall);
 const char* lbac_batch_last_error(lbac_batch* b);

@@ -2,7 +2,7 @@
 // launch, replayed from a captured HIP graph (see batch_kernel in
 // lbac_kernels.hpp for the dependency protocol).
 //
-// Host side: the work list of (instance, 60-column block, strip) items, a
+// Host side: the work list of (instance, 128-column block, strip) items, a
 // longest-processing-time-first assignment of items to workgroups (work =
 // nodes x steps), occupancy-limited workgroup count so that every workgroup
 // is resident, graph capture of reset -> persistent kernel -> time advance,
@@ -21,12 +21,16 @@
 using namespace lbac;
 using namespace lbac_host;
 
+// rows per strip at least: a pass reads kBatchGrow rows beyond its strip on
+// each side, and the neighbour lists hold at most four strips per axis
+constexpr int kBatchMinStrip = kBatchGrow + 2;
+
 struct lbac_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<lbac_ctx*> inst;
-    int strip_h = 32;
+    int strip_h = 32;  // >= kBatchMinStrip
     int wgs = 0;        // 0: occupancy limit
     int max_wgs = 0;    // occupancy limit (resident workgroups)
     double ticks_per_s = 1e8;
@@ -99,9 +103,10 @@ void release(lbac_batch* b) {
 
 // Work items and their neighbour lists for the current strip height.  The
 // neighbours of an item are the items whose tiles overlap its read region,
-// columns x0-2 .. x0+w+1 and rows ys-2 .. ys+hh+1 (periodic).
+// columns x0-G .. x0+w-1+G and rows ys-G .. ys+hh-1+G (G = kBatchGrow,
+// periodic).
 void build_items(lbac_batch* b) {
-    constexpr int W = kTileW;
+    constexpr int W = kBatchTile, G = kBatchGrow;
     b->items.clear();
     b->item_nodes.clear();
     for (int k = 0; k < (int)b->inst.size(); ++k) {
@@ -114,8 +119,8 @@ void build_items(lbac_batch* b) {
             for (int i = 0; i < nbx; ++i) {
                 const int w = std::min(W, nx - i * W), h = std::min(sh, ny - j * sh);
                 std::vector<int> tx, ty;
-                for (int cx = i * W - 2; cx <= i * W + w + 1; ++cx) tx.push_back(((cx % nx) + nx) % nx / W);
-                for (int ry = j * sh - 2; ry <= j * sh + h + 1; ++ry) ty.push_back(((ry % ny) + ny) % ny / sh);
+                for (int cx = i * W - G; cx <= i * W + w - 1 + G; ++cx) tx.push_back(((cx % nx) + nx) % nx / W);
+                for (int ry = j * sh - G; ry <= j * sh + h - 1 + G; ++ry) ty.push_back(((ry % ny) + ny) % ny / sh);
                 std::sort(tx.begin(), tx.end());
                 tx.erase(std::unique(tx.begin(), tx.end()), tx.end());
                 std::sort(ty.begin(), ty.end());
@@ -129,7 +134,8 @@ void build_items(lbac_batch* b) {
                 it.bxi = i;
                 it.syi = j;
                 it.down = j & 1;
-                // at most 4 tiles per axis (only the last tile or strip can be narrower than two)
+                // at most 4 tiles per axis (strips are at least G + 2 rows high and
+                // tiles 128 columns wide; only the last tile or strip can be narrower)
                 for (int m = 0; m < 16; ++m) it.nbr[m] = nb.empty() ? base + j * nbx + i : nb[m % nb.size()];
                 b->items.push_back(it);
                 b->item_nodes.push_back((int64_t)w * h);
@@ -185,12 +191,23 @@ int capture(lbac_batch* b) {
     drop_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const int count = (int)b->inst.size();
+    // full passes, then (counters reset, error flag kept) the one-step passes
     hipLaunchKernelGGL(batch_reset_kernel, dim3((b->nitems + 255) / 256), dim3(256), 0, b->stream, b->d_done,
-                       b->nitems, b->d_ctl);
+                       b->nitems, b->d_ctl, 1);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_kernel<MODEL_IMPROVED>, dim3(b->nwg), dim3(kBatchBX), 0, b->stream, b->d_inst,
-                           b->d_items, b->d_wg_off, b->d_wg_items, b->d_done, b->d_ctl);
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3(b->nwg), dim3(block_threads<kBatchTile>()), 0,
+                           b->stream, b->d_inst, b->d_items, b->d_wg_off, b->d_wg_items, b->d_done, b->d_ctl);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL(batch_reset_kernel, dim3((b->nitems + 255) / 256), dim3(256), 0, b->stream, b->d_done,
+                           b->nitems, b->d_ctl, 0);
+        e = hipGetLastError();
+    }
+    if (e == hipSuccess) {
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3(b->nwg), dim3(block_threads<kBatchTile>()), 0,
+                           b->stream, b->d_inst, b->d_items, b->d_wg_off, b->d_wg_items, b->d_done, b->d_ctl);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -216,12 +233,13 @@ int capture(lbac_batch* b) {
 // state and write the scratch buffer (state and time untouched).
 int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
     const int count = (int)b->inst.size();
-    int64_t max_steps = 0;
+    int64_t max_full = 0, max_rest = 0;
     for (int k = 0; k < count; ++k) {
         if (nsteps[k] < 0 || nsteps[k] > (int64_t)INT32_MAX) return bfail(b, LBAC_EINVAL, "step count out of range");
-        max_steps = std::max(max_steps, nsteps[k]);
+        max_full = std::max(max_full, nsteps[k] / kBatchS);
+        max_rest = std::max(max_rest, nsteps[k] % kBatchS);
     }
-    if (b->strip_h < 2) return bfail(b, LBAC_EINVAL, "strip height must be >= 2");
+    if (b->strip_h < kBatchMinStrip) return bfail(b, LBAC_EINVAL, "strip height too small");
     build_items(b);
     const int nwg = std::max(1, std::min(b->wgs > 0 ? std::min(b->wgs, b->max_wgs) : b->max_wgs, b->nitems));
     b->nwg = nwg;
@@ -231,17 +249,23 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
     lpt(b, nsteps, nwg, off, list);
     for (int k = 0; k < count; ++k) {
         lbac_ctx* c = b->inst[k];
+        // even passes read pop[cur] and write the other buffer, odd passes the
+        // reverse (a dry run reads pop[cur] on every pass)
         StepArgs a = make_args(c, c->cur, 0);
         a.strip_h = std::min(b->strip_h, c->p.ny);
-        b->h_inst[k].a = a;
-        b->h_inst[k].nsteps = nsteps[k];
+        StepArgs o = make_args(c, dry ? c->cur : c->cur ^ 1, 0);
+        o.strip_h = a.strip_h;
+        b->h_inst[2 * k].a = a;
+        b->h_inst[2 * k + 1].a = o;
+        b->h_inst[2 * k].nsteps = b->h_inst[2 * k + 1].nsteps = nsteps[k];
     }
-    b->h_ctl->max_steps = max_steps;
+    b->h_ctl->max_full = max_full;
+    b->h_ctl->max_rest = max_rest;
     b->h_ctl->timeout_ticks = (int64_t)(b->timeout_s * b->ticks_per_s);
     b->h_ctl->dry = dry ? 1 : 0;
     b->h_ctl->err = 0;
     b->h_ctl->test_stall = b->test_stall;
-    BHIP(b, hipMemcpyAsync(b->d_inst, b->h_inst, sizeof(BatchInst) * count, hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_inst, b->h_inst, sizeof(BatchInst) * 2 * count, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_items, b->items.data(), sizeof(BatchItem) * b->nitems, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_wg_items, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, b->stream));
@@ -266,7 +290,7 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
     if (b->h_ctl->err) return bfail(b, LBAC_EDEVICE, "batch schedule stalled: a dependency wait timed out");
     if (!dry)
         for (int k = 0; k < count; ++k) {
-            b->inst[k]->cur ^= (int)(nsteps[k] & 1);
+            b->inst[k]->cur ^= (int)(batch_passes(nsteps[k]) & 1);  // one buffer swap per pass
             b->inst[k]->t += nsteps[k];
         }
     return LBAC_OK;
@@ -309,17 +333,19 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         b->inst[k] = c;
     }
     int per_cu = 0, cus = 0, khz = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<MODEL_IMPROVED>, kBatchBX, 0) !=
+    // the multi-step launch has the lower occupancy; both launches use its grid
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<MODEL_IMPROVED, kBatchS>,
+                                                     block_threads<kBatchTile>(), 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
         return bail(LBAC_EDEVICE);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) == hipSuccess && khz > 0)
         b->ticks_per_s = 1000.0 * khz;
     b->max_wgs = std::max(1, per_cu * cus);
-    if (hipMalloc(&b->d_inst, sizeof(BatchInst) * count) != hipSuccess ||
+    if (hipMalloc(&b->d_inst, sizeof(BatchInst) * 2 * count) != hipSuccess ||
         hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess ||
         hipHostMalloc((void**)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&b->h_inst, sizeof(BatchInst) * count, hipHostMallocDefault) != hipSuccess)
+        hipHostMalloc((void**)&b->h_inst, sizeof(BatchInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
         return bail(LBAC_ENOMEM);
     std::memset(b->h_ctl, 0, sizeof(BatchCtl));
     *out = b;
@@ -354,7 +380,7 @@ int lbac_batch_count(lbac_batch* b, int32_t* count) {
 
 int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups) {
     if (!b) return LBAC_EINVAL;
-    if (strip_h < 2) return bfail(b, LBAC_EINVAL, "strip height must be >= 2");
+    if (strip_h < kBatchMinStrip) return bfail(b, LBAC_EINVAL, "strip height must be >= 8");
     if (workgroups < 0) return bfail(b, LBAC_EINVAL, "workgroups must be >= 0 (0: occupancy limit)");
     b->strip_h = strip_h;
     b->wgs = workgroups;
@@ -375,7 +401,7 @@ int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms) {
     const int count = (int)b->inst.size();
     std::vector<int64_t> ns(count, steps);
     const int keep_h = b->strip_h, keep_w = b->wgs;
-    const int hs[5] = {8, 16, 32, 48, 64};
+    const int hs[7] = {16, 32, 64, 96, 128, 192, 256};
     const int fr[3] = {4, 3, 2};  // workgroups = max * fr / 4
     float best = 1e30f;
     int best_h = keep_h, best_w = keep_w;

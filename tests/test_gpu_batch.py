@@ -59,7 +59,7 @@ def test_batch_bitwise_equals_single_instances(gpu_lib):
     b.close()
 
 
-@pytest.mark.parametrize("strip_h,wgs", [(2, 0), (7, 5), (32, 1), (64, 0)])
+@pytest.mark.parametrize("strip_h,wgs", [(8, 0), (9, 5), (32, 1), (64, 0), (128, 3)])
 def test_batch_shapes_and_continuation(gpu_lib, strip_h, wgs):
     say("case: batch shape", strip_h, wgs)
     cases, phis, steps = mixed_cases()
@@ -119,6 +119,14 @@ def test_batch_seeded_list_subset(gpu_lib):
     b.run(steps)
     for k in (0, 5, 6, 11):
         assert np.array_equal(b.instance(k).phi(), single(gpu_lib, cases[k], phis[k], steps[k])), k
+    b.close()
+
+
+def test_batch_rejects_short_strips(gpu_lib):
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases[:2], phis[:2])
+    with pytest.raises(gpu_lib.LbacError):
+        b.set_shape(7, 0)
     b.close()
 
 
