@@ -16,6 +16,7 @@
 #include <string>
 #include <vector>
 
+#include "lbac_batch_kernels.hpp"
 #include "lbac_internal.hpp"
 
 using namespace lbac;
