@@ -206,6 +206,28 @@ def closure_leg(lbac, torch, case, phi0, steps, theta=0.02):
                 band_fraction=band / n, mac_per_band_node=5824, theta=theta)
 
 
+def c2_leg(lbac, torch, W, n, steps):
+    """The 1024^2 single vortex (R = 0.15 n at (0.5 n, 0.75 n), tau 0.8, U
+    0.02, period = `steps`) at eps 0.5 and 1 with FP32, FP16 and BF16 shifted
+    storage, each over one full period from phi0: MLUPS, E1 and E2 against
+    phi0 at t = T, mass drift, and E2 of each 16-bit form relative to FP32.
+    The state (75 MB for FP32) stays in the 256 MB last-level cache, so these
+    rates are not HBM rates."""
+    out = {}
+    for eps in (0.5, 1.0):
+        case = W.single_vortex_case(n, eps=eps, tau=0.8, U=0.02, period_T=float(steps))
+        phi0 = W.circle(n, eps)
+        runs = {}
+        for prec in ("f32", "f32_f16store", "f32_bf16store"):
+            r = run_form(lbac, torch, case, phi0, prec, steps, 64, autotune=True)
+            runs[prec] = dict(mlups=round(n * n * steps / (r["ms_total"] * 1e-3) / 1e6, 1), e2=r["e2"], e1=r["e1"],
+                              mass_drift=r["mass_drift"], launch=r["launch"])
+        for prec in ("f32_f16store", "f32_bf16store"):
+            runs[prec]["e2_vs_f32"] = runs[prec]["e2"] / runs["f32"]["e2"]
+        out["eps=%g" % eps] = runs
+    return dict(grid=n, steps=steps, **out)
+
+
 def leg_3d(lbac, torch, W, n, steps, launch=None):
     """The D3Q19 form on an n^3 ball in the deformation field (FP32 storage),
     launch shape autotuned (or given); timed on the library's stream."""
@@ -274,6 +296,8 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
+    ap.add_argument("--c2-steps", type=int, default=16384,
+                    help="steps (= period) of the 1024^2 storage-form comparison (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
     ap.add_argument("--one-step-steps", type=int, default=512,
                     help="steps of the one-step kernel timed for comparison when the two-step kernel runs (0: skip)")
@@ -366,6 +390,10 @@ def main():
         print("bench: closure", file=sys.stderr, flush=True)
         closure = closure_leg(lbac, torch, case, phi0, args.closure_steps)
     d3 = None
+    c2 = None
+    if args.c2_steps > 0:
+        print("bench: 1024^2 storage forms, %d steps" % args.c2_steps, file=sys.stderr, flush=True)
+        c2 = c2_leg(lbac, torch, W, 1024, args.c2_steps)
     if args.grid3d > 0:
         print("bench: 3-D form %d^3" % args.grid3d, file=sys.stderr, flush=True)
         launch3d = tuple(int(v) for v in args.launch3d.split(",")) if args.launch3d else None
@@ -414,6 +442,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "closure": closure,
+        "c2_1024": c2,
         "d3q19": d3,
         "cpu_baseline": cpu,
     }
