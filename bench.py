@@ -365,7 +365,8 @@ def main():
         # the same launch shape with the one-step kernel, for comparison
         print("bench: one-step kernel", file=sys.stderr, flush=True)
         lb = main_run["launch"]
-        r1 = run_form(lbac, torch, case, phi0, args.precision, args.one_step_steps, 0, launch=(lb[0], lb[1], 2))
+        bx1 = lb[0] if lb[0] in (64, 128, 256) else 256  # tile widths the one-step kernel has
+        r1 = run_form(lbac, torch, case, phi0, args.precision, args.one_step_steps, 0, launch=(bx1, lb[1], 2))
         ms1 = r1["ms_total"] / args.one_step_steps
         one_step = dict(launch=r1["launch"], steps=args.one_step_steps, ms_per_step=round(ms1, 4),
                         mlups=round(nodes / (ms1 * 1e-3) / 1e6, 1),
