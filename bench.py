@@ -81,7 +81,7 @@ def measured_valu_instructions(launch):
     return _counter_summary(SQ_FILE, "valu_instructions_per_launch", launch)
 
 
-def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False):
+def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False, graph=0):
     # a stream of our own: the library works on it and the events are recorded
     # on it (torch's default stream has handle 0, which the library would
     # replace by a private stream)
@@ -102,6 +102,8 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     # timed run from the initial field
     sim = lbac.Simulation(c, phi0, stream=stream.cuda_stream)
     sim.set_launch(*launch)
+    if graph:
+        sim.set_graph_chunk(graph)
     m0 = sim.mass()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -212,20 +214,33 @@ def c2_leg(lbac, torch, W, n, steps):
     storage, each over one full period from phi0: MLUPS, E1 and E2 against
     phi0 at t = T, mass drift, and E2 of each 16-bit form relative to FP32.
     The state (75 MB for FP32) stays in the 256 MB last-level cache, so these
-    rates are not HBM rates."""
+    rates are not HBM rates; the steps are replayed from captured HIP graphs
+    of 96 steps."""
     out = {}
     for eps in (0.5, 1.0):
         case = W.single_vortex_case(n, eps=eps, tau=0.8, U=0.02, period_T=float(steps))
         phi0 = W.circle(n, eps)
         runs = {}
         for prec in ("f32", "f32_f16store", "f32_bf16store"):
-            r = run_form(lbac, torch, case, phi0, prec, steps, 64, autotune=True)
+            r = run_form(lbac, torch, case, phi0, prec, steps, 64, autotune=True, graph=96)
             runs[prec] = dict(mlups=round(n * n * steps / (r["ms_total"] * 1e-3) / 1e6, 1), e2=r["e2"], e1=r["e1"],
                               mass_drift=r["mass_drift"], launch=r["launch"])
         for prec in ("f32_f16store", "f32_bf16store"):
             runs[prec]["e2_vs_f32"] = runs[prec]["e2"] / runs["f32"]["e2"]
         out["eps=%g" % eps] = runs
     return dict(grid=n, steps=steps, **out)
+
+
+def c1_leg(lbac, torch, W, steps):
+    """The 64^2 single vortex in FP64 (R = 9.6 at (32, 48), eps 1, tau 0.8, U
+    0.02, period = `steps`), the parity configuration, over one period from
+    phi0: E1, E2 and mass drift at t = T, and MLUPS with the steps replayed
+    from captured HIP graphs of 100 steps (4096 nodes per step: launch-bound)."""
+    case = W.single_vortex_case(64, eps=1.0, tau=0.8, U=0.02, period_T=float(steps))
+    phi0 = W.circle(64, 1.0)
+    r = run_form(lbac, torch, case, phi0, "f64", steps, 0, autotune=False, graph=100)
+    return dict(grid=64, steps=steps, precision="f64", mlups=round(64 * 64 * steps / (r["ms_total"] * 1e-3) / 1e6, 1),
+                e2=r["e2"], e1=r["e1"], mass_drift=r["mass_drift"], launch=r["launch"])
 
 
 def leg_3d(lbac, torch, W, n, steps, launch=None):
@@ -296,6 +311,7 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
+    ap.add_argument("--c1-steps", type=int, default=2000, help="steps (= period) of the 64^2 FP64 run (0: skip)")
     ap.add_argument("--c2-steps", type=int, default=16384,
                     help="steps (= period) of the 1024^2 storage-form comparison (0: skip)")
     ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
@@ -391,6 +407,10 @@ def main():
         print("bench: closure", file=sys.stderr, flush=True)
         closure = closure_leg(lbac, torch, case, phi0, args.closure_steps)
     d3 = None
+    c1 = None
+    if args.c1_steps > 0:
+        print("bench: 64^2 FP64, %d steps" % args.c1_steps, file=sys.stderr, flush=True)
+        c1 = c1_leg(lbac, torch, W, args.c1_steps)
     c2 = None
     if args.c2_steps > 0:
         print("bench: 1024^2 storage forms, %d steps" % args.c2_steps, file=sys.stderr, flush=True)
@@ -443,6 +463,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "closure": closure,
+        "c1_64": c1,
         "c2_1024": c2,
         "d3q19": d3,
         "cpu_baseline": cpu,
