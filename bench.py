@@ -234,11 +234,12 @@ def c2_leg(lbac, torch, W, n, steps):
 def c1_leg(lbac, torch, W, steps):
     """The 64^2 single vortex in FP64 (R = 9.6 at (32, 48), eps 1, tau 0.8, U
     0.02, period = `steps`), the parity configuration, over one period from
-    phi0: E1, E2 and mass drift at t = T, and MLUPS with the steps replayed
-    from captured HIP graphs of 100 steps (4096 nodes per step: launch-bound)."""
+    phi0: E1, E2 and mass drift at t = T, and MLUPS with the launch shape
+    autotuned and the steps replayed from captured HIP graphs of 100 steps
+    (4096 nodes per step: latency- and launch-bound)."""
     case = W.single_vortex_case(64, eps=1.0, tau=0.8, U=0.02, period_T=float(steps))
     phi0 = W.circle(64, 1.0)
-    r = run_form(lbac, torch, case, phi0, "f64", steps, 0, autotune=False, graph=100)
+    r = run_form(lbac, torch, case, phi0, "f64", steps, 0, autotune=True, graph=100)
     return dict(grid=64, steps=steps, precision="f64", mlups=round(64 * 64 * steps / (r["ms_total"] * 1e-3) / 1e6, 1),
                 e2=r["e2"], e1=r["e1"], mass_drift=r["mass_drift"], launch=r["launch"])
 
