@@ -276,9 +276,9 @@ def leg_3d(lbac, torch, W, n, steps, launch=None):
                 mass_drift=abs(m - phi0.sum()) / phi0.sum(), launch=list(launch))
 
 
-def cpu_baseline(phi0, case, steps):
-    """The FP64 oracle as it stands, on the host cores, for `steps` steps of the
-    same grid (a bounded sample of the workload)."""
+def _oracle_rate(case, phi0, steps):
+    """Seconds of stepping (set-up subtracted) of the FP64 oracle for `steps`
+    steps of `case`, with whatever OpenMP thread count this process has."""
     from oracle import lib as O
 
     p = O.Params(case["nx"], case["ny"], eps=case["eps"], tau=case["tau"], delta=case["delta"],
@@ -289,11 +289,54 @@ def cpu_baseline(phi0, case, steps):
     t1 = time.perf_counter()
     O.run(p, phi0, steps)
     t2 = time.perf_counter()
-    dt = (t2 - t1) - (t1 - t0)
+    return (t2 - t1) - (t1 - t0)
+
+
+def _single_core_child(spec):
+    """Child-process body of the single-core oracle leg: `spec` is "n,steps";
+    prints one JSON object.  Runs with OMP_NUM_THREADS=1 and touches no GPU."""
+    from paper_2203_05230_amd import workloads as W
+
+    n, steps = (int(v) for v in spec.split(","))
+    case = W.single_vortex_case(n, eps=1.0, tau=0.8, U=0.02, period_T=4096.0)
+    dt = _oracle_rate(case, W.circle(n, 1.0), steps)
+    print(json.dumps({"n": n, "steps": steps, "seconds": dt}), flush=True)
+
+
+def cpu_baseline(phi0, case, steps, single_core_n=2048, single_core_steps=4):
+    """The FP64 oracle as it stands, on the host cores, for `steps` steps of the
+    same grid (a bounded sample of the workload); plus the same oracle on one
+    core, in a child process, over `single_core_steps` steps of the same
+    vortex on a `single_core_n` grid (per-node rate; the grid still far exceeds
+    the caches)."""
+    dt = _oracle_rate(case, phi0, steps)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
-    return dict(value=case["nx"] * case["ny"] * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
-                sample="%d steps of the %dx%d single vortex (FP64 oracle, OpenMP over rows); %.1f s of "
-                "stepping, set-up time subtracted" % (steps, case["nx"], case["ny"], dt))
+    out = dict(value=case["nx"] * case["ny"] * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
+               sample="%d steps of the %dx%d single vortex (FP64 oracle, OpenMP over rows); %.1f s of "
+               "stepping, set-up time subtracted" % (steps, case["nx"], case["ny"], dt))
+    if single_core_steps > 0:
+        import subprocess
+
+        env = dict(os.environ, OMP_NUM_THREADS="1")
+        r = subprocess.run([sys.executable, os.path.abspath(__file__), "--cpu-single-core",
+                            "%d,%d" % (single_core_n, single_core_steps)],
+                           env=env, capture_output=True, text=True, timeout=600)
+        if r.returncode == 0:
+            sc = json.loads(r.stdout.strip().splitlines()[-1])
+            out["single_core"] = dict(
+                value=sc["n"] ** 2 * sc["steps"] / sc["seconds"] / 1e6, unit="MLUPS", cores=1,
+                sample="%d steps of the %dx%d single vortex, one OpenMP thread; %.1f s of stepping"
+                % (sc["steps"], sc["n"], sc["n"], sc["seconds"]))
+        else:
+            out["single_core"] = dict(error=r.stderr.strip().splitlines()[-1:] or ["exit %d" % r.returncode])
+    try:
+        with open("/proc/cpuinfo") as fh:
+            names = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
+        out["cpu_model"] = names[0] if names else None
+    except OSError:
+        out["cpu_model"] = None
+    out["host_cpus"] = os.cpu_count()
+    return out
 
 
 def main():
@@ -307,7 +350,8 @@ def main():
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--forms", default="f32_f16store,f32_bf16store",
                     help="extra storage forms timed on the same workload ('' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=2, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-single-core", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
@@ -324,6 +368,9 @@ def main():
                     help="only run a plain device-to-device copy of MIB MiB three times (reference kernel for "
                          "scaling HBM byte counters) and exit")
     args = ap.parse_args()
+    if args.cpu_single_core:
+        _single_core_child(args.cpu_single_core)
+        return
     if args.copy_calibration:
         import torch
 

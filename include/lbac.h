@@ -152,10 +152,13 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
  * launch takes S = 2 or 3 steps, the populations between them kept in LDS
  * (the block layout; step k of S is computed on the tile grown by
  * 2 (S - 1 - k) columns and rows on each side), so HBM is read and written
- * once per S steps; a step count that is not a multiple of S ends with
- * one-step launches, and with the closure on every step is a one-step
- * launch.  strip_h: rows each tile marches (>= 1).  Results do not depend on
- * the shape or variant (bitwise).  LBAC_EINVAL for unsupported values. */
+ * once per S steps; their tiles are bx = 64, 96, 128, ..., 320 columns (any
+ * multiple of 32 in that range), the block being the bx + 4S grown columns
+ * rounded up to whole wavefronts; a step count that is not a multiple of S
+ * ends with one-step launches (bx 256 where bx is not 64, 128 or 256), and
+ * with the closure on every step is a one-step launch.  strip_h: rows each
+ * tile marches (>= 1).  Results do not depend on the shape or variant
+ * (bitwise).  LBAC_EINVAL for unsupported values. */
 #define LBAC_KERNEL_BLOCK 0
 #define LBAC_KERNEL_WAVE 1
 #define LBAC_KERNEL_BLOCK_DEEP 2
@@ -164,9 +167,9 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h);
 int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h);
 
-/* Times every supported launch shape (variant; bx; strip_h among the powers
- * of two from 8 to 512 and ceil(ny / k) for k = 1..32) over `steps` launches
- * each (state is left unchanged) and keeps the fastest per step;
+/* Times every supported launch shape (variant; bx; strip_h among the
+ * multiples of 8 up to 256, 512 and ceil(ny / k) for k = 1..32) over `steps`
+ * launches each (state is left unchanged) and keeps the fastest per step;
  * *us_per_step (may be NULL) gets its time per step. */
 int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step);
 

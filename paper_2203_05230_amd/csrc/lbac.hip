@@ -218,13 +218,20 @@ hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant, int 
     return launch_step_bx<R, ST, MODEL_IMPROVED>(a, variant, bx, h->stream);
 }
 
+// Tile widths of the one-step block kernels.
+bool one_step_bx(int bx) { return bx == 64 || bx == 128 || bx == 256; }
+
+// Tile widths of the S-step kernels: multiples of 32 columns from 64 to 320,
+// so every tile row starts on a 128-byte line.
+bool stepS_bx(int bx) { return bx >= 64 && bx <= 320 && bx % 32 == 0; }
+
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
     // one-step launches of the S-step variants use the deep block kernel, at a
-    // tile width it has (192 and 320 exist for the S-step kernels only)
+    // tile width it has (the others exist for the S-step kernels only)
     const int var1 =
         h->variant == LBAC_KERNEL_FUSED2 || h->variant == LBAC_KERNEL_FUSED3 ? LBAC_KERNEL_BLOCK_DEEP : h->variant;
-    const int bx1 = h->bx == 192 || h->bx == 320 ? 256 : h->bx;
+    const int bx1 = one_step_bx(h->bx) ? h->bx : 256;
     if (h->closure) {
         // FP32 plain storage.  The block variants write the band masks; then the
         // band list is rebuilt and the correction pass adds the network's flux
@@ -261,30 +268,39 @@ int launch_steps_of(const lbac_ctx* h) {
     return h->variant == LBAC_KERNEL_FUSED2 ? 2 : (h->variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
 }
 
+// One S-step launch with tile width BX.
+template <int MODEL, int S, int BX>
+hipError_t launch_stepS_shape(StepArgs a, hipStream_t s) {
+    a.nbx = (a.nx + BX - 1) / BX;
+    const dim3 grid(a.nbx * a.nby);
+    hipLaunchKernelGGL((stepS_kernel_lds<MODEL, BX, S>), grid, dim3(stepS_threads<BX, S>()), 0, s, a);
+    return hipGetLastError();
+}
+
 template <int MODEL, int S>
 hipError_t launch_stepS_m(StepArgs a, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
-    a.nbx = (a.nx + bx - 1) / bx;
-    const dim3 grid(a.nbx * a.nby);
     switch (bx) {
     case 64:
-        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 64, S>), grid, dim3(block_threads<64>()), 0, s, a);
-        break;
+        return launch_stepS_shape<MODEL, S, 64>(a, s);
+    case 96:
+        return launch_stepS_shape<MODEL, S, 96>(a, s);
     case 128:
-        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 128, S>), grid, dim3(block_threads<128>()), 0, s, a);
-        break;
+        return launch_stepS_shape<MODEL, S, 128>(a, s);
+    case 160:
+        return launch_stepS_shape<MODEL, S, 160>(a, s);
     case 192:
-        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 192, S>), grid, dim3(block_threads<192>()), 0, s, a);
-        break;
+        return launch_stepS_shape<MODEL, S, 192>(a, s);
+    case 224:
+        return launch_stepS_shape<MODEL, S, 224>(a, s);
+    case 288:
+        return launch_stepS_shape<MODEL, S, 288>(a, s);
     case 320:
-        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 320, S>), grid, dim3(block_threads<320>()), 0, s, a);
-        break;
+        return launch_stepS_shape<MODEL, S, 320>(a, s);
     default:
-        hipLaunchKernelGGL((stepS_kernel_lds<MODEL, 256, S>), grid, dim3(block_threads<256>()), 0, s, a);
-        break;
+        return launch_stepS_shape<MODEL, S, 256>(a, s);
     }
-    return hipGetLastError();
 }
 
 // Steps k .. k + S - 1 of the current run in one launch, from pop[src] into pop[1 - src].
@@ -701,9 +717,10 @@ int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (variant < LBAC_KERNEL_BLOCK || variant > LBAC_KERNEL_FUSED3) return fail(h, LBAC_EINVAL, "unknown kernel variant");
     if ((variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3) && h->p.precision != LBAC_F32)
         return fail(h, LBAC_EINVAL, "the multi-step variants need LBAC_F32 storage");
-    const bool multi = variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3;
-    if (bx != 64 && bx != 128 && bx != 256 && !(multi && (bx == 192 || bx == 320)))
-        return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256 (or 192, 320 with the multi-step variants)");
+    const int S = variant == LBAC_KERNEL_FUSED2 ? 2 : (variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
+    if (!(S == 1 ? one_step_bx(bx) : stepS_bx(bx)))
+        return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256 (with the multi-step variants any multiple of 32 from "
+                                    "64 to 320)");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
     h->bx = bx;
@@ -723,11 +740,15 @@ int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h
 int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     if (!h || steps < 1) return LBAC_EINVAL;
     DeviceGuard g(h->device);
-    const int bxs[5] = {64, 128, 192, 256, 320};
-    // strip heights: powers of two, and ny split into k equal strips (so that a
-    // grid whose tiles all fit on the device at once marches long strips in step)
+    const int bxs[9] = {64, 96, 128, 160, 192, 224, 256, 288, 320};
+    // strip heights: multiples of 8 up to 256 and powers of two up to 512 (the
+    // count of tiles against the workgroups resident at once decides how full
+    // the last round of tiles is, so heights between the powers of two can
+    // win), and ny split into k equal strips (so that a grid whose tiles all
+    // fit on the device at once marches long strips in step)
     std::vector<int> hs;
-    for (int sh = 8; sh <= 512; sh *= 2) hs.push_back(std::min(sh, h->p.ny));
+    for (int sh = 8; sh <= 256; sh += 8) hs.push_back(std::min(sh, h->p.ny));
+    hs.push_back(std::min(512, h->p.ny));
     for (int k = 1; k <= 32; ++k) hs.push_back((h->p.ny + k - 1) / k);
     std::sort(hs.begin(), hs.end());
     hs.erase(std::unique(hs.begin(), hs.end()), hs.end());
@@ -741,8 +762,9 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     const int last_var = h->p.precision == LBAC_F32 && !h->closure ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
     for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
+        const int S = var == LBAC_KERNEL_FUSED2 ? 2 : (var == LBAC_KERNEL_FUSED3 ? 3 : 1);
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
-        if ((bx == 192 || bx == 320) && var != LBAC_KERNEL_FUSED2 && var != LBAC_KERNEL_FUSED3) continue;
+        if (S == 1 ? !one_step_bx(bx) : !stepS_bx(bx)) continue;
         for (int sh : hs) {
             h->variant = var;
             h->bx = bx;

@@ -107,8 +107,11 @@ __global__ __launch_bounds__(block_threads<kBatchTile>()) __attribute__((amdgpu_
             const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : p * kBatchS));
             if constexpr (S == 1)
                 step_tile_lds<float, ST_PLAIN, MODEL, kBatchTile, 2>(a, item->bxi, item->syi, t, item->down != 0, lds);
-            else
+            else {
+                static_assert(stepS_threads<kBatchTile, kBatchS>() == block_threads<kBatchTile>(),
+                              "one block size serves both tile functions");
                 stepS_tile_lds<MODEL, kBatchTile, kBatchS>(a, item->bxi, item->syi, t, item->down != 0, lds);
+            }
             // publish: every wavefront's stores are visible before the counter moves
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             __syncthreads();

@@ -664,30 +664,45 @@ struct TileSLds {
     float ps[S][3][W];     // psi of stage k on its last three rows
 };
 
+// Threads of an S-step tile: the BX + 4S columns of the grown tile rounded up
+// to whole wavefronts.  The wavefronts but the last own the tile's first
+// C = threads - 64 columns; the last one takes the 2S left halo columns and
+// then columns C .. BX + 2S - 1 (the rest of the tile and the right halo).
+// Every wavefront but the last thus loads and stores aligned 64-column
+// segments, and for BX a multiple of 64 the last one is a pure halo
+// wavefront.
+template <int BX, int S>
+__host__ __device__ constexpr int stepS_threads() {
+    return (BX + 4 * S + 63) / 64 * 64;
+}
+
 template <int MODEL, int BX, int S>
 __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
                                                TileSLds<BX, S>& lds) {
+    static_assert(BX + 4 * S <= stepS_threads<BX, S>() && stepS_threads<BX, S>() - 64 <= BX,
+                  "the last wavefront holds the halo and the tile's remaining columns");
+    constexpr int C = stepS_threads<BX, S>() - 64;
     const int l = threadIdx.x;
-    const bool colw = l < BX;  // a column thread
-    const int h = l - BX;      // lane of the halo wavefront
     const int x0 = bxi * BX;
     const int w = min(BX, a.nx - x0);
     const int ys = syi * a.strip_h;
     const int hh = min(a.strip_h, a.ny - ys);
-    const bool act = colw && l < w;  // owns column x0 + l
-    // Column of this thread, relative to x0: a column thread its own (idle
-    // ones of a narrow last tile: the tile's last column, a duplicate); halo
-    // lanes 0..4S-1 the columns -2S..-1 and w..w+2S-1; the other halo lanes
-    // duplicate a column thread.  Duplicates load and write the same values
-    // as the owner and do no stage work.
-    const int cxo = colw ? min(l, w - 1) : (h < 2 * S ? h - 2 * S : (h < 4 * S ? w + h - 2 * S : min(h - 4 * S, w - 1)));
+    // cxo: column of this thread relative to x0.  Threads past the grown tile
+    // (w + 4S columns; fewer than BX + 4S on a narrow last tile) duplicate
+    // its last column: they load and write the same values as the owner and
+    // do no stage work.  act: owns tile column x0 + cxo.
+    const int hl = l - C;  // lane in the last wavefront
+    const int craw = l < C ? l : (hl < 2 * S ? hl - 2 * S : C + hl - 2 * S);
+    const bool dup = craw > w + 2 * S - 1;
+    const int cxo = min(craw, w + 2 * S - 1);
+    const bool act = cxo >= 0 && cxo < w && !dup;
     // stage k forms phi/psi on columns -(2(S-k)-1) .. w+2(S-k)-2 and updates
     // -(2(S-k)-2) .. w+2(S-k)-3
     bool pk[S], uk[S];
 #pragma unroll
     for (int k = 0; k < S; ++k) {
-        pk[k] = act || (!colw && h >= 2 * k + 1 && h <= 4 * S - 2 * k - 2);
-        uk[k] = act || (!colw && h >= 2 * k + 2 && h <= 4 * S - 2 * k - 3);
+        pk[k] = !dup && cxo >= -(2 * (S - k) - 1) && cxo <= w + 2 * (S - k) - 2;
+        uk[k] = !dup && cxo >= -(2 * (S - k) - 2) && cxo <= w + 2 * (S - k) - 3;
     }
     const int gcol = wrap_idx(x0 + cxo, a.nx);
     const int j = cxo + 2 * S;
@@ -816,7 +831,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                     put(k + 1, s3, s2, ob);
             }
         }
-        io.store(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + l), ob, phi_out);
+        io.store(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + cxo), ob, phi_out);
         // ---- age the histories by one iteration
 #pragma unroll
         for (int k = 0; k < S; ++k) {
@@ -841,7 +856,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
 }
 
 template <int MODEL, int BX, int S>
-__global__ __launch_bounds__(block_threads<BX>()) void stepS_kernel_lds(StepArgs a) {
+__global__ __launch_bounds__((stepS_threads<BX, S>())) void stepS_kernel_lds(StepArgs a) {
     __shared__ TileSLds<BX, S> lds;
     const int ntile = a.nbx * a.nby;
     const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);

@@ -299,8 +299,9 @@ class Simulation:
 
     def set_launch(self, bx, strip_h, variant=0):
         """variant 0: block-wide tiles through LDS; 1: one tile per wavefront in
-        registers; 2: block-wide with two rows of loads in flight; 3: two steps
-        per launch (FP32 storage)."""
+        registers; 2: block-wide with two rows of loads in flight; 3, 4: two or
+        three steps per launch (FP32 storage).  bx: tile columns, 64, 128 or
+        256; the multi-step variants take any multiple of 32 from 64 to 320."""
         _check(load().lbac_set_launch(self.h, int(variant), int(bx), int(strip_h)), self.h)
 
     def get_launch(self):

@@ -22,6 +22,12 @@ def say(*a):
     sys.stdout.flush()
 
 
+def full_widths(variant):
+    """Tile widths of the multi-step kernels that are not multiples of 64: the
+    last wavefront then holds tile columns besides the halo."""
+    return [96, 160, 224, 288]
+
+
 def run(lb, case, phi0, steps, launch, graph=0, chunks=None):
     sim = lb.Simulation({**case, "precision": "f32"}, phi0)
     sim.set_launch(*launch)
@@ -39,8 +45,9 @@ def test_bitwise_equal_to_one_step_kernels(gpu_lib, model, variant):
     case = {**W.single_vortex_case(320, U=0.05, period_T=100.0), "model": model}
     phi0 = W.circle(320, 1.0)
     base = run(gpu_lib, case, phi0, 13, (256, 64, 0)).phi()
+    fw = full_widths(variant)
     for bx, strip in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17), (128, 2), (256, 3), (192, 40), (320, 7),
-                      (192, 1), (320, 320)):
+                      (192, 1), (320, 320), (fw[1], 9), (fw[2], 64), (fw[3], 1), (fw[2], 320), (fw[2], 2), (fw[0], 11)):
         phi = run(gpu_lib, case, phi0, 13, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -53,7 +60,9 @@ def test_ragged_and_degenerate_grids(gpu_lib, nx, ny, variant):
     rng = np.random.default_rng(nx * 1000 + ny)
     phi0 = W.circle(max(nx, ny), 1.5, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
     base = run(gpu_lib, case, phi0, 11, (64, 7, 0)).phi()
-    for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2), (192, 3), (320, 5)):
+    fw = full_widths(variant)
+    for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2), (192, 3), (320, 5), (fw[2], 4), (fw[1], 13),
+                      (fw[3], 2), (fw[0], 6)):
         phi = run(gpu_lib, case, phi0, 11, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -71,7 +80,9 @@ def test_step_counts_and_graph_chunks(gpu_lib, variant):
     chunks = [1, 2, 3, 8, 5, 6, 12, 7, 1]
     ref = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
     ref.set_launch(128, 16, 0)
-    sims = [run(gpu_lib, case, phi0, 0, (128, 16, variant), graph=g, chunks=[0]) for g in (0, 6, 8, 4)]
+    fw = full_widths(variant)
+    sims = [run(gpu_lib, case, phi0, 0, (bx, 16, variant), graph=g, chunks=[0])
+            for g, bx in ((0, 128), (6, 128), (8, fw[2]), (4, fw[1]))]
     for n in chunks:
         ref.step(n)
         for s in sims:
@@ -129,20 +140,25 @@ def test_needs_fp32_storage(gpu_lib, prec):
 
 
 def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
-    """192- and 320-column tiles exist for the multi-step kernels; the
-    one-step launches such a context makes (a remainder, or with the closure
-    on) use 256-column tiles, bit for bit the same."""
+    """Tiles of 96, 160, 192, 224, 288 and 320 columns exist for the
+    multi-step kernels only; the one-step launches such a
+    context makes (a remainder, or with the closure on) use 256-column tiles,
+    bit for bit the same."""
     case = W.single_vortex_case(200, U=0.05, period_T=100.0)
     phi0 = W.circle(200, 1.0)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
     for variant in (0, 1, 2):
-        for bx in (192, 320):
+        for bx in [192, 320] + full_widths(FUSED3):
+            with pytest.raises(gpu_lib.LbacError):
+                sim.set_launch(bx, 16, variant)
+    for variant in VARIANTS:
+        for bx in (32, 80, 244, 248, 352):
             with pytest.raises(gpu_lib.LbacError):
                 sim.set_launch(bx, 16, variant)
     sim.close()
     base = run(gpu_lib, case, phi0, 7, (256, 16, 0)).phi()
-    for bx in (192, 320):
-        for variant in VARIANTS:
+    for variant in VARIANTS:
+        for bx in [192, 320] + full_widths(variant):
             assert np.array_equal(run(gpu_lib, case, phi0, 7, (bx, 16, variant)).phi(), base), (bx, variant)
 
 
