@@ -41,6 +41,10 @@ __host__ __device__ constexpr int cx(int q) {
 __host__ __device__ constexpr int cy(int q) {
     return q == 2 || q == 5 || q == 6 ? 1 : (q == 4 || q == 7 || q == 8 ? -1 : 0);
 }
+// The population with velocity (cx, -cy): the mirror image of q under y -> -y.
+__host__ __device__ constexpr int mirror_q(int q) {
+    return q == 2 ? 4 : (q == 4 ? 2 : (q == 5 ? 8 : (q == 8 ? 5 : (q == 6 ? 7 : (q == 7 ? 6 : q)))));
+}
 template <typename R>
 __host__ __device__ constexpr R wq(int q) {
     return q == 0 ? R(4) / R(9) : (q < 5 ? R(1) / R(9) : R(1) / R(36));
@@ -224,6 +228,20 @@ __device__ __forceinline__ R clip01(R p) {
     return p < R(0) ? R(0) : (p > R(1) ? R(1) : p);
 }
 
+// Sums over the populations, in an order that the mirror y -> -y of the
+// lattice (which swaps populations 2 and 4, 5 and 8, 6 and 7) leaves
+// unchanged: a kernel that marches a strip downward in the mirrored frame
+// then rounds exactly like one working in the lattice frame.  sum9 over all
+// nine, sum_moving over 1..8.
+template <typename R>
+__device__ __forceinline__ R sum_moving(const R (&f)[9]) {
+    return ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[8]) + (f[6] + f[7]));
+}
+template <typename R>
+__device__ __forceinline__ R sum9(const R (&f)[9]) {
+    return f[0] + sum_moving(f);
+}
+
 // Row factor of the velocity tables (Ay or By at row y): the same for the
 // whole workgroup, read through the constant address space so that it is a
 // scalar load, which does not queue behind the rows being prefetched.
@@ -309,10 +327,7 @@ __device__ __forceinline__ void collide(const R* fp, R phi, R u, R v, R Gx, R Gy
     out[6] = fmaR(k.keep, fp[6], (a5 - x5) + y5);
     out[7] = fmaR(k.keep, fp[7], (a5 - x5) - y5);
     out[8] = fmaR(k.keep, fp[8], (a5 + x5) - y5);
-    R rest = phi;
-#pragma unroll
-    for (int q = 1; q < 9; ++q) rest -= out[q];
-    out[0] = rest;
+    out[0] = phi - sum_moving(out);
 }
 
 // Uniform per-plane base pointers and 32-bit byte offsets (a plane is far
@@ -359,6 +374,16 @@ struct Io<R, ST_PLAIN> {
         for (int q = 0; q < 9; ++q) {
             s[q] = static_cast<const char*>(a.src) + (size_t)q * a.plane_stride * sizeof(R);
             d[q] = static_cast<char*>(a.dst) + (size_t)q * a.plane_stride * sizeof(R);
+        }
+    }
+    // In the mirrored frame (y -> -y) population q lives in the plane of its
+    // mirror image: 2 <-> 4, 5 <-> 8, 6 <-> 7.
+    __device__ __forceinline__ Io(const StepArgs& a, bool mirror) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int m = mirror ? mirror_q(q) : q;
+            s[q] = static_cast<const char*>(a.src) + (size_t)m * a.plane_stride * sizeof(R);
+            d[q] = static_cast<char*>(a.dst) + (size_t)m * a.plane_stride * sizeof(R);
         }
     }
     __device__ __forceinline__ void load(uint32_t off, R (&v)[9]) const {
@@ -513,14 +538,10 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
         const int slot_s = down ? slot : slot2;  // row c - 1
         // ---- row r into the ring
         {
-            R s = R(0);
 #pragma unroll
-            for (int q = 0; q < 9; ++q) {
-                ring[slot][q][lj] = nv[q];
-                s += nv[q];
-            }
+            for (int q = 0; q < 9; ++q) ring[slot][q][lj] = nv[q];
             // phi at t-1 on this row: the stored sum (plain) or phi* itself (shifted)
-            P0 = Io<R, ST>::kShifted ? nv[0] : s;
+            P0 = Io<R, ST>::kShifted ? nv[0] : sum9(nv);
         }
         // ---- prefetch row r + PF dir into the registers just consumed
         io.load(row_of(it + PF) * (uint32_t)a.pitch + lcol, nv);
@@ -541,13 +562,12 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
                 fcur[0] = R(0);  // the rest population is formed as the remainder after collision
                 s = R(d);
             } else {
-                s = R(0);
 #pragma unroll
                 for (int q = 0; q < 9; ++q) {
                     const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
                     fcur[q] = ring[sl][q][pj - cx(q)];
-                    s += fcur[q];
                 }
+                s = sum9(fcur);
             }
             phicur = s;
             sring[slot][pj - 1] = normal_source<R, MODEL>(s, kc);
@@ -651,8 +671,8 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // Rings.  A pull f_i(x, c) = f*_i(x - c_i) needs another thread's column only
 // for the six populations with c_x != 0, and each of those only from one
 // row: the centre row (populations 1 and 3), the row behind it in the march
-// direction (the "old" pair: 5, 6 marching up, 8, 7 marching down) or the row
-// ahead (the "new" pair).  So the rings hold, per pair, as many rows as the
+// direction (the "old" pair 5, 6; the march runs toward +y in the frame the
+// stages see) or the row ahead (the "new" pair 8, 7).  So the rings hold, per pair, as many rows as the
 // pull is late; the three populations with c_x = 0 stay in the thread's
 // registers.  Pairs are stored c_x = +1 first.  Index j <-> column x0 - 2S + j.
 template <int BX, int S>
@@ -706,10 +726,18 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     }
     const int gcol = wrap_idx(x0 + cxo, a.nx);
     const int j = cxo + 2 * S;
-    const Io<float, ST_PLAIN> io(a);
+    // A strip marched downward is computed in the mirrored frame y -> -y:
+    // populations are read from and written to the planes of their mirror
+    // images and the y velocity changes sign, so the march always runs
+    // toward +y in the frame the stages see and no value depends on the
+    // direction.  Every node helper rounds mirror-symmetrically (sums in
+    // mirror-invariant order, y components that only change sign), so the
+    // results equal the lattice-frame computation bit for bit.
+    const Io<float, ST_PLAIN> io(a, down);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
-    const float Ax = float(a.vtab[gcol]), Bx = float(a.vtab[a.nx + gcol]);
+    const float Ax = float(a.vtab[gcol]);
+    const float Bx = down ? -float(a.vtab[a.nx + gcol]) : float(a.vtab[a.nx + gcol]);
     NodeConst<float> kcs[S];  // stage k at time t + k
 #pragma unroll
     for (int k = 0; k < S; ++k) kcs[k] = NodeConst<float>(a, t + k);
@@ -745,19 +773,16 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, hh + 4 * S - 1)), a.ny); };
     // a stage's input into its ring and histories (v: populations at the own column)
     auto put = [&](int k, int s3, int s2, const float(&v)[9]) __attribute__((always_inline)) {
-        float s = 0.f;
-#pragma unroll
-        for (int q = 0; q < 9; ++q) s += v[q];
-        P[k][0] = s;
-        lds.ro[k][s3][0][j] = down ? v[8] : v[5];
-        lds.ro[k][s3][1][j] = down ? v[7] : v[6];
+        P[k][0] = sum9(v);
+        lds.ro[k][s3][0][j] = v[5];
+        lds.ro[k][s3][1][j] = v[6];
         lds.rm[k][s2][0][j] = v[1];
         lds.rm[k][s2][1][j] = v[3];
-        lds.rn[k][0][j] = down ? v[5] : v[8];
-        lds.rn[k][1][j] = down ? v[6] : v[7];
+        lds.rn[k][0][j] = v[8];
+        lds.rn[k][1][j] = v[7];
         z0[k][0] = v[0];
-        zo[k][0] = down ? v[4] : v[2];
-        zn[k][0] = down ? v[2] : v[4];
+        zo[k][0] = v[2];
+        zn[k][0] = v[4];
     };
     auto body = [&](const int it, float(&nv)[9], auto parity) __attribute__((always_inline)) {
         constexpr int B = decltype(parity)::value;  // it & 1
@@ -778,33 +803,28 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
             if (it >= 5 * k + 2 && pk[k]) {
                 const int so = (it + 1 + 2 * lag) % 3;  // old pair: it - 2 - lag
                 const int sm = B ^ 1 ^ lag;             // populations 1, 3: it - 1 - lag
-                const float o0 = lds.ro[k][so][0][j - 1], o1 = lds.ro[k][so][1][j + 1];
-                const float n0 = lds.rn[k][0][j - 1], n1 = lds.rn[k][1][j + 1];
-                const float zo_ = zo[k][2 + lag], zn_ = zn[k][lag];
                 float(&f)[9] = fp[k][B];
                 f[0] = z0[k][1 + lag];
                 f[1] = lds.rm[k][sm][0][j - 1];
-                f[2] = down ? zn_ : zo_;
+                f[2] = zo[k][2 + lag];
                 f[3] = lds.rm[k][sm][1][j + 1];
-                f[4] = down ? zo_ : zn_;
-                f[5] = down ? n0 : o0;
-                f[6] = down ? n1 : o1;
-                f[7] = down ? o1 : n1;
-                f[8] = down ? o0 : n0;
-                float s = 0.f;
-#pragma unroll
-                for (int q = 0; q < 9; ++q) s += f[q];
+                f[4] = zn[k][lag];
+                f[5] = lds.ro[k][so][0][j - 1];
+                f[6] = lds.ro[k][so][1][j + 1];
+                f[7] = lds.rn[k][1][j + 1];
+                f[8] = lds.rn[k][0][j - 1];
+                const float s = sum9(f);
                 ph[k][B] = s;
                 lds.ps[k][s3][j] = normal_source<float, MODEL>(s, kcs[k]);
             }
         }
         lds_barrier();
 
-        // psi rows around an updated row (centre slot it + 2; the newest row
-        // is one step ahead of it in the march direction)
+        // psi rows around an updated row (centre slot it + 2; the newest row,
+        // slot it, is one step ahead of it: +y in the stages' frame)
         const int c0 = (it + 2) % 3;
-        const int cm = down ? it % 3 : (it + 1) % 3;
-        const int cp = down ? (it + 1) % 3 : it % 3;
+        const int cm = (it + 1) % 3;
+        const int cp = it % 3;
         // ---- updates: stage k on row R - (3k + 2) dir at t + k; the last stage into HBM
         const bool st = act && it >= 5 * S - 1;
         const int yl = min(max(Rr - (3 * S - 1) * dir, 0), a.ny - 1);
@@ -1119,10 +1139,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
         if constexpr (Io<R, ST>::kShifted) {
             P[0] = r0[0];  // phi* itself
         } else {
-            R s = R(0);
-#pragma unroll
-            for (int q = 0; q < 9; ++q) s += r0[q];
-            P[0] = s;
+            P[0] = sum9(r0);
         }
         // unconditional, like the update's stores below, so that the compiler
         // counts the memory operations in flight exactly (past the strip's
@@ -1158,9 +1175,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
                 fc[0] = R(0);  // the rest population is formed as the remainder after collision
                 s = R(d);
             } else {
-                s = R(0);
-#pragma unroll
-                for (int q = 0; q < 9; ++q) s += fc[q];
+                s = sum9(fh[0]);
             }
             ph[0] = s;
             ps[0] = normal_source<R, MODEL>(s, kc);
@@ -1283,17 +1298,17 @@ static __global__ __launch_bounds__(kClWaves * kWave) void closure_apply_kernel(
         const bool on = e < n;
         const int node = list[on ? e : g * kWave];
         const int y = node / a.nx, x = node % a.nx;
-        // phi(t) on the 5x5 neighbourhood: sum_i f*_i(z - c_i, t - 1), i = 0..8 in order
+        // phi(t) on the 5x5 neighbourhood: sum_i f*_i(z - c_i, t - 1), summed as in the step
         float xin[25];
         for (int dy = -2; dy <= 2; ++dy)
             for (int dx = -2; dx <= 2; ++dx) {
                 const int zy = wrap_idx(y + dy, a.ny), zx = wrap_idx(x + dx, a.nx);
-                float s = 0.f;
+                float fz[9];
 #pragma unroll
                 for (int q = 0; q < 9; ++q)
-                    s += src[q * a.plane_stride + (int64_t)wrap_idx(zy - cy(q), a.ny) * a.pitch +
-                             wrap_idx(zx - cx(q), a.nx)];
-                xin[(dy + 2) * 5 + (dx + 2)] = s;
+                    fz[q] = src[q * a.plane_stride + (int64_t)wrap_idx(zy - cy(q), a.ny) * a.pitch +
+                                wrap_idx(zx - cx(q), a.nx)];
+                xin[(dy + 2) * 5 + (dx + 2)] = sum9(fz);
             }
         float ccx, ccy;
         closure_mlp(cl, xin, ccx, ccy);
@@ -1315,10 +1330,7 @@ static __global__ __launch_bounds__(kClWaves * kWave) void closure_apply_kernel(
             f[7] -= dx5 + dy5;
             f[6] += dy5 - dx5;
             f[8] -= dy5 - dx5;
-            float rest = phi;
-#pragma unroll
-            for (int q = 1; q < 9; ++q) rest -= f[q];
-            dst[off] = rest;
+            dst[off] = phi - sum_moving(f);
 #pragma unroll
             for (int q = 1; q < 9; ++q) dst[q * a.plane_stride + off] = f[q];
         }

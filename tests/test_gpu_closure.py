@@ -177,8 +177,12 @@ def test_trained_closure_reduces_shape_error(gpu_lib):
     train = CL.coarse_cases(64, 1, n=128, eps=0.5)
     X, Y = CL.generate(train, snapshots=16, theta=0.02, log=say)
     w, hist, _ = CL.train(X, Y, steps=3000, batch=4096, lr=2e-3, seed=1, log=lambda m: None)
-    say("  loss %.3e -> %.3e" % (hist[0][1], hist[-1][1]))
-    assert hist[-1][1] < 0.1 * hist[0][1]
+    # each logged loss is one minibatch of 4096 samples from heavy-tailed
+    # targets (outliers beyond 30 standard deviations), so single values spike
+    # by up to 10x at any step: judge the median of the second half
+    late = float(np.median([h[1] for h in hist[len(hist) // 2:]]))
+    say("  loss %.3e -> median %.3e over the second half" % (hist[0][1], late))
+    assert late < 0.1 * hist[0][1]
     rows = CL.evaluate(w, CL.coarse_cases(4, 1001, n=128, eps=0.5), theta=0.02, log=say)
     ratios = [r["closure"][1] / r["plain"][1] for r in rows]
     say("  E2 closure / plain:", ["%.3f" % v for v in ratios])
