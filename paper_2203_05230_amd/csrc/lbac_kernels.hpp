@@ -674,10 +674,13 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // direction (the "old" pair 5, 6; the march runs toward +y in the frame the
 // stages see) or the row ahead (the "new" pair 8, 7).  So the rings hold, per pair, as many rows as the
 // pull is late; the three populations with c_x = 0 stay in the thread's
-// registers.  Pairs are stored c_x = +1 first.  Index j <-> column x0 - 2S + j.
+// registers.  Pairs are stored c_x = +1 first.  Index j <-> column
+// x0 - 2S - 1 + j; indices 0 and W - 1 are padding, so that every thread's
+// reads at j - 1 and j + 1 stay inside its row, and W - 1 also takes the
+// writes of duplicate threads.
 template <int BX, int S>
 struct TileSLds {
-    static constexpr int W = BX + 4 * S;
+    static constexpr int W = BX + 4 * S + 2;
     float ro[S][3][2][W];  // input of stage k: old pair, three rows
     float rm[S][2][2][W];  // populations 1 and 3, two rows
     float rn[S][2][W];     // new pair, one row
@@ -716,16 +719,16 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     const bool dup = craw > w + 2 * S - 1;
     const int cxo = min(craw, w + 2 * S - 1);
     const bool act = cxo >= 0 && cxo < w && !dup;
-    // stage k forms phi/psi on columns -(2(S-k)-1) .. w+2(S-k)-2 and updates
-    // -(2(S-k)-2) .. w+2(S-k)-3
-    bool pk[S], uk[S];
-#pragma unroll
-    for (int k = 0; k < S; ++k) {
-        pk[k] = !dup && cxo >= -(2 * (S - k) - 1) && cxo <= w + 2 * (S - k) - 2;
-        uk[k] = !dup && cxo >= -(2 * (S - k) - 2) && cxo <= w + 2 * (S - k) - 3;
-    }
+    // Stage k forms phi/psi validly on columns -(2(S-k)-1) .. w+2(S-k)-2 and
+    // updates -(2(S-k)-2) .. w+2(S-k)-3.  Every thread runs every stage
+    // (branching on these ranges would only hold per-lane masks, since every
+    // wavefront has lanes inside them): outside them a thread forms values
+    // from rows or columns that are not valid yet, which no valid value reads
+    // (each range is the next one's reach plus one column on each side), and
+    // a duplicate thread writes its LDS values to the padding column.
     const int gcol = wrap_idx(x0 + cxo, a.nx);
-    const int j = cxo + 2 * S;
+    const int j = cxo + 2 * S + 1;                         // reads
+    const int jw = dup ? TileSLds<BX, S>::W - 1 : j;  // writes
     // A strip marched downward is computed in the mirrored frame y -> -y:
     // populations are read from and written to the planes of their mirror
     // images and the y velocity changes sign, so the march always runs
@@ -774,12 +777,12 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     // a stage's input into its ring and histories (v: populations at the own column)
     auto put = [&](int k, int s3, int s2, const float(&v)[9]) __attribute__((always_inline)) {
         P[k][0] = sum9(v);
-        lds.ro[k][s3][0][j] = v[5];
-        lds.ro[k][s3][1][j] = v[6];
-        lds.rm[k][s2][0][j] = v[1];
-        lds.rm[k][s2][1][j] = v[3];
-        lds.rn[k][0][j] = v[8];
-        lds.rn[k][1][j] = v[7];
+        lds.ro[k][s3][0][jw] = v[5];
+        lds.ro[k][s3][1][jw] = v[6];
+        lds.rm[k][s2][0][jw] = v[1];
+        lds.rm[k][s2][1][jw] = v[3];
+        lds.rn[k][0][jw] = v[8];
+        lds.rn[k][1][jw] = v[7];
         z0[k][0] = v[0];
         zo[k][0] = v[2];
         zn[k][0] = v[4];
@@ -800,7 +803,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int lag = k == 0 ? 0 : 1;
-            if (it >= 5 * k + 2 && pk[k]) {
+            if (it >= 5 * k + 2) {
                 const int so = (it + 1 + 2 * lag) % 3;  // old pair: it - 2 - lag
                 const int sm = B ^ 1 ^ lag;             // populations 1, 3: it - 1 - lag
                 float(&f)[9] = fp[k][B];
@@ -815,7 +818,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                 f[8] = lds.rn[k][0][j - 1];
                 const float s = sum9(f);
                 ph[k][B] = s;
-                lds.ps[k][s3][j] = normal_source<float, MODEL>(s, kcs[k]);
+                lds.ps[k][s3][jw] = normal_source<float, MODEL>(s, kcs[k]);
             }
         }
         lds_barrier();
@@ -831,7 +834,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const bool last = k == S - 1;
-            if (last ? st : (it >= 5 * k + 4 && uk[k])) {
+            if (it >= 5 * k + 4) {
                 const NodeConst<float>& kc = kcs[k];
                 const int y = last ? yl : wrap_idx(Rr - (3 * k + 2) * dir, a.ny);
                 const float(&ps)[3][TileSLds<BX, S>::W] = lds.ps[k];
