@@ -58,6 +58,7 @@ void release(lbac_ctx* h) {
         dev_free(h, h->phis[i]);
     }
     dev_free(h, h->vtab);
+    dev_free(h, h->vtabf);
     dev_free(h, h->t_dev);
     dev_free(h, h->rows);
     dev_free(h, h->red5);
@@ -146,6 +147,7 @@ StepArgs lbac_host::make_args(const lbac_ctx* h, int src, int32_t k) {
     a.ny = h->p.ny;
     a.strip_h = h->strip_h;
     a.vtab = h->vtab;
+    a.vtabf = h->vtabf;
     a.t_dev = h->t_dev;
     a.k = k;
     a.period_T = time_period(h->p);
@@ -465,17 +467,21 @@ int lbac_host::create(const lbac_params* p, const double* phi0, bool phi0_on_dev
     std::vector<double> tab;
     build_velocity(h->p, tab);
     h->vtab = (double*)dev_alloc(h, tab.size() * sizeof(double));
+    h->vtabf = (float*)dev_alloc(h, tab.size() * sizeof(float));
+    std::vector<float> tabf(tab.begin(), tab.end());
     h->t_dev = (int64_t*)dev_alloc(h, 64);
     h->rows = (double*)dev_alloc(h, 5 * sizeof(double) * (size_t)p->ny);
     h->red5 = (double*)dev_alloc(h, 64);
     h->dtmp = (double*)dev_alloc(h, n * sizeof(double));
-    if (!h->vtab || !h->t_dev || !h->rows || !h->red5 || !h->dtmp) return bail(LBAC_ENOMEM);
+    if (!h->vtab || !h->vtabf || !h->t_dev || !h->rows || !h->red5 || !h->dtmp) return bail(LBAC_ENOMEM);
     if (hipHostMalloc((void**)&h->host5, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         h->host5 = nullptr;
         return bail(LBAC_ENOMEM);
     }
     if (hipMemcpyAsync(h->vtab, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, h->stream) !=
-        hipSuccess)
+            hipSuccess ||
+        hipMemcpyAsync(h->vtabf, tabf.data(), tabf.size() * sizeof(float), hipMemcpyHostToDevice, h->stream) !=
+            hipSuccess)
         return bail(LBAC_EDEVICE);
     const double* src0 = phi0;
     if (!phi0_on_device) {

@@ -45,6 +45,7 @@ struct lbac_ctx {
     void* pop[2] = {nullptr, nullptr};
     float* phis[2] = {nullptr, nullptr};
     double* vtab = nullptr;
+    float* vtabf = nullptr;  // vtab rounded to FP32
     int64_t* t_dev = nullptr;
     double* rows = nullptr;
     double* red5 = nullptr;

@@ -63,6 +63,7 @@ struct StepArgs {
     int32_t nx, ny;
     int32_t strip_h;        // rows per block
     const double* vtab;     // Ax[nx], Bx[nx], Ay[ny], By[ny]: u = s(t) Ax Ay, v = s(t) Bx By
+    const float* vtabf;     // the same table rounded to FP32
     const int64_t* t_dev;   // step count at the start of this launch sequence
     int32_t k;              // this launch is step t_dev[0] + k
     double period_T;        // s(t) = cos(pi t / period_T) when > 0, else 1
@@ -223,10 +224,12 @@ struct Math<double> {
 __device__ __forceinline__ float fmaR(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 __device__ __forceinline__ double fmaR(double a, double b, double c) { return __builtin_fma(a, b, c); }
 
-template <typename R>
-__device__ __forceinline__ R clip01(R p) {
-    return p < R(0) ? R(0) : (p > R(1) ? R(1) : p);
-}
+// min(max(p, 0), 1) for finite p (the clip of Eq. (13)): one median-of-three
+// instruction in FP32.  A signed zero may come out as either zero, which no
+// use distinguishes (each adds delta, subtracts from 1 or compares with a
+// positive bound).
+__device__ __forceinline__ float clip01(float p) { return __builtin_amdgcn_fmed3f(p, 0.f, 1.f); }
+__device__ __forceinline__ double clip01(double p) { return __builtin_fmin(__builtin_fmax(p, 0.0), 1.0); }
 
 // Sums over the populations, in an order that the mirror y -> -y of the
 // lattice (which swaps populations 2 and 4, 5 and 8, 6 and 7) leaves
@@ -247,6 +250,9 @@ __device__ __forceinline__ R sum9(const R (&f)[9]) {
 // scalar load, which does not queue behind the rows being prefetched.
 __device__ __forceinline__ double row_factor(const double* vtab, int64_t i) {
     return ((const __attribute__((address_space(4))) double*)vtab)[i];
+}
+__device__ __forceinline__ float row_factor(const float* vtabf, int64_t i) {
+    return ((const __attribute__((address_space(4))) float*)vtabf)[i];
 }
 
 // Per-step constants of the update.
@@ -739,8 +745,10 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     const Io<float, ST_PLAIN> io(a, down);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
-    const float Ax = float(a.vtab[gcol]);
-    const float Bx = down ? -float(a.vtab[a.nx + gcol]) : float(a.vtab[a.nx + gcol]);
+    // FP32 velocity factors: the FP64 table rounded once on the host, as the
+    // one-step kernels round it on the device
+    const float Ax = a.vtabf[gcol];
+    const float Bx = down ? -a.vtabf[a.nx + gcol] : a.vtabf[a.nx + gcol];
     NodeConst<float> kcs[S];  // stage k at time t + k
 #pragma unroll
     for (int k = 0; k < S; ++k) kcs[k] = NodeConst<float>(a, t + k);
@@ -842,8 +850,8 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                 iso_gradient(ps[c0][j + 1], ps[c0][j - 1], ps[cp][j], ps[cm][j], ps[cp][j + 1], ps[cp][j - 1],
                              ps[cm][j + 1], ps[cm][j - 1], gx, gy);
                 const float phi = ph[k][B ^ 1];
-                const float uxr = Ax * float(row_factor(a.vtab, 2 * a.nx + y));
-                const float uyr = Bx * float(row_factor(a.vtab, 2 * a.nx + a.ny + y));
+                const float uxr = Ax * row_factor(a.vtabf, 2 * a.nx + y);
+                const float uyr = Bx * row_factor(a.vtabf, 2 * a.nx + a.ny + y);
                 const float phio = P[k][k == 0 ? 2 : 3];
                 flux_bracket<float, MODEL>(gx, gy, phi, kc.first ? phi : phio, kc.s_now * uxr, kc.s_now * uyr,
                                            kc.s_old * uxr, kc.s_old * uyr, kc, Gx, Gy);
