@@ -47,25 +47,42 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
+def _summary_fields(path):
+    kv = {}
+    with open(path) as fh:
+        for line in fh:
+            if ":" in line:
+                k, v = line.split(":", 1)
+                kv[k.strip()] = v.strip()
+    return kv
+
+
 def _counter_summary(path, key, launch):
     """A value from a committed rocprofv3 counter summary, if the summary was
-    taken on the current kernel source with the same kernel variant and tile
-    width (the strip height, which the autotuner may pick differently within
-    its timing noise, changes the figures by a few tenths of a percent);
-    else None."""
+    taken on the current kernel source in the same launch shape (tile width,
+    strip height and variant: the strip height changes the rows re-read
+    between strips, hence the fetched bytes); else None."""
     try:
-        kv = {}
-        with open(path) as fh:
-            for line in fh:
-                if ":" in line:
-                    k, v = line.split(":", 1)
-                    kv[k.strip()] = v.strip()
+        kv = _summary_fields(path)
         if kv.get("kernel_source_sha") != kernel_source_hash():
             return None
-        bx, _, variant = (int(v) for v in kv["launch"].split(","))
-        if launch is None or (bx, variant) != (int(launch[0]), int(launch[2])):
+        shape = tuple(int(v) for v in kv["launch"].split(","))
+        if launch is None or shape != tuple(int(v) for v in launch):
             return None
         return float(kv[key])
+    except (OSError, KeyError, ValueError):
+        return None
+
+
+def profiled_launch():
+    """The launch shape (bx, strip_h, variant) the committed counter summary
+    of the step kernel was taken on (the shape the autotuner picked on the
+    profiling run), if it was taken on the current kernel source; else None."""
+    try:
+        kv = _summary_fields(COUNTERS_FILE)
+        if kv.get("kernel_source_sha") != kernel_source_hash():
+            return None
+        return tuple(int(v) for v in kv["launch"].split(","))
     except (OSError, KeyError, ValueError):
         return None
 
@@ -359,7 +376,9 @@ def main():
     ap.add_argument("--c1-steps", type=int, default=2000, help="steps (= period) of the 64^2 FP64 run (0: skip)")
     ap.add_argument("--c2-steps", type=int, default=16384,
                     help="steps (= period) of the 1024^2 storage-form comparison (0: skip)")
-    ap.add_argument("--launch", default="", help="bx,strip_h,variant (default: autotune)")
+    ap.add_argument("--launch", default="",
+                    help="bx,strip_h,variant, or 'auto' to autotune (default: the shape the committed counters were "
+                         "taken on, when they match the kernel source and the default workload; else autotune)")
     ap.add_argument("--one-step-steps", type=int, default=512,
                     help="steps of the one-step kernel timed for comparison when the two-step kernel runs (0: skip)")
     ap.add_argument("--steps3d", type=int, default=200, help="timed steps of the D3Q19 leg")
@@ -398,7 +417,15 @@ def main():
     n = args.n
     case = W.single_vortex_case(n, eps=args.eps, tau=0.8, U=0.02, period_T=args.period)
     phi0 = W.circle(n, args.eps)
-    launch = tuple(int(v) for v in args.launch.split(",")) if args.launch else None
+    if args.launch == "auto":
+        launch = None
+    elif args.launch:
+        launch = tuple(int(v) for v in args.launch.split(","))
+    else:
+        default_case = args.n == 8192 and args.precision == "f32" and args.eps == 1.0 and args.period == 4096.0
+        launch = profiled_launch() if default_case else None
+        if launch is not None:
+            print("bench: launch shape of the committed profiles: %s" % (launch,), file=sys.stderr, flush=True)
     print("bench: %dx%d %s, warmup %d, steps %d" % (n, n, args.precision, args.warmup, args.steps),
           file=sys.stderr, flush=True)
     main_run = run_form(lbac, torch, case, phi0, args.precision, args.steps, args.warmup, launch=launch,
