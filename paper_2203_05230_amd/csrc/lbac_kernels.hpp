@@ -1388,17 +1388,24 @@ __global__ void init_kernel(StepArgs a, const double* __restrict__ phi0) {
     }
 }
 
-// phi(x) = sum_i f*_i(x - c_i) from the stored state in a.src, in FP64.
+// phi(x) = sum_i f*_i(x - c_i) from the stored state in a.src, in FP64 (plain
+// storage: summed in the mirror-invariant order of the step).
 template <typename R, int ST>
 __device__ __forceinline__ double pulled_phi(const StepArgs& a, int x, int y) {
-    double s = 0.0;
     const int64_t own = (int64_t)y * a.pitch + x;
+    double v[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) {
         const int xs = wrap_idx(x - cx(q), a.nx), ys = wrap_idx(y - cy(q), a.ny);
-        s += (double)Store<R, ST>::load_one(a, (int64_t)ys * a.pitch + xs, q);
-        // shifted storage: phi = phi* + sum_{i>=1} [v_i(x - c_i) - v_i(x)]
-        if (Store<R, ST>::kShifted && q > 0) s -= (double)Store<R, ST>::load_one(a, own, q);
+        v[q] = (double)Store<R, ST>::load_one(a, (int64_t)ys * a.pitch + xs, q);
+    }
+    if constexpr (!Store<R, ST>::kShifted) return sum9(v);
+    // shifted storage: phi = phi* + sum_{i>=1} [v_i(x - c_i) - v_i(x)]
+    double s = 0.0;
+#pragma unroll
+    for (int q = 0; q < 9; ++q) {
+        s += v[q];
+        if (q > 0) s -= (double)Store<R, ST>::load_one(a, own, q);
     }
     return s;
 }
