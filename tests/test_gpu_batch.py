@@ -122,6 +122,34 @@ def test_batch_seeded_list_subset(gpu_lib):
     b.close()
 
 
+def oracle_params(c):
+    if c["vel"] == "rotation":
+        return O.Params(c["nx"], c["ny"], eps=c["eps"], tau=c["tau"], delta=c["delta"], vel_kind=O.VEL_ROTATION,
+                        omega=c["omega"], cx=c["cx"], cy=c["cy"])
+    return O.Params(c["nx"], c["ny"], eps=c["eps"], tau=c["tau"], delta=c["delta"], vel_kind=O.VEL_VORTEX,
+                    U=c["U"], period_T=c["period_T"])
+
+
+def test_batch_small_seeded_instances_match_oracle(gpu_lib):
+    """Eight small instances from the batched workload's seeded generator
+    (sides 32..96, both flows, eps and tau drawn as in the full list), each
+    against the FP64 oracle after its own step count (FP32 storage: relative
+    L2 <= 1e-5)."""
+    say("case: 8 small seeded batch instances vs oracle")
+    cases = W.batch_cases(count=8, seed=11, sides=(32, 48, 64, 96))
+    phis = [W.initial_field(c) for c in cases]
+    steps = [60 + 13 * k for k in range(8)]
+    b = gpu_lib.Batch(cases, phis)
+    b.run(steps)
+    for k, c in enumerate(cases):
+        ref = O.run(oracle_params(c), phis[k], steps[k])
+        err = float(np.linalg.norm(b.instance(k).phi() - ref) / np.linalg.norm(ref))
+        say("  instance %d (%s, n %d, eps %g, tau %.3f, %d steps): rel L2 %.2e" % (
+            k, c["vel"], c["nx"], c["eps"], c["tau"], steps[k], err))
+        assert err <= 1e-5, k
+    b.close()
+
+
 def test_batch_rejects_short_strips(gpu_lib):
     cases, phis, steps = mixed_cases()
     b = gpu_lib.Batch(cases[:2], phis[:2])
