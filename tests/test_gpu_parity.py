@@ -172,6 +172,30 @@ def test_velocity_fields_fp64(gpu_lib, vel, extra):
     assert_fp64_parity(sim.phi(), ref, 300, 1.0)
 
 
+@pytest.mark.parametrize("launch", [(256, 16, 0), (64, 5, 1)])
+def test_axis_invariant_data_reduce_to_d1q3(gpu_lib, launch):
+    """D2Q9 on data invariant along y (and along x) with a transverse velocity
+    is the D1Q3 scheme, written independently in 1-D in oracle/d1q3.py: the
+    FP64 HIP path against it directly, to round-off (Eq. (9)-(13) in 1-D)."""
+    from oracle import d1q3
+
+    N, eps, tau, steps = 64, 1.0, 0.8, 200
+    ref = d1q3.run(W.slab(N, 1, eps)[0], eps, tau, 1e-10, steps, lambda n: 0.05)
+    cx = dict(nx=N, ny=6, eps=eps, tau=tau, delta=1e-10, vel="uniform", ux=0.05, uy=0.03, precision="f64")
+    sx = gpu_lib.Simulation(cx, W.slab(N, 6, eps))
+    sx.set_launch(*launch)
+    sx.step(steps)
+    cy = dict(nx=6, ny=N, eps=eps, tau=tau, delta=1e-10, vel="uniform", ux=-0.02, uy=0.05, precision="f64")
+    sy = gpu_lib.Simulation(cy, W.slab(6, N, eps, axis=1))
+    sy.set_launch(*launch)
+    sy.step(steps)
+    err = max(np.max(np.abs(sx.phi() - ref[None, :])), np.max(np.abs(sy.phi() - ref[:, None])))
+    sx.close()
+    sy.close()
+    say("  max |D2Q9 - D1Q3| %.2e" % err)
+    assert err < 1e-12
+
+
 def test_conventional_model_fp64(gpu_lib):
     say("case: conventional model")
     case = {**W.single_vortex_case(64, U=0.04, period_T=400.0), "model": "conventional"}
