@@ -346,6 +346,17 @@ def cpu_baseline(phi0, case, steps, single_core_n=2048, single_core_steps=4):
                 % (sc["steps"], sc["n"], sc["n"], sc["seconds"]))
         else:
             out["single_core"] = dict(error=r.stderr.strip().splitlines()[-1:] or ["exit %d" % r.returncode])
+    # the oracle on the two smaller single-vortex configurations, for context:
+    # 64^2 over its full 2000-step period and 1024^2 over 128 steps
+    from paper_2203_05230_amd import workloads as W
+
+    others = {}
+    for n, period, nsteps in ((64, 2000.0, 2000), (1024, 16384.0, 128)):
+        c = W.single_vortex_case(n, eps=1.0, tau=0.8, U=0.02, period_T=period)
+        t = _oracle_rate(c, W.circle(n, 1.0), nsteps)
+        others["%dx%d" % (n, n)] = dict(value=n * n * nsteps / t / 1e6, unit="MLUPS", steps=nsteps,
+                                        seconds=round(t, 2))
+    out["other_configs"] = others
     try:
         with open("/proc/cpuinfo") as fh:
             names = [ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")]
