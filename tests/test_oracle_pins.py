@@ -121,8 +121,26 @@ def pin_vortex_nonnegative_finite(mutation=0):
     return bool(np.all(np.isfinite(a)) and a.min() < 0.0), float(a.min())
 
 
+def pin_symmetry(mutation=0, steps=60):
+    """D2Q9 and Eq. (9)-(13) are invariant under the reflection y -> -y
+    (with v -> -v) and under exchanging x and y (with u <-> v): a run from the
+    reflected or transposed field with the matching uniform velocity must be
+    the reflected or transposed run, to round-off."""
+    nx, ny, eps = 40, 32, 1.0
+    rng = np.random.default_rng(5)
+    phi0 = W.circle(40, 1.5, R_frac=0.25, yc_frac=0.4)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
+    ux, uy = 0.03, 0.02
+    run = lambda f, a, b: O.run(O.Params(f.shape[1], f.shape[0], eps=eps, tau=0.7, vel_kind=O.VEL_UNIFORM, ux=a,
+                                         uy=b, mutation=mutation), np.ascontiguousarray(f), steps)
+    base = run(phi0, ux, uy)
+    refl = run(phi0[::-1], ux, -uy)[::-1]
+    trans = run(phi0.T, uy, ux).T
+    err = max(np.max(np.abs(refl - base)), np.max(np.abs(trans - base)))
+    return bool(err < 1e-12), err
+
+
 ALL_PINS = [pin_mass, pin_stationary, pin_d1q3, pin_fv_large_u, pin_fv_diffusive, pin_translation, pin_trivial,
-            pin_vortex_nonnegative_finite]
+            pin_vortex_nonnegative_finite, pin_symmetry]
 
 
 # --------------------------------------------------------------------------
@@ -349,6 +367,19 @@ def test_planted_mistake_is_caught(name):
             failed.append(pin.__name__)
             break
     assert failed, "mistake %s passed every pin" % name
+
+
+def test_reflection_and_transposition_symmetry():
+    ok, err = pin_symmetry()
+    assert ok, err
+
+
+@pytest.mark.parametrize("name", ["grad_swap", "vel_swap"])
+def test_symmetry_pin_catches_axis_mistakes(name):
+    """Mistakes that treat x and y differently break the symmetry pin on
+    their own."""
+    ok, err = pin_symmetry(mutation=O.MUTATIONS[name])
+    assert not ok, err
 
 
 def test_unmutated_oracle_passes_every_pin():
