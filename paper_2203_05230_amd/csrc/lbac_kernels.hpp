@@ -690,9 +690,9 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // for the six populations with c_x != 0, and each of those only from one
 // row: the centre row (populations 1 and 3), the row behind it in the march
 // direction (the "old" pair 5, 6; the march runs toward +y in the frame the
-// stages see) or the row ahead (the "new" pair 8, 7).  So the rings hold, per pair, as many rows as the
-// pull is late; the three populations with c_x = 0 stay in the thread's
-// registers.  Pairs are stored c_x = +1 first.  Index j <-> column
+// stages see) or the row ahead (the "new" pair 8, 7).  So the rings hold,
+// per pair, as many rows as the pull is late; the three populations with
+// c_x = 0 stay in the thread's registers.  Pairs are stored c_x = +1 first.  Index j <-> column
 // x0 - 2S - 1 + j; indices 0 and W - 1 are padding, so that every thread's
 // reads at j - 1 and j + 1 stay inside its row, and W - 1 also takes the
 // writes of duplicate threads.
@@ -730,8 +730,8 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     const int hh = min(a.strip_h, a.ny - ys);
     // cxo: column of this thread relative to x0.  Threads past the grown tile
     // (w + 4S columns; fewer than BX + 4S on a narrow last tile) duplicate
-    // its last column: they load and write the same values as the owner and
-    // do no stage work.  act: owns tile column x0 + cxo.
+    // its last column: they load what its owner loads, write their LDS values
+    // to the padding column and store nothing.  act: owns tile column x0 + cxo.
     const int hl = l - C;  // lane in the last wavefront
     const int craw = l < C ? l : (hl < 2 * S ? hl - 2 * S : C + hl - 2 * S);
     const bool dup = craw > w + 2 * S - 1;
@@ -745,8 +745,8 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     // (each range is the next one's reach plus one column on each side), and
     // a duplicate thread writes its LDS values to the padding column.
     const int gcol = wrap_idx(x0 + cxo, a.nx);
-    const int j = cxo + 2 * S + 1;                         // reads
-    const int jw = dup ? TileSLds<BX, S>::W - 1 : j;  // writes
+    const int j = cxo + 2 * S + 1;                    // LDS column read
+    const int jw = dup ? TileSLds<BX, S>::W - 1 : j;  // LDS column written
     // A strip marched downward is computed in the mirrored frame y -> -y:
     // populations are read from and written to the planes of their mirror
     // images and the y velocity changes sign, so the march always runs
