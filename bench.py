@@ -378,7 +378,7 @@ def main():
     ap.add_argument("--precision", default="f32")
     ap.add_argument("--forms", default="f32_f16store,f32_bf16store",
                     help="extra storage forms timed on the same workload ('' for none)")
-    ap.add_argument("--cpu-steps", type=int, default=12, help="oracle steps for the CPU baseline (0: skip)")
+    ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-single-core", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
