@@ -145,12 +145,13 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     return out
 
 
-def batch_leg(lbac, torch, W, count, seed, step_cap):
+def batch_leg(lbac, torch, W, count, seed, step_cap, shape=None):
     """The batched form on the seeded instance list (sides 128..512, eps in
     {0.5, 1, 2}, tau in [0.6, 1]; half single vortex, half slotted disk under
     rotation), every instance advanced min(its run length, step_cap) steps in
     one persistent launch, against the same list advanced one instance after
-    another through lbac_step (default launch shape, HIP-graph replay)."""
+    another through lbac_step (default launch shape, HIP-graph replay).
+    shape: (strip height, workgroups) of the batched launch, else autotuned."""
     cases = W.batch_cases(count=count, seed=seed)
     phis = [W.initial_field(c) for c in cases]
     steps = [min(c["steps"], step_cap) for c in cases]
@@ -158,7 +159,10 @@ def batch_leg(lbac, torch, W, count, seed, step_cap):
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     b = lbac.Batch(cases, phis, stream=stream.cuda_stream)
-    b.autotune(4)  # dry runs: the instances' state is kept
+    if shape:
+        b.set_shape(*shape)
+    else:
+        b.autotune(4)  # dry runs of one pass each: the instances' state is kept
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -382,6 +386,7 @@ def main():
     ap.add_argument("--cpu-single-core", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
+    ap.add_argument("--batch-shape", default="", help="strip_h,workgroups of the batched leg (default: autotune)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--c1-steps", type=int, default=2000, help="steps (= period) of the 64^2 FP64 run (0: skip)")
@@ -487,7 +492,8 @@ def main():
     batched = None
     if args.batch > 0:
         print("bench: batched form, %d instances" % args.batch, file=sys.stderr, flush=True)
-        batched = batch_leg(lbac, torch, W, args.batch, 0, args.batch_steps)
+        bshape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
+        batched = batch_leg(lbac, torch, W, args.batch, 0, args.batch_steps, shape=bshape)
     closure = None
     if args.closure_steps > 0:
         print("bench: closure", file=sys.stderr, flush=True)
