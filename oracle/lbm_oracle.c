@@ -93,7 +93,11 @@ enum {
     MUT_NO_CLIP = 6,         /* psi from the unclipped phi (|.| inside the log) */
     MUT_VEL_SWAP = 7,        /* u and v exchanged */
     MUT_FEQ_NO_U = 8,        /* velocity term dropped from Eq. (10) */
-    MUT_DIAG_WEIGHT = 9      /* diagonal weight 1/36 replaced by 1/18 in the collision */
+    MUT_DIAG_WEIGHT = 9,     /* diagonal weight 1/36 replaced by 1/18 in the collision */
+    MUT_CONV_WIDTH4 = 10,    /* conventional model: 4 phi (1 - phi) / eps, the paper's width, under the Jain width */
+    MUT_CONV_NORMAL_PSI = 11, /* conventional model: normal taken from grad psi instead of grad phi */
+    MUT_CLOSURE_NO_CS2 = 12, /* closure correction added to the bracket of Eq. (11) without the c_s^2 factor */
+    MUT_CLOSURE_STENCIL_T = 13 /* closure input neighbourhood transposed (dx outer, dy inner) */
 };
 
 int orc_nparam(void) { return MLP_NPARAM; }
@@ -253,7 +257,7 @@ void orc_flux(const orc_params* p, const double* phi, int nx, int ny, double* fx
     }
 #pragma omp parallel for schedule(static)
     for (size_t k = 0; k < n; ++k) {
-        if (p->model == MODEL_CONVENTIONAL)
+        if (p->model == MODEL_CONVENTIONAL && p->mutation != MUT_CONV_NORMAL_PSI)
             src[k] = phi[k];
         else if (p->mutation == MUT_NO_CLIP)
             src[k] = p->eps * log((phi[k] + p->delta) / (1.0 - phi[k] + p->delta));
@@ -272,6 +276,7 @@ void orc_flux(const orc_params* p, const double* phi, int nx, int ny, double* fx
         double nxv = gx[k] / (mag + p->delta), nyv = gy[k] / (mag + p->delta);
         double S = p->model == MODEL_CONVENTIONAL ? orc_sharpen_conventional(phi[k], p->eps, p->reading)
                                                   : orc_sharpen(src[k], p->eps, p->reading);
+        if (p->model == MODEL_CONVENTIONAL && p->mutation == MUT_CONV_WIDTH4) S *= 4.0;
         fx[k] = S * nxv;
         fy[k] = S * nyv;
     }
@@ -295,7 +300,12 @@ void orc_closure_field(const orc_params* p, const double* phi, int nx, int ny, d
             double in[MLP_IN], out[MLP_OUT];
             int m = 0;
             for (int dy = -2; dy <= 2; ++dy)
-                for (int dx = -2; dx <= 2; ++dx) in[m++] = phi[(size_t)wrap(j + dy, ny) * nx + wrap(i + dx, nx)];
+                for (int dx = -2; dx <= 2; ++dx) {
+                    if (p->mutation == MUT_CLOSURE_STENCIL_T)
+                        in[m++] = phi[(size_t)wrap(j + dx, ny) * nx + wrap(i + dy, nx)];
+                    else
+                        in[m++] = phi[(size_t)wrap(j + dy, ny) * nx + wrap(i + dx, nx)];
+                }
             orc_mlp(p->mlp, in, out);
             cxo[k] = out[0];
             cyo[k] = out[1];
@@ -381,6 +391,10 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
                 /* bracket of Eq. (11): d_t(phi u) (explicit Euler) + c_s^2 (S n + c) */
                 double gx = dtw * (phu - pux[k]) + CS2 * (sgn * fxs[k] + ccx[k]);
                 double gy = dtw * (phv - puy[k]) + CS2 * (sgn * fys[k] + ccy[k]);
+                if (p->mutation == MUT_CLOSURE_NO_CS2) {
+                    gx += (1.0 - CS2) * ccx[k];
+                    gy += (1.0 - CS2) * ccy[k];
+                }
                 double fe[9], F[9];
                 orc_feq(phi[k], p->mutation == MUT_FEQ_NO_U ? 0.0 : u, p->mutation == MUT_FEQ_NO_U ? 0.0 : v, fe);
                 orc_forcing(gx, gy, F);

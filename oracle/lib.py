@@ -15,6 +15,9 @@ VEL_ZERO, VEL_VORTEX, VEL_ROTATION, VEL_UNIFORM, VEL_VORTEX_PAPER = range(5)
 # planted mistakes for pin-sensitivity tests (see the MUT_* list in lbm_oracle.c)
 MUTATIONS = {"drop_dt_phiu": 1, "no_force_factor": 2, "flux_sign": 3, "grad_swap": 4, "stream_back": 5,
              "no_clip": 6, "vel_swap": 7, "feq_no_u": 8, "diag_weight": 9}
+# planted mistakes in the conventional model (Eq. (1)) and in the closure hook
+MUTATIONS_CONVENTIONAL = {"conv_width4": 10, "conv_normal_psi": 11}
+MUTATIONS_CLOSURE = {"closure_no_cs2": 12, "closure_stencil_t": 13}
 READ_JAIN, READ_LITERAL, READ_LIANG = range(3)
 MODEL_IMPROVED, MODEL_CONVENTIONAL = range(2)
 
