@@ -214,18 +214,21 @@ void* lbac_stream(lbac_ctx* h);
 
 /* ---- batched form --------------------------------------------------------
  * Many independent lattices (instances) of uneven sizes and parameters
- * advanced together by ONE persistent kernel launch, replayed from a captured
- * HIP graph.  Work is split into (instance, 128-column block, strip) items
- * assigned to resident workgroups longest-first.  An item takes three steps
- * per pass (the populations between them kept in LDS, as with
- * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes) and
- * waits for its eight neighbours of the previous pass through per-item
- * progress counters (no grid-wide barrier), so instances retire
- * independently.  Every instance uses
- * FP32 collide and storage and the improved model; results are bitwise those
- * of lbac_step on the same instance.  Requires the GPU to itself (all
- * workgroups resident); a wait that exceeds the time-out makes every
- * workgroup exit and the run return LBAC_EDEVICE. */
+ * advanced together by ONE persistent kernel launch (plus one for the last
+ * nsteps mod 3 steps), replayed from a captured HIP graph.  Work is split
+ * into (instance, column tile of at most 224 columns, strip of rows) items.
+ * An item takes three steps per pass (the populations between them kept in
+ * LDS, as with LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step
+ * passes).  The (pass, item) slots are numbered pass by pass and workgroups
+ * take them one at a time from an atomic counter; a slot waits, through
+ * per-item progress counters, for the previous pass of its own item and of
+ * the items its read region overlaps (no grid-wide barrier), so instances
+ * retire independently.  Every slot waited for has a smaller number and is
+ * held by a running workgroup or done, so the schedule progresses whatever
+ * number of workgroups the device keeps resident.  Every instance uses FP32
+ * collide and storage and the improved model; results are bitwise those of
+ * lbac_step on the same instance.  A wait that exceeds the time-out makes
+ * every workgroup exit and the run return LBAC_EDEVICE. */
 typedef struct lbac_batch lbac_batch;
 
 /* params[k], phi0[k] (host, ny*nx doubles): instance k, k < count.  The stream
@@ -237,7 +240,9 @@ int lbac_batch_free(lbac_batch* b);
 
 /* Advances instance k by nsteps[k] >= 0 steps (host array of count values) in
  * one persistent launch.  Synchronous.  LBAC_EDEVICE if a dependency wait
- * timed out (state then undefined). */
+ * timed out: some passes have then overwritten both buffers of some
+ * instances, so the batch and every instance context return LBAC_ESTATE from
+ * then on (lbac_batch_free still works). */
 int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 
 /* Context of instance k, owned by the batch: use it with lbac_phi, lbac_mass,
@@ -246,8 +251,8 @@ int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
 int lbac_batch_count(lbac_batch* b, int32_t* count);
 
-/* Strip height (rows per item, >= 8) and workgroup count (0: the occupancy
- * limit, which is also the maximum). */
+/* Strip height (rows per item, >= 8) and workgroup count (0: as many as the
+ * device keeps resident, which is also the maximum). */
 int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups);
 int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, int32_t* max_workgroups);
 
@@ -261,6 +266,24 @@ int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms);
  * can be tested: each workgroup exits after `seconds`. */
 int lbac_batch_set_timeout(lbac_batch* b, double seconds, int32_t test_stall);
 const char* lbac_batch_last_error(lbac_batch* b);
+
+/* Host-only check of the batched schedule (no GPU involved): builds the items,
+ * dependency lists and slot tables the library would build for count
+ * instances of nx[k] x ny[k] nodes advanced by nsteps[k] steps with strips of
+ * strip_h rows, and runs a slot protocol on the CPU with `workers`
+ * workgroups running at once and their actions interleaved at random (seed).
+ * protocol 0: the library's (pass-major slot numbers from one counter, waits
+ * for the previous pass of the dependencies); 1: the same without the waits;
+ * 2: fixed item lists of 2 * workers workgroups, each walked pass by pass, of
+ * which only `workers` run at once (the two others exist to show that the
+ * check detects what goes wrong with them).
+ * *verdict: 0 = every slot ran and every slot read only tiles holding the
+ * previous pass while no running slot wrote them; 1 = deadlock (no workgroup
+ * could act before the end); 2 = a read or write hazard.  *slots_run (may be
+ * NULL) gets the number of slots run.  LBAC_EINVAL for bad sizes. */
+int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_t* nsteps, int32_t count,
+                              int32_t strip_h, int32_t workers, int32_t protocol, uint64_t seed, int32_t* verdict,
+                              int64_t* slots_run);
 
 /* Text of a status code, and of the last failure of a context. */
 const char* lbac_strerror(int code);

@@ -263,57 +263,69 @@ hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     }
 }
 
-// Steps one launch takes: S with the S-step variants (FP32 storage, closure
-// off), else 1.
+// Steps one launch takes: S with the S-step variants (FP32 or shifted 16-bit
+// storage, closure off), else 1.
 int launch_steps_of(const lbac_ctx* h) {
-    if (h->closure || h->p.precision != LBAC_F32) return 1;
+    if (h->closure || h->p.precision == LBAC_F64) return 1;
     return h->variant == LBAC_KERNEL_FUSED2 ? 2 : (h->variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
 }
 
 // One S-step launch with tile width BX.
-template <int MODEL, int S, int BX>
+template <int MODEL, int S, int ST, int BX>
 hipError_t launch_stepS_shape(StepArgs a, hipStream_t s) {
     a.nbx = (a.nx + BX - 1) / BX;
     const dim3 grid(a.nbx * a.nby);
-    hipLaunchKernelGGL((stepS_kernel_lds<MODEL, BX, S>), grid, dim3(stepS_threads<BX, S>()), 0, s, a);
+    hipLaunchKernelGGL((stepS_kernel_lds<MODEL, BX, S, ST>), grid, dim3(stepS_threads<BX, S>()), 0, s, a);
     return hipGetLastError();
 }
 
-template <int MODEL, int S>
+template <int MODEL, int S, int ST>
 hipError_t launch_stepS_m(StepArgs a, int bx, hipStream_t s) {
     a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
     a.n_xcd = kXcds;
     switch (bx) {
     case 64:
-        return launch_stepS_shape<MODEL, S, 64>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 64>(a, s);
     case 96:
-        return launch_stepS_shape<MODEL, S, 96>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 96>(a, s);
     case 128:
-        return launch_stepS_shape<MODEL, S, 128>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 128>(a, s);
     case 160:
-        return launch_stepS_shape<MODEL, S, 160>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 160>(a, s);
     case 192:
-        return launch_stepS_shape<MODEL, S, 192>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 192>(a, s);
     case 224:
-        return launch_stepS_shape<MODEL, S, 224>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 224>(a, s);
     case 288:
-        return launch_stepS_shape<MODEL, S, 288>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 288>(a, s);
     case 320:
-        return launch_stepS_shape<MODEL, S, 320>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 320>(a, s);
     default:
-        return launch_stepS_shape<MODEL, S, 256>(a, s);
+        return launch_stepS_shape<MODEL, S, ST, 256>(a, s);
     }
+}
+
+template <int ST>
+hipError_t launch_stepS_st(const lbac_ctx* h, const StepArgs& a, int S) {
+    const bool conv = h->p.model == LBAC_MODEL_CONVENTIONAL;
+    if (S == 3)
+        return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 3, ST>(a, h->bx, h->stream)
+                    : launch_stepS_m<MODEL_IMPROVED, 3, ST>(a, h->bx, h->stream);
+    return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 2, ST>(a, h->bx, h->stream)
+                : launch_stepS_m<MODEL_IMPROVED, 2, ST>(a, h->bx, h->stream);
 }
 
 // Steps k .. k + S - 1 of the current run in one launch, from pop[src] into pop[1 - src].
 hipError_t launch_stepS(const lbac_ctx* h, int src, int32_t k, int S) {
     const StepArgs a = make_args(h, src, k);
-    const bool conv = h->p.model == LBAC_MODEL_CONVENTIONAL;
-    if (S == 3)
-        return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 3>(a, h->bx, h->stream)
-                    : launch_stepS_m<MODEL_IMPROVED, 3>(a, h->bx, h->stream);
-    return conv ? launch_stepS_m<MODEL_CONVENTIONAL, 2>(a, h->bx, h->stream)
-                : launch_stepS_m<MODEL_IMPROVED, 2>(a, h->bx, h->stream);
+    switch (h->p.precision) {
+    case LBAC_F32_F16STORE:
+        return launch_stepS_st<ST_F16>(h, a, S);
+    case LBAC_F32_BF16STORE:
+        return launch_stepS_st<ST_BF16>(h, a, S);
+    default:
+        return launch_stepS_st<ST_PLAIN>(h, a, S);
+    }
 }
 
 // Queues `n` steps starting at offset k0 of the current run from pop[src]:
@@ -350,7 +362,10 @@ hipError_t launch_aux_t(const lbac_ctx* h, int which, const StepArgs& a, double*
         hipLaunchKernelGGL((phi_kernel<R, ST>), g2, dim3(256), 0, h->stream, a, out);
         break;
     default:
-        hipLaunchKernelGGL((row_sums_kernel<R, ST>), dim3(a.ny), dim3(kRedThreads), 0, h->stream, a, ref, h->rows);
+        hipLaunchKernelGGL((row_sums_kernel<R, ST>), dim3(a.ny), dim3(kRedThreads), 0, h->stream, a, ref,
+                           static_cast<R*>(h->rows));
+        hipLaunchKernelGGL((reduce_rows_kernel<R>), dim3(1), dim3(kRedThreads), 0, h->stream,
+                           static_cast<const R*>(h->rows), a.ny, h->red5);
         break;
     }
     return hipGetLastError();
@@ -470,7 +485,7 @@ int lbac_host::create(const lbac_params* p, const double* phi0, bool phi0_on_dev
     h->vtabf = (float*)dev_alloc(h, tab.size() * sizeof(float));
     std::vector<float> tabf(tab.begin(), tab.end());
     h->t_dev = (int64_t*)dev_alloc(h, 64);
-    h->rows = (double*)dev_alloc(h, 5 * sizeof(double) * (size_t)p->ny);
+    h->rows = dev_alloc(h, 10 * sizeof(double) * (size_t)p->ny);  // five compensated pairs per row
     h->red5 = (double*)dev_alloc(h, 64);
     h->dtmp = (double*)dev_alloc(h, n * sizeof(double));
     if (!h->vtab || !h->vtabf || !h->t_dev || !h->rows || !h->red5 || !h->dtmp) return bail(LBAC_ENOMEM);
@@ -541,8 +556,6 @@ int capture_graph(lbac_ctx* h, int parity) {
 int reduce5(lbac_ctx* h, const double* ref_dev) {
     StepArgs a = make_args(h, h->cur, 0);
     HIPCHK(h, launch_aux(h, 2, a, nullptr, ref_dev, nullptr));
-    hipLaunchKernelGGL(reduce_rows_kernel, dim3(1), dim3(kRedThreads), 0, h->stream, h->rows, h->p.ny, h->red5);
-    HIPCHK(h, hipGetLastError());
     HIPCHK(h, hipMemcpyAsync(h->host5, h->red5, 5 * sizeof(double), hipMemcpyDeviceToHost, h->stream));
     HIPCHK(h, hipStreamSynchronize(h->stream));
     return LBAC_OK;
@@ -584,6 +597,7 @@ int lbac_free(lbac_ctx* h) {
 
 int lbac_step(lbac_ctx* h, int64_t n) {
     if (!h) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     if (n < 0) return fail(h, LBAC_EINVAL, "negative step count");
     DeviceGuard g(h->device);
     if (!g.ok) return fail(h, LBAC_EDEVICE, "hipSetDevice failed");
@@ -612,6 +626,7 @@ int lbac_step(lbac_ctx* h, int64_t n) {
 
 int lbac_phi_device(lbac_ctx* h, double* out_device) {
     if (!h || !out_device) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
     StepArgs a = make_args(h, h->cur, 0);
     HIPCHK(h, launch_aux(h, 1, a, out_device, nullptr, nullptr));
@@ -620,6 +635,7 @@ int lbac_phi_device(lbac_ctx* h, double* out_device) {
 
 int lbac_phi(lbac_ctx* h, double* out) {
     if (!h || !out) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
     int rc = lbac_phi_device(h, h->dtmp);
     if (rc != LBAC_OK) return rc;
@@ -631,6 +647,7 @@ int lbac_phi(lbac_ctx* h, double* out) {
 
 int lbac_mass(lbac_ctx* h, double* out) {
     if (!h || !out) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
     int rc = reduce5(h, nullptr);
     if (rc != LBAC_OK) return rc;
@@ -641,6 +658,7 @@ int lbac_mass(lbac_ctx* h, double* out) {
 
 int lbac_shape_error(lbac_ctx* h, const double* ref, double* e1, double* e2) {
     if (!h || !ref) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
     const size_t n = (size_t)h->p.nx * h->p.ny;
     HIPCHK(h, hipMemcpyAsync(h->dtmp, ref, n * sizeof(double), hipMemcpyHostToDevice, h->stream));
@@ -662,6 +680,7 @@ int lbac_time(lbac_ctx* h, int64_t* t) {
 
 int lbac_get_state(lbac_ctx* h, void* buf, size_t* bytes) {
     if (!h || !bytes) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     const size_t plane = (size_t)h->pitch * h->p.ny * h->elem_bytes;
     const size_t phib = h->storage == ST_PLAIN ? 0 : (size_t)h->pitch * h->p.ny * sizeof(float);
     const size_t need = 64 + plane * h->nplanes + phib;
@@ -691,6 +710,7 @@ int lbac_get_state(lbac_ctx* h, void* buf, size_t* bytes) {
 
 int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
     if (!h || !buf) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     const size_t plane = (size_t)h->pitch * h->p.ny * h->elem_bytes;
     const size_t phib = h->storage == ST_PLAIN ? 0 : (size_t)h->pitch * h->p.ny * sizeof(float);
     const size_t need = 64 + plane * h->nplanes + phib;
@@ -721,8 +741,8 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes) {
 int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     if (!h) return LBAC_EINVAL;
     if (variant < LBAC_KERNEL_BLOCK || variant > LBAC_KERNEL_FUSED3) return fail(h, LBAC_EINVAL, "unknown kernel variant");
-    if ((variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3) && h->p.precision != LBAC_F32)
-        return fail(h, LBAC_EINVAL, "the multi-step variants need LBAC_F32 storage");
+    if ((variant == LBAC_KERNEL_FUSED2 || variant == LBAC_KERNEL_FUSED3) && h->p.precision == LBAC_F64)
+        return fail(h, LBAC_EINVAL, "the multi-step variants need FP32 collision (LBAC_F32 or a 16-bit storage)");
     const int S = variant == LBAC_KERNEL_FUSED2 ? 2 : (variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
     if (!(S == 1 ? one_step_bx(bx) : stepS_bx(bx)))
         return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256 (with the multi-step variants any multiple of 32 from "
@@ -745,6 +765,7 @@ int lbac_get_launch(lbac_ctx* h, int32_t* variant, int32_t* bx, int32_t* strip_h
 
 int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     if (!h || steps < 1) return LBAC_EINVAL;
+    if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
     const int bxs[9] = {64, 96, 128, 160, 192, 224, 256, 288, 320};
     // strip heights: multiples of 8 up to 256 and powers of two up to 512 (the
@@ -765,7 +786,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    const int last_var = h->p.precision == LBAC_F32 && !h->closure ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
+    const int last_var = h->p.precision != LBAC_F64 && !h->closure ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
     for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
         const int S = var == LBAC_KERNEL_FUSED2 ? 2 : (var == LBAC_KERNEL_FUSED3 ? 3 : 1);

@@ -345,7 +345,7 @@ __global__ void phi3_kernel(Args3 a, double* __restrict__ out) {
 __global__ __launch_bounds__(lbac::kRedThreads) void sum5_kernel(const double* __restrict__ phi,
                                                                  const double* __restrict__ ref, int64_t n,
                                                                  int64_t chunk, double* __restrict__ part) {
-    __shared__ double sh[lbac::kRedThreads / 64];
+    __shared__ double sh[2 * lbac::kRedThreads / 64];
     const int64_t b = (int64_t)blockIdx.x * chunk, e = min(b + chunk, n);
     double v[5] = {0, 0, 0, 0, 0};
     for (int64_t i = b + threadIdx.x; i < e; i += blockDim.x) {
@@ -360,7 +360,9 @@ __global__ __launch_bounds__(lbac::kRedThreads) void sum5_kernel(const double* _
         }
     }
     for (int c = 0; c < 5; ++c) {
-        const double r = lbac::block_sum(v[c], sh);
+        lbac::CompSum<double> acc;
+        acc.s = v[c];
+        const double r = lbac::block_sum(acc, sh).value();
         if (threadIdx.x == 0) part[5 * (int64_t)blockIdx.x + c] = r;
     }
 }

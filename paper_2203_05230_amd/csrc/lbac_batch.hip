@@ -1,18 +1,21 @@
 // Batched form: many independent lattices advanced by one persistent kernel
-// launch, replayed from a captured HIP graph (see batch_kernel in
-// lbac_kernels.hpp for the dependency protocol).
+// launch per run phase, replayed from a captured HIP graph (see batch_kernel
+// in lbac_batch_kernels.hpp for the slot schedule and its dependency rule).
 //
-// Host side: the work list of (instance, 128-column block, strip) items, a
-// longest-processing-time-first assignment of items to workgroups (work =
-// nodes x steps), occupancy-limited workgroup count so that every workgroup
-// is resident, graph capture of reset -> persistent kernel -> time advance,
-// and an autotuner over the strip height and the workgroup count.
+// Host side: the work list of (instance, column tile, strip) items with their
+// dependency lists, the pass-major slot tables of the two launches, graph
+// capture of reset -> full passes -> reset -> one-step passes -> time
+// advance, and an autotuner over the strip height and the workgroup count.
+// It also exports a host-only check of the schedule (lbac_batch_schedule_check)
+// that runs the kernel's slot protocol on the CPU with a bounded number of
+// concurrently running workgroups.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <numeric>
-#include <queue>
+#include <random>
 #include <string>
 #include <vector>
 
@@ -22,36 +25,145 @@
 using namespace lbac;
 using namespace lbac_host;
 
-// rows per strip at least: a pass reads kBatchGrow rows beyond its strip on
-// each side, and the neighbour lists hold at most four strips per axis
+namespace {
+
+// Rows per strip at least (a shorter last strip of an instance is allowed).
 constexpr int kBatchMinStrip = kBatchGrow + 2;
+
+struct Geometry {
+    int nx, ny;
+};
+
+// An item of the schedule (host form).
+struct ItemH {
+    int inst, x0, w, ys, hh, down;
+    std::vector<int32_t> dep;  // itself first, then the items overlapping its read region
+};
+
+// Column tiles of an instance nx columns wide: widths that are multiples of 32
+// columns (so every tile starts on a 128-byte line), at most kBatchTile, the
+// last one ragged; chosen to minimise the wavefronts that run per row
+// (ceil((w + 4S) / 64) per tile), then the number of tiles, the widest tiles
+// first.
+std::vector<std::pair<int, int>> column_tiles(int nx) {
+    constexpr int U = 32;
+    const int n = (nx + U - 1) / U;
+    std::vector<std::pair<int, int>> best(n + 1, {INT_MAX, INT_MAX});
+    std::vector<int> next(n + 1, n);
+    best[n] = {0, 0};
+    for (int c = n - 1; c >= 0; --c)
+        for (int k = std::min(kBatchTile / U, n - c); k >= 1; --k) {
+            const int w = std::min(nx, (c + k) * U) - c * U;
+            const std::pair<int, int> cand(best[c + k].first + (w + 4 * kBatchS + 63) / 64, best[c + k].second + 1);
+            if (cand < best[c]) {
+                best[c] = cand;
+                next[c] = c + k;
+            }
+        }
+    std::vector<std::pair<int, int>> t;
+    for (int c = 0; c < n; c = next[c]) t.push_back({c * U, std::min(nx, next[c] * U) - c * U});
+    return t;
+}
+
+// Items of every instance (instance-major, strips, tiles) and their dependency
+// lists: an item depends on itself and on every item of its instance whose
+// tile overlaps its read region, columns x0 - G .. x0 + w - 1 + G and rows
+// ys - G .. ys + hh - 1 + G (G = kBatchGrow, periodic).  Returns false if an
+// item would need more than kBatchDeps entries.
+bool build_items(const std::vector<Geometry>& geo, int strip_h, std::vector<ItemH>& items) {
+    constexpr int G = kBatchGrow;
+    items.clear();
+    for (int k = 0; k < (int)geo.size(); ++k) {
+        const int nx = geo[k].nx, ny = geo[k].ny;
+        const std::vector<std::pair<int, int>> ct = column_tiles(nx);
+        const int sh = std::max(1, std::min(strip_h, ny));
+        const int nby = (ny + sh - 1) / sh, nbx = (int)ct.size();
+        std::vector<int> tile_of_col(nx), strip_of_row(ny);
+        for (int i = 0; i < nbx; ++i)
+            for (int c = ct[i].first; c < ct[i].first + ct[i].second; ++c) tile_of_col[c] = i;
+        for (int r = 0; r < ny; ++r) strip_of_row[r] = r / sh;
+        const int base = (int)items.size();
+        for (int j = 0; j < nby; ++j)
+            for (int i = 0; i < nbx; ++i) {
+                ItemH it;
+                it.inst = k;
+                it.x0 = ct[i].first;
+                it.w = ct[i].second;
+                it.ys = j * sh;
+                it.hh = std::min(sh, ny - j * sh);
+                it.down = j & 1;
+                std::vector<int> tx, ty;
+                for (int c = it.x0 - G; c <= it.x0 + it.w - 1 + G; ++c) tx.push_back(tile_of_col[((c % nx) + nx) % nx]);
+                for (int r = it.ys - G; r <= it.ys + it.hh - 1 + G; ++r) ty.push_back(strip_of_row[((r % ny) + ny) % ny]);
+                std::sort(tx.begin(), tx.end());
+                tx.erase(std::unique(tx.begin(), tx.end()), tx.end());
+                std::sort(ty.begin(), ty.end());
+                ty.erase(std::unique(ty.begin(), ty.end()), ty.end());
+                it.dep.push_back(base + j * nbx + i);
+                for (int jj : ty)
+                    for (int ii : tx)
+                        if (ii != i || jj != j) it.dep.push_back(base + jj * nbx + ii);
+                if ((int)it.dep.size() > kBatchDeps) return false;
+                items.push_back(std::move(it));
+            }
+    }
+    return true;
+}
+
+// Pass-major slot tables of a launch: items ordered by decreasing passes
+// (stable), cum[p] = first slot of pass p, cum[npass] = slot count.
+void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, std::vector<int32_t>& order,
+                 std::vector<int64_t>& cum) {
+    const int n = (int)items.size();
+    order.resize(n);
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(),
+                     [&](int a, int b) { return passes[items[a].inst] > passes[items[b].inst]; });
+    int64_t npass = 0;
+    for (int64_t p : passes) npass = std::max(npass, p);
+    cum.assign(npass + 1, 0);
+    // items with pass p: those whose instance has more than p passes
+    std::vector<int64_t> cnt(npass + 1, 0);
+    for (const ItemH& it : items) cnt[passes[it.inst]] += 1;  // count per exact pass count
+    int64_t with_more = n;  // items whose instance has > p passes, for p = 0
+    for (int64_t p = 0; p < npass; ++p) {
+        with_more -= cnt[p];  // drop the items with exactly p passes
+        cum[p + 1] = cum[p] + with_more;
+    }
+}
+
+}  // namespace
 
 struct lbac_batch {
     int device = 0;
     hipStream_t stream = nullptr;
     bool own_stream = false;
     std::vector<lbac_ctx*> inst;
-    int strip_h = 32;  // >= kBatchMinStrip
+    int strip_h = 40;   // >= kBatchMinStrip
     int wgs = 0;        // 0: occupancy limit
     int max_wgs = 0;    // occupancy limit (resident workgroups)
     double ticks_per_s = 1e8;
     double timeout_s = 20.0;
     int test_stall = 0;
+    bool failed = false;  // a run timed out: the state is undefined until the instances are set again
     // schedule
+    int items_h = -1;  // strip height the item list was built for
+    std::vector<ItemH> items;
     int nitems = 0, nwg = 0;
-    std::vector<BatchItem> items;
-    std::vector<int64_t> item_nodes;
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
-    int32_t* d_wg_off = nullptr;
-    int32_t* d_wg_items = nullptr;
+    int32_t* d_order[2] = {nullptr, nullptr};
+    int64_t* d_cum[2] = {nullptr, nullptr};
     int32_t* d_done = nullptr;
     BatchCtl* d_ctl = nullptr;
-    BatchCtl* h_ctl = nullptr;  // pinned
+    BatchCtl* h_ctl = nullptr;    // pinned
     BatchInst* h_inst = nullptr;  // pinned
-    int cap_items = 0, cap_wg = 0;
+    int32_t* d_npass = nullptr;   // passes of the two launches (read by the kernels)
+    int32_t* h_npass = nullptr;   // pinned
+    int cap_items = 0;
+    int64_t cap_cum[2] = {0, 0};
     hipGraphExec_t gexec = nullptr;
-    int g_nwg = -1, g_nitems = -1;
+    int g_nwg = -1;
     std::string err;
 };
 
@@ -71,18 +183,23 @@ int bfail(lbac_batch* b, int code, const std::string& msg) {
 void drop_graph(lbac_batch* b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
-    b->g_nwg = b->g_nitems = -1;
+    b->g_nwg = -1;
 }
 
 void free_tables(lbac_batch* b) {
     drop_graph(b);
     (void)hipFree(b->d_items);
-    (void)hipFree(b->d_wg_off);
-    (void)hipFree(b->d_wg_items);
     (void)hipFree(b->d_done);
     b->d_items = nullptr;
-    b->d_wg_off = b->d_wg_items = b->d_done = nullptr;
-    b->cap_items = b->cap_wg = 0;
+    b->d_done = nullptr;
+    b->cap_items = 0;
+    for (int L = 0; L < 2; ++L) {
+        (void)hipFree(b->d_order[L]);
+        (void)hipFree(b->d_cum[L]);
+        b->d_order[L] = nullptr;
+        b->d_cum[L] = nullptr;
+        b->cap_cum[L] = 0;
+    }
 }
 
 void release(lbac_batch* b) {
@@ -90,8 +207,10 @@ void release(lbac_batch* b) {
     free_tables(b);
     (void)hipFree(b->d_inst);
     (void)hipFree(b->d_ctl);
+    (void)hipFree(b->d_npass);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
+    if (b->h_npass) (void)hipHostFree(b->h_npass);
     for (lbac_ctx* c : b->inst) {
         if (c) {
             c->in_batch = false;
@@ -102,113 +221,64 @@ void release(lbac_batch* b) {
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// Work items and their neighbour lists for the current strip height.  The
-// neighbours of an item are the items whose tiles overlap its read region,
-// columns x0-G .. x0+w-1+G and rows ys-G .. ys+hh-1+G (G = kBatchGrow,
-// periodic).
-void build_items(lbac_batch* b) {
-    constexpr int W = kBatchTile, G = kBatchGrow;
-    b->items.clear();
-    b->item_nodes.clear();
-    for (int k = 0; k < (int)b->inst.size(); ++k) {
-        const lbac_ctx* c = b->inst[k];
-        const int nx = c->p.nx, ny = c->p.ny;
-        const int sh = std::min(b->strip_h, ny);
-        const int nbx = (nx + W - 1) / W, nby = (ny + sh - 1) / sh;
-        const int base = (int)b->items.size();
-        for (int j = 0; j < nby; ++j)
-            for (int i = 0; i < nbx; ++i) {
-                const int w = std::min(W, nx - i * W), h = std::min(sh, ny - j * sh);
-                std::vector<int> tx, ty;
-                for (int cx = i * W - G; cx <= i * W + w - 1 + G; ++cx) tx.push_back(((cx % nx) + nx) % nx / W);
-                for (int ry = j * sh - G; ry <= j * sh + h - 1 + G; ++ry) ty.push_back(((ry % ny) + ny) % ny / sh);
-                std::sort(tx.begin(), tx.end());
-                tx.erase(std::unique(tx.begin(), tx.end()), tx.end());
-                std::sort(ty.begin(), ty.end());
-                ty.erase(std::unique(ty.begin(), ty.end()), ty.end());
-                std::vector<int32_t> nb;
-                for (int jj : ty)
-                    for (int ii : tx)
-                        if (ii != i || jj != j) nb.push_back(base + jj * nbx + ii);
-                BatchItem it{};
-                it.inst = k;
-                it.bxi = i;
-                it.syi = j;
-                it.down = j & 1;
-                // at most 4 tiles per axis (strips are at least G + 2 rows high and
-                // tiles 128 columns wide; only the last tile or strip can be narrower)
-                for (int m = 0; m < 16; ++m) it.nbr[m] = nb.empty() ? base + j * nbx + i : nb[m % nb.size()];
-                b->items.push_back(it);
-                b->item_nodes.push_back((int64_t)w * h);
-            }
-    }
-    b->nitems = (int)b->items.size();
-}
-
-// Longest processing time first: items by work (nodes x steps), each to the
-// least loaded workgroup; each workgroup then walks its items in id order.
-void lpt(const lbac_batch* b, const int64_t* nsteps, int nwg, std::vector<int32_t>& off, std::vector<int32_t>& list) {
-    std::vector<int> order(b->nitems);
-    std::iota(order.begin(), order.end(), 0);
-    auto work = [&](int i) { return (double)b->item_nodes[i] * (double)std::max<int64_t>(nsteps[b->items[i].inst], 1); };
-    std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return work(x) > work(y); });
-    using E = std::pair<double, int>;
-    std::priority_queue<E, std::vector<E>, std::greater<E>> pq;
-    for (int w = 0; w < nwg; ++w) pq.push({0.0, w});
-    std::vector<std::vector<int32_t>> per(nwg);
-    for (int i : order) {
-        E e = pq.top();
-        pq.pop();
-        per[e.second].push_back(i);
-        e.first += work(i);
-        pq.push(e);
-    }
-    off.assign(nwg + 1, 0);
-    list.clear();
-    for (int w = 0; w < nwg; ++w) {
-        std::sort(per[w].begin(), per[w].end());
-        off[w] = (int32_t)list.size();
-        list.insert(list.end(), per[w].begin(), per[w].end());
-    }
-    off[nwg] = (int32_t)list.size();
-}
-
-int ensure_tables(lbac_batch* b, int nwg) {
-    if (b->cap_items < b->nitems || b->cap_wg < nwg) {
-        free_tables(b);
-        const int ci = std::max(b->nitems, 1), cw = std::max(nwg, 1);
+// Device tables large enough for the items and for npass + 1 slot starts per
+// launch; a reallocation invalidates the captured graph (its kernel arguments).
+int ensure_tables(lbac_batch* b, const int64_t npass[2]) {
+    if (b->cap_items < b->nitems) {
+        drop_graph(b);
+        (void)hipFree(b->d_items);
+        (void)hipFree(b->d_done);
+        b->d_items = nullptr;
+        b->d_done = nullptr;
+        b->cap_items = 0;
+        for (int L = 0; L < 2; ++L) {
+            (void)hipFree(b->d_order[L]);
+            b->d_order[L] = nullptr;
+        }
+        const int ci = std::max(b->nitems, 1);
         BHIP(b, hipMalloc(&b->d_items, sizeof(BatchItem) * ci));
-        BHIP(b, hipMalloc(&b->d_wg_items, sizeof(int32_t) * ci));
         BHIP(b, hipMalloc(&b->d_done, sizeof(int32_t) * ci));
-        BHIP(b, hipMalloc(&b->d_wg_off, sizeof(int32_t) * (cw + 1)));
+        for (int L = 0; L < 2; ++L) BHIP(b, hipMalloc(&b->d_order[L], sizeof(int32_t) * ci));
         b->cap_items = ci;
-        b->cap_wg = cw;
     }
+    for (int L = 0; L < 2; ++L)
+        if (b->cap_cum[L] < npass[L] + 1) {
+            drop_graph(b);
+            (void)hipFree(b->d_cum[L]);
+            b->d_cum[L] = nullptr;
+            b->cap_cum[L] = 0;
+            const int64_t cc = std::max<int64_t>(npass[L] + 1, 64);
+            BHIP(b, hipMalloc(&b->d_cum[L], sizeof(int64_t) * cc));
+            b->cap_cum[L] = cc;
+        }
     return LBAC_OK;
 }
 
 int capture(lbac_batch* b) {
-    if (b->gexec && b->g_nwg == b->nwg && b->g_nitems == b->nitems) return LBAC_OK;
+    if (b->gexec && b->g_nwg == b->nwg) return LBAC_OK;
     drop_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const int count = (int)b->inst.size();
+    const int nreset = std::max(b->cap_items, 1);
     // full passes, then (counters reset, error flag kept) the one-step passes
-    hipLaunchKernelGGL(batch_reset_kernel, dim3((b->nitems + 255) / 256), dim3(256), 0, b->stream, b->d_done,
-                       b->nitems, b->d_ctl, 1);
+    hipLaunchKernelGGL(batch_reset_kernel, dim3((nreset + 255) / 256), dim3(256), 0, b->stream, b->d_done, nreset,
+                       b->d_ctl, 0, 1);
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) {
-        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3(b->nwg), dim3(block_threads<kBatchTile>()), 0,
-                           b->stream, b->d_inst, b->d_items, b->d_wg_off, b->d_wg_items, b->d_done, b->d_ctl);
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3(b->nwg), dim3(kBatchThreads), 0, b->stream,
+                           b->d_inst, b->d_items, BatchSlots{b->d_order[0], b->d_cum[0], b->d_npass}, b->d_done,
+                           b->d_ctl);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL(batch_reset_kernel, dim3((b->nitems + 255) / 256), dim3(256), 0, b->stream, b->d_done,
-                           b->nitems, b->d_ctl, 0);
+        hipLaunchKernelGGL(batch_reset_kernel, dim3((nreset + 255) / 256), dim3(256), 0, b->stream, b->d_done, nreset,
+                           b->d_ctl, 1, 0);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
-        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3(b->nwg), dim3(block_threads<kBatchTile>()), 0,
-                           b->stream, b->d_inst, b->d_items, b->d_wg_off, b->d_wg_items, b->d_done, b->d_ctl);
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3(b->nwg), dim3(kBatchThreads), 0, b->stream,
+                           b->d_inst, b->d_items, BatchSlots{b->d_order[1], b->d_cum[1], b->d_npass + 1}, b->d_done,
+                           b->d_ctl);
         e = hipGetLastError();
     }
     if (e == hipSuccess) {
@@ -226,51 +296,85 @@ int capture(lbac_batch* b) {
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(b, LBAC_EDEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));
     b->g_nwg = b->nwg;
-    b->g_nitems = b->nitems;
     return LBAC_OK;
 }
 
-// One persistent launch over all instances.  dry: steps read the current
-// state and write the scratch buffer (state and time untouched).
+void mark_failed(lbac_batch* b) {
+    b->failed = true;
+    for (lbac_ctx* c : b->inst) c->failed = true;
+}
+
+// One run over all instances.  dry: steps read the current state and write
+// the scratch buffer (state and time untouched).
 int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
+    if (b->failed) return bfail(b, LBAC_ESTATE, "a previous run timed out; the batch state is undefined");
     const int count = (int)b->inst.size();
-    int64_t max_full = 0, max_rest = 0;
-    for (int k = 0; k < count; ++k) {
+    for (int k = 0; k < count; ++k)
         if (nsteps[k] < 0 || nsteps[k] > (int64_t)INT32_MAX) return bfail(b, LBAC_EINVAL, "step count out of range");
-        max_full = std::max(max_full, nsteps[k] / kBatchS);
-        max_rest = std::max(max_rest, nsteps[k] % kBatchS);
-    }
     if (b->strip_h < kBatchMinStrip) return bfail(b, LBAC_EINVAL, "strip height too small");
-    build_items(b);
-    const int nwg = std::max(1, std::min(b->wgs > 0 ? std::min(b->wgs, b->max_wgs) : b->max_wgs, b->nitems));
+    if (b->items_h != b->strip_h) {
+        std::vector<Geometry> geo(count);
+        for (int k = 0; k < count; ++k) geo[k] = {b->inst[k]->p.nx, b->inst[k]->p.ny};
+        if (!build_items(geo, b->strip_h, b->items)) return bfail(b, LBAC_EINVAL, "item dependency list too long");
+        b->nitems = (int)b->items.size();
+        b->items_h = b->strip_h;
+    }
+    std::vector<int64_t> pf(count), pr(count);
+    int64_t npass[2] = {0, 0};
+    for (int k = 0; k < count; ++k) {
+        pf[k] = nsteps[k] / kBatchS;
+        pr[k] = nsteps[k] % kBatchS;
+        npass[0] = std::max(npass[0], pf[k]);
+        npass[1] = std::max(npass[1], pr[k]);
+    }
+    if (npass[0] > INT32_MAX) return bfail(b, LBAC_EINVAL, "too many passes");
+    const int nwg = std::max(1, b->wgs > 0 ? std::min(b->wgs, b->max_wgs) : b->max_wgs);
     b->nwg = nwg;
-    int rc = ensure_tables(b, nwg);
+    int rc = ensure_tables(b, npass);
     if (rc != LBAC_OK) return rc;
-    std::vector<int32_t> off, list;
-    lpt(b, nsteps, nwg, off, list);
+    std::vector<int32_t> order[2];
+    std::vector<int64_t> cum[2];
+    build_slots(b->items, pf, order[0], cum[0]);
+    build_slots(b->items, pr, order[1], cum[1]);
+    std::vector<BatchItem> di(b->nitems);
+    for (int i = 0; i < b->nitems; ++i) {
+        const ItemH& it = b->items[i];
+        BatchItem& d = di[i];
+        d.inst = it.inst;
+        d.x0 = it.x0;
+        d.w = it.w;
+        d.ys = it.ys;
+        d.hh = it.hh;
+        d.down = it.down;
+        for (int m = 0; m < kBatchDeps; ++m) d.dep[m] = it.dep[m % it.dep.size()];
+    }
     for (int k = 0; k < count; ++k) {
         lbac_ctx* c = b->inst[k];
         // even passes read pop[cur] and write the other buffer, odd passes the
         // reverse (a dry run reads pop[cur] on every pass)
-        StepArgs a = make_args(c, c->cur, 0);
-        a.strip_h = std::min(b->strip_h, c->p.ny);
-        StepArgs o = make_args(c, dry ? c->cur : c->cur ^ 1, 0);
-        o.strip_h = a.strip_h;
+        const StepArgs a = make_args(c, c->cur, 0);
+        const StepArgs o = make_args(c, dry ? c->cur : c->cur ^ 1, 0);
         b->h_inst[2 * k].a = a;
         b->h_inst[2 * k + 1].a = o;
         b->h_inst[2 * k].nsteps = b->h_inst[2 * k + 1].nsteps = nsteps[k];
     }
-    b->h_ctl->max_full = max_full;
-    b->h_ctl->max_rest = max_rest;
+    b->h_ctl->ticket[0] = b->h_ctl->ticket[1] = 0;
     b->h_ctl->timeout_ticks = (int64_t)(b->timeout_s * b->ticks_per_s);
     b->h_ctl->dry = dry ? 1 : 0;
     b->h_ctl->err = 0;
     b->h_ctl->test_stall = b->test_stall;
+    b->h_npass[0] = (int32_t)npass[0];
+    b->h_npass[1] = (int32_t)npass[1];
     BHIP(b, hipMemcpyAsync(b->d_inst, b->h_inst, sizeof(BatchInst) * 2 * count, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_items, b->items.data(), sizeof(BatchItem) * b->nitems, hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_wg_items, list.data(), sizeof(int32_t) * list.size(), hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_wg_off, off.data(), sizeof(int32_t) * off.size(), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_npass, b->h_npass, 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_items, di.data(), sizeof(BatchItem) * b->nitems, hipMemcpyHostToDevice, b->stream));
+    for (int L = 0; L < 2; ++L) {
+        BHIP(b, hipMemcpyAsync(b->d_order[L], order[L].data(), sizeof(int32_t) * b->nitems, hipMemcpyHostToDevice,
+                               b->stream));
+        BHIP(b, hipMemcpyAsync(b->d_cum[L], cum[L].data(), sizeof(int64_t) * cum[L].size(), hipMemcpyHostToDevice,
+                               b->stream));
+    }
     rc = capture(b);
     if (rc != LBAC_OK) return rc;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -288,7 +392,11 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
         (void)hipEventDestroy(e0);
         (void)hipEventDestroy(e1);
     }
-    if (b->h_ctl->err) return bfail(b, LBAC_EDEVICE, "batch schedule stalled: a dependency wait timed out");
+    if (b->h_ctl->err) {
+        // passes that did run have overwritten both buffers of some instances
+        if (!dry) mark_failed(b);
+        return bfail(b, LBAC_EDEVICE, "batch schedule stalled: a dependency wait timed out");
+    }
     if (!dry)
         for (int k = 0; k < count; ++k) {
             b->inst[k]->cur ^= (int)(batch_passes(nsteps[k]) & 1);  // one buffer swap per pass
@@ -334,9 +442,10 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         b->inst[k] = c;
     }
     int per_cu = 0, cus = 0, khz = 0;
-    // the multi-step launch has the lower occupancy; both launches use its grid
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<MODEL_IMPROVED, kBatchS>,
-                                                     block_threads<kBatchTile>(), 0) !=
+    // the default grid: as many workgroups as the device keeps resident (the
+    // schedule itself does not depend on residency); the multi-step launch
+    // has the lower occupancy and sets it for both
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<MODEL_IMPROVED, kBatchS>, kBatchThreads, 0) !=
             hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
         return bail(LBAC_EDEVICE);
@@ -344,8 +453,9 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         b->ticks_per_s = 1000.0 * khz;
     b->max_wgs = std::max(1, per_cu * cus);
     if (hipMalloc(&b->d_inst, sizeof(BatchInst) * 2 * count) != hipSuccess ||
-        hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess ||
+        hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess || hipMalloc(&b->d_npass, 64) != hipSuccess ||
         hipHostMalloc((void**)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_npass, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_inst, sizeof(BatchInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
         return bail(LBAC_ENOMEM);
     std::memset(b->h_ctl, 0, sizeof(BatchCtl));
@@ -398,11 +508,12 @@ int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, i
 
 int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms) {
     if (!b || steps < 1) return LBAC_EINVAL;
+    if (b->failed) return bfail(b, LBAC_ESTATE, "a previous run timed out; the batch state is undefined");
     DeviceGuard g(b->device);
     const int count = (int)b->inst.size();
     std::vector<int64_t> ns(count, steps);
     const int keep_h = b->strip_h, keep_w = b->wgs;
-    const int hs[7] = {16, 32, 64, 96, 128, 192, 256};
+    const int hs[8] = {16, 24, 32, 40, 48, 64, 96, 128};
     const int fr[3] = {4, 3, 2};  // workgroups = max * fr / 4
     float best = 1e30f;
     int best_h = keep_h, best_w = keep_w;
@@ -437,5 +548,156 @@ int lbac_batch_set_timeout(lbac_batch* b, double seconds, int32_t test_stall) {
 }
 
 const char* lbac_batch_last_error(lbac_batch* b) { return b ? b->err.c_str() : "no batch"; }
+
+int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_t* nsteps, int32_t count,
+                              int32_t strip_h, int32_t workers, int32_t protocol, uint64_t seed, int32_t* verdict,
+                              int64_t* slots_run) {
+    if (!nx || !ny || !nsteps || !verdict || count < 1 || strip_h < kBatchMinStrip || workers < 1 || protocol < 0 ||
+        protocol > 2)
+        return LBAC_EINVAL;
+    std::vector<Geometry> geo(count);
+    std::vector<int64_t> pf(count), pr(count);
+    for (int k = 0; k < count; ++k) {
+        if (nx[k] < 1 || ny[k] < 1 || nsteps[k] < 0 || nsteps[k] > (int64_t)INT32_MAX) return LBAC_EINVAL;
+        geo[k] = {nx[k], ny[k]};
+        pf[k] = nsteps[k] / kBatchS;
+        pr[k] = nsteps[k] % kBatchS;
+    }
+    std::vector<ItemH> items;
+    if (!build_items(geo, strip_h, items)) return LBAC_EINVAL;
+    const int n = (int)items.size();
+    // The state, per buffer and item tile: the pass (run-wide index) that last
+    // wrote it; the initial state is in buffer 0 (pass -1), buffer 1 holds
+    // nothing valid.  Pass gp reads buffer gp & 1 and writes the other one.
+    std::vector<int64_t> ver[2] = {std::vector<int64_t>(n, -1), std::vector<int64_t>(n, -3)};
+    std::mt19937_64 rng(seed);
+    *verdict = 0;
+    int64_t ran = 0;
+    struct Slot {
+        int32_t p, id;
+        int64_t gp;
+        bool started;
+    };
+    for (int L = 0; L < 2 && *verdict == 0; ++L) {
+        const std::vector<int64_t>& passes = L == 0 ? pf : pr;
+        std::vector<int32_t> order;
+        std::vector<int64_t> cum;
+        build_slots(items, passes, order, cum);
+        const int32_t npass = (int32_t)(cum.size() - 1);
+        const int64_t total = cum[npass];
+        const BatchSlots tab{order.data(), cum.data(), &npass};
+        // protocol 2: fixed item lists of 2 * workers workgroups (items dealt
+        // longest-first to the least loaded list, each list walked pass by
+        // pass), of which `workers` run at once; a list's workgroup starts
+        // when a running one has finished its whole list
+        const int lists = 2 * workers;
+        std::vector<std::vector<int32_t>> list(lists);
+        if (protocol == 2) {
+            std::vector<double> load(lists, 0.0);
+            for (int32_t id : order) {
+                const int m = (int)(std::min_element(load.begin(), load.end()) - load.begin());
+                list[m].push_back(id);
+                load[m] += (double)items[id].w * items[id].hh * std::max<int64_t>(passes[items[id].inst], 1);
+            }
+            for (auto& l : list) std::sort(l.begin(), l.end());
+        }
+        std::vector<int32_t> done(n, -1);
+        std::vector<Slot> slot(workers);
+        std::vector<int32_t> cursor(workers, 0);
+        std::vector<bool> busy(workers, false);
+        // protocol 2 state of a worker: its list, pass and position in the list
+        std::vector<int> wl(workers, -1), wpos(workers, 0);
+        std::vector<int32_t> wpass(workers, 0);
+        int next_list = 0;
+        int64_t next = 0, finished = 0;
+        // the next (pass, item) of worker w under protocol 2, or false at the
+        // end of its list (the worker then takes the next list, if any)
+        auto static_next = [&](int w, Slot& s) -> bool {
+            for (;;) {
+                if (wl[w] < 0) {
+                    if (next_list >= lists) return false;
+                    wl[w] = next_list++;
+                    wpos[w] = 0;
+                    wpass[w] = 0;
+                }
+                const std::vector<int32_t>& l = list[wl[w]];
+                while (wpass[w] < npass) {
+                    while (wpos[w] < (int)l.size() && passes[items[l[wpos[w]]].inst] <= wpass[w]) ++wpos[w];
+                    if (wpos[w] < (int)l.size()) {
+                        s.id = l[wpos[w]++];
+                        s.p = wpass[w];
+                        return true;
+                    }
+                    ++wpass[w];
+                    wpos[w] = 0;
+                }
+                wl[w] = -1;
+            }
+        };
+        // Each worker is a resident workgroup running the kernel's loop: take
+        // the next slot, wait until every dependency has published p - 1, work
+        // (reading its read region and writing its tile anywhere in that
+        // interval), publish.  The interleaving of the workers' actions is
+        // random; a state in which no worker can act before every slot has
+        // finished is a deadlock.  A worker that starts working checks that
+        // every tile it reads holds the previous pass and that no working
+        // worker writes a tile it reads or reads the tile it writes.
+        while (finished < total && *verdict == 0) {
+            std::vector<int> can;
+            for (int w = 0; w < workers; ++w) {
+                if (!busy[w]) {
+                    if (protocol == 2 ? (wl[w] >= 0 || next_list < lists) : next < total) can.push_back(w);
+                } else if (slot[w].started) {
+                    can.push_back(w);
+                } else {
+                    bool ready = true;
+                    if (slot[w].p > 0 && protocol != 1)
+                        for (int32_t d : items[slot[w].id].dep) ready = ready && done[d] >= slot[w].p - 1;
+                    if (ready) can.push_back(w);
+                }
+            }
+            if (can.empty()) {
+                *verdict = 1;
+                break;
+            }
+            const int w = can[rng() % can.size()];
+            Slot& s = slot[w];
+            if (!busy[w]) {
+                if (protocol == 2) {
+                    if (!static_next(w, s)) continue;
+                } else {
+                    s.id = batch_slot(tab, next++, cursor[w]);
+                    s.p = cursor[w];
+                }
+                s.gp = (L == 0 ? 0 : pf[items[s.id].inst]) + s.p;
+                s.started = false;
+                busy[w] = true;
+            } else if (!s.started) {
+                const int rb = (int)(s.gp & 1), wb = rb ^ 1;
+                for (int32_t d : items[s.id].dep)
+                    if (ver[rb][d] != s.gp - 1) *verdict = 2;
+                for (int v = 0; v < workers; ++v) {
+                    if (v == w || !busy[v] || !slot[v].started) continue;
+                    const Slot& o = slot[v];
+                    const int orb = (int)(o.gp & 1), owb = orb ^ 1;
+                    for (int32_t d : items[s.id].dep)
+                        if (owb == rb && o.id == d) *verdict = 2;  // o writes a tile s reads
+                    for (int32_t d : items[o.id].dep)
+                        if (wb == orb && s.id == d) *verdict = 2;  // s writes a tile o reads
+                    if (wb == owb && s.id == o.id) *verdict = 2;  // both write one tile
+                }
+                s.started = true;
+            } else {
+                ver[(s.gp & 1) ^ 1][s.id] = s.gp;
+                done[s.id] = s.p;
+                busy[w] = false;
+                ++finished;
+                ++ran;
+            }
+        }
+    }
+    if (slots_run) *slots_run = ran;
+    return LBAC_OK;
+}
 
 }  // extern "C"

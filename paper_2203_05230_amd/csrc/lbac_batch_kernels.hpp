@@ -5,33 +5,37 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include <type_traits>
-
 #include "lbac_kernels.hpp"
 
 // ---------------------------------------------------------------------------
 // Batched form: many independent lattices advanced by ONE persistent launch.
 //
-// Work is split into items = (instance, kBatchTile-column block, strip).
-// Each workgroup (the block layout: kBatchTile column threads and one halo
-// wavefront) owns a fixed list of items and walks them in pass-major order.
-// A run is two persistent launches: the first takes the full passes of
-// kBatchS steps each with the multi-step tile function, the second the
-// remaining nsteps mod kBatchS steps as one-step passes of the block tile
-// function.  An item reads its tile grown by 2 kBatchS nodes and writes its
-// own tile once per pass.  Before item I runs pass p it waits until the
-// items of the same instance whose tiles overlap I's grown tile have
-// completed pass p-1: they wrote the rows and columns I reads, and (the
-// relation is symmetric) they have finished reading the part of the buffer I
-// is about to overwrite.  With every workgroup resident (the grid never
-// exceeds the occupancy limit) the lowest pending pass can always proceed,
-// so the schedule cannot deadlock; every wait is also bounded in wall-clock
-// time and sets an error flag that makes all workgroups exit.
+// Work is split into items = (instance, tile of at most kBatchTile columns,
+// strip of rows).  A run is two persistent launches: the first takes the full
+// passes of kBatchS steps each (the multi-step tile function, the populations
+// between the steps in LDS), the second the remaining nsteps mod kBatchS steps
+// as one-step passes of the same tile function.  A pass of an item reads its
+// tile grown by kBatchGrow nodes (its own rows and the rows of the items
+// around it) and writes its own tile once.
+//
+// Schedule.  The (pass, item) slots of a launch are numbered pass-major (every
+// slot of pass p before any slot of pass p + 1) and workgroups take them one
+// at a time from a single atomic counter.  Before slot (p, I) runs it waits
+// until I and the items whose tiles overlap I's read region have published
+// pass p - 1: they wrote the rows I reads, and (the relation is symmetric)
+// they have finished reading the part of the buffer I is about to overwrite.
+// Every slot waited for has a smaller number, so it is finished or held by a
+// workgroup that is running: the lowest unfinished slot can always proceed,
+// whatever number of workgroups the device keeps resident, and the schedule
+// cannot deadlock.  Every wait is also bounded in wall-clock time and sets an
+// error flag that makes all workgroups exit.
 namespace lbac {
 
-constexpr int kBatchTile = 128;  // columns per item
-constexpr int kBatchS = 3;       // steps per full pass
+constexpr int kBatchTile = 224;          // widest item tile (columns)
+constexpr int kBatchS = 3;               // steps per full pass
 constexpr int kBatchGrow = 2 * kBatchS;  // read region: the tile grown by this many nodes
+constexpr int kBatchThreads = stepS_threads<kBatchTile, kBatchS>();
+constexpr int kBatchDeps = 16;           // items a slot waits for (itself included)
 
 struct BatchInst {
     StepArgs a;       // entry 2k: instance k as seen by even passes; 2k + 1: by odd passes (src, dst swapped)
@@ -39,24 +43,33 @@ struct BatchInst {
 };
 
 struct BatchItem {
-    int32_t inst, bxi, syi, down;
-    // ids of the items whose tiles overlap this item's read region (its tile
-    // grown by kBatchGrow nodes, periodic), itself excluded; repeats pad the list
-    int32_t nbr[16];
+    int32_t inst;       // instance
+    int32_t x0, w;      // columns [x0, x0 + w)
+    int32_t ys, hh;     // rows [ys, ys + hh)
+    int32_t down;       // march direction of the strip
+    // the items whose pass p - 1 must be published before this item's pass p:
+    // itself and every item whose tile overlaps its read region (periodic);
+    // repeats pad the list
+    int32_t dep[kBatchDeps];
 };
 
 struct BatchCtl {
-    int64_t max_full, max_rest;  // passes of the first and of the second launch, largest over the instances
+    uint64_t ticket[2];     // next slot of the first and of the second launch
     int64_t timeout_ticks;  // wall-clock ticks a wait may take before giving up
-    int32_t dry;            // 1: every pass reads src and writes dst (state untouched)
+    int32_t dry;            // 1: every pass reads the current state and writes the other buffer (state untouched)
     int32_t err;            // set to 1 when a wait gave up
     int32_t test_stall;     // 1: waits ask for a pass that never completes (tests the time-out path)
+    int32_t pad;
 };
 
+// Passes of an instance: full passes of kBatchS steps, then one-step passes.
 __host__ __device__ constexpr int64_t batch_passes(int64_t nsteps) { return nsteps / kBatchS + nsteps % kBatchS; }
 
-__device__ __forceinline__ bool batch_wait(const int32_t* done, const BatchItem* item, int32_t need, BatchCtl* ctl) {
-    const int32_t* p = done + item->nbr[threadIdx.x & 15];
+// Waits until every item of dep has published pass `need` (or the time-out
+// or another workgroup's error ends the wait: returns false).  Lanes 0..15 of
+// each wavefront read one entry each.
+__device__ __forceinline__ bool batch_wait(const int32_t* done, const int32_t* dep, int32_t need, BatchCtl* ctl) {
+    const int32_t* p = done + dep[threadIdx.x & (kBatchDeps - 1)];
     if (ctl->test_stall) need += (1 << 30);
     const uint64_t t0 = wall_clock64();
     for (;;) {
@@ -74,59 +87,73 @@ __device__ __forceinline__ bool batch_wait(const int32_t* done, const BatchItem*
     return true;
 }
 
-// S = kBatchS: the full passes; S = 1: the remaining one-step passes.  Three
-// waves per SIMD are asked for: the loop over items around the multi-step
-// tile function would otherwise take 190 registers (two waves per SIMD); at
-// 168 a few values of the prologue spill, and the batch runs 1.33x faster.
+// Slot tables of a launch: order[] lists the items by decreasing number of
+// passes (so the items that have pass p are the first cum[p + 1] - cum[p]
+// entries), cum[p] is the number of the first slot of pass p, cum[npass] the
+// slot count.
+struct BatchSlots {
+    const int32_t* order;
+    const int64_t* cum;
+    const int32_t* npass;  // passes of the launch (device memory: a captured graph's arguments stay valid)
+};
+
+// Maps slot number T of a launch to its pass (cursor p advanced from its
+// previous value: a workgroup's slot numbers only increase) and item.
+__host__ __device__ inline int32_t batch_slot(const BatchSlots& s, int64_t T, int32_t& p) {
+    while (s.cum[p + 1] <= T) ++p;
+    return s.order[T - s.cum[p]];
+}
+
+// S = kBatchS: the full passes; S = 1: the remaining one-step passes (launch
+// L = 1).  Both use the tile function of the multi-step kernel, so one block
+// shape serves both and the results are those of the single-instance kernels.
 template <int MODEL, int S>
-__global__ __launch_bounds__(block_threads<kBatchTile>()) __attribute__((amdgpu_waves_per_eu(3))) void batch_kernel(const BatchInst* __restrict__ insts,
-                                                                          const BatchItem* __restrict__ items,
-                                                                          const int32_t* __restrict__ wg_off,
-                                                                          const int32_t* __restrict__ wg_items,
-                                                                          int32_t* done, BatchCtl* ctl) {
-    __shared__ typename std::conditional<S == 1, TileLds<float, kBatchTile>, TileSLds<kBatchTile, kBatchS>>::type lds;
-    if (S == 1 && __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return;
-    const int beg = wg_off[blockIdx.x], end = wg_off[blockIdx.x + 1];
-    const int64_t max_passes = S == 1 ? ctl->max_rest : ctl->max_full;
+__global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst* __restrict__ insts,
+                                                              const BatchItem* __restrict__ items, BatchSlots slots,
+                                                              int32_t* done, BatchCtl* ctl) {
+    static_assert(stepS_threads<kBatchTile, S>() == kBatchThreads, "one block size serves both launches");
+    constexpr int L = S == 1 ? 1 : 0;
+    __shared__ TileSLds<kBatchTile, S> lds;
+    __shared__ int64_t slot;
+    const int64_t total = slots.cum[*slots.npass];
     const bool dry = ctl->dry != 0;
-    for (int64_t p = 0; p < max_passes; ++p) {
-        bool any = false;
-        for (int i = beg; i < end; ++i) {
-            const int id = wg_items[i];
-            const BatchItem* item = items + id;
-            const int64_t nsteps = insts[2 * item->inst].nsteps;
-            const int64_t nfull = nsteps / kBatchS;
-            if (p >= (S == 1 ? nsteps % kBatchS : nfull)) continue;
-            any = true;
-            if (p > 0) {
-                const bool ok = batch_wait(done, item, (int32_t)(p - 1), ctl);
-                if (__syncthreads_or(!ok)) return;  // every wavefront leaves together
-            }
-            const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
-            const StepArgs& a = insts[2 * item->inst + (int)(gp & 1)].a;
-            const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : p * kBatchS));
-            if constexpr (S == 1)
-                step_tile_lds<float, ST_PLAIN, MODEL, kBatchTile, 2>(a, item->bxi, item->syi, t, item->down != 0, lds);
-            else {
-                static_assert(stepS_threads<kBatchTile, kBatchS>() == block_threads<kBatchTile>(),
-                              "one block size serves both tile functions");
-                stepS_tile_lds<MODEL, kBatchTile, kBatchS>(a, item->bxi, item->syi, t, item->down != 0, lds);
-            }
-            // publish: every wavefront's stores are visible before the counter moves
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-            __syncthreads();
-            if (threadIdx.x == 0) __hip_atomic_store(done + id, (int32_t)p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    int32_t p = 0;
+    for (;;) {
+        if (threadIdx.x == 0) {
+            const bool stop = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+            slot = stop ? total : (int64_t)atomicAdd((unsigned long long*)&ctl->ticket[L], 1ull);
         }
-        if (!any) break;
+        __syncthreads();
+        const int64_t T = slot;  // rewritten only after the barriers of this slot's work
+        if (T >= total) return;
+        const int32_t id = batch_slot(slots, T, p);
+        const BatchItem& item = items[id];
+        if (p > 0) {
+            const bool ok = batch_wait(done, item.dep, p - 1, ctl);
+            if (__syncthreads_or(!ok)) return;  // every wavefront leaves together
+        }
+        const int64_t nfull = insts[2 * item.inst].nsteps / kBatchS;
+        const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
+        const StepArgs& a = insts[2 * item.inst + (int)(gp & 1)].a;
+        const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : (int64_t)p * kBatchS));
+        stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0, lds);
+        // publish: every wavefront's stores are visible before the counter moves
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        __syncthreads();
+        if (threadIdx.x == 0) __hip_atomic_store(done + id, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     }
 }
 
-// Resets the progress counters and, if asked, the error flag (a kernel, not
-// a memset, so that the whole run can be replayed from a captured graph).
-static __global__ void batch_reset_kernel(int32_t* done, int32_t nitems, BatchCtl* ctl, int32_t reset_err) {
+// Resets the progress counters and the slot counter of launch L and, if
+// asked, the error flag (a kernel, not a memset, so that the whole run can be
+// replayed from a captured graph).
+static __global__ void batch_reset_kernel(int32_t* done, int32_t nitems, BatchCtl* ctl, int32_t L, int32_t reset_err) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < nitems) done[i] = -1;
-    if (i == 0 && reset_err) ctl->err = 0;
+    if (i == 0) {
+        ctl->ticket[L] = 0;
+        if (reset_err) ctl->err = 0;
+    }
 }
 
 // Advances every instance's step counter by its step count (skipped on dry runs).

@@ -47,7 +47,7 @@ struct lbac_ctx {
     double* vtab = nullptr;
     float* vtabf = nullptr;  // vtab rounded to FP32
     int64_t* t_dev = nullptr;
-    double* rows = nullptr;
+    void* rows = nullptr;    // per-row partial sums (working precision)
     double* red5 = nullptr;
     double* dtmp = nullptr;  // ny*nx doubles (phi0 upload, phi output, reference field)
     double* host5 = nullptr; // pinned
@@ -60,6 +60,7 @@ struct lbac_ctx {
     int gexec_chunk[2] = {0, 0};
     int gexec_flips[2] = {0, 0};  // parity of the launches in each graph
     bool in_batch = false;   // owned by a batch: lbac_free refuses it
+    bool failed = false;     // its batch's run timed out: the state is undefined
     // learned closure (FP32 plain storage only)
     bool closure = false;
     float cl_theta = 0.f;

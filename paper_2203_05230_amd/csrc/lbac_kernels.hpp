@@ -107,6 +107,20 @@ __device__ __forceinline__ double time_factor(double period, int64_t t) {
 }
 
 // ---- storage access --------------------------------------------------------
+// Sums over the populations, in an order that the mirror y -> -y of the
+// lattice (which swaps populations 2 and 4, 5 and 8, 6 and 7) leaves
+// unchanged: a kernel that marches a strip downward in the mirrored frame
+// then rounds exactly like one working in the lattice frame.  sum9 over all
+// nine, sum_moving over 1..8.
+template <typename R>
+__device__ __forceinline__ R sum_moving(const R (&f)[9]) {
+    return ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[8]) + (f[6] + f[7]));
+}
+template <typename R>
+__device__ __forceinline__ R sum9(const R (&f)[9]) {
+    return f[0] + sum_moving(f);
+}
+
 template <typename R, int ST>
 struct Store;
 
@@ -121,11 +135,6 @@ struct Store<R, ST_PLAIN> {
     }
     __device__ __forceinline__ static R load_one(const StepArgs& a, int64_t off, int q) {
         return static_cast<const R*>(a.src)[q * a.plane_stride + off];
-    }
-    __device__ __forceinline__ static void store(const StepArgs& a, int64_t off, const R (&v)[9], R /*phi*/) {
-        R* d = static_cast<R*>(a.dst);
-#pragma unroll
-        for (int q = 0; q < 9; ++q) d[q * a.plane_stride + off] = v[q];
     }
 };
 
@@ -142,11 +151,10 @@ __device__ __forceinline__ __half f2h<__half>(float f) { return __float2half_rn(
 template <>
 __device__ __forceinline__ __hip_bfloat16 f2h<__hip_bfloat16>(float f) { return __float2bfloat16(f); }
 
-// Shifted 16-bit storage.  load() returns v[0] = phi* and v[i] = w_i phi* + g_i
-// (i >= 1); the rest population f_0 = phi* - sum_{i>=1} v_i is never formed
-// in FP32: phi(x) = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] is summed in
-// FP64 and rounded once, so the mass carried by phi* changes only by that one
-// unbiased rounding per node and step.
+// Shifted 16-bit storage.  The planes hold phi* = sum_i f*_i in FP32 and
+// g_i = f*_i - w_i phi* (i >= 1) in 16 bits (g_0 is implied).  load() returns
+// v[0] = phi* and the moving populations they stand for, v_i = w_i phi* + g_i
+// (i >= 1), in FP32.  The pulled sum is then formed by shifted_phi below.
 template <typename H>
 struct StoreShifted {
     static constexpr bool kShifted = true;
@@ -157,19 +165,28 @@ struct StoreShifted {
 #pragma unroll
         for (int q = 1; q < 9; ++q) v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(s[(q - 1) * a.plane_stride + off]));
     }
+    // v_q at `off` for a moving population (q >= 1)
     __device__ __forceinline__ static float load_one(const StepArgs& a, int64_t off, int q) {
         const H* s = static_cast<const H*>(a.src);
-        const float ph = a.src_phi[off];
-        if (q == 0) return ph;
-        return __builtin_fmaf(wq<float>(q), ph, h2f<H>(s[(q - 1) * a.plane_stride + off]));
-    }
-    __device__ __forceinline__ static void store(const StepArgs& a, int64_t off, const float (&v)[9], float phi) {
-        H* d = static_cast<H*>(a.dst);
-#pragma unroll
-        for (int q = 1; q < 9; ++q) d[(q - 1) * a.plane_stride + off] = f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]));
-        a.dst_phi[off] = phi;
+        return __builtin_fmaf(wq<float>(q), a.src_phi[off], h2f<H>(s[(q - 1) * a.plane_stride + off]));
     }
 };
+
+// phi(x) = sum_i f*_i(x - c_i) for shifted storage, as
+// phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] (the rest population cancels):
+// each difference of neighbouring values of one population is exact in FP32
+// wherever they lie within a factor two of each other (Sterbenz's lemma) and
+// small elsewhere, so the sum carries about one rounding of phi, and what one
+// node gains from v_i(y) another loses exactly: the 16-bit roundings of the
+// stored values cannot move the mass.  pulled[i] = v_i(x - c_i), own[i] = v_i(x);
+// summed in the mirror-invariant order of sum_moving.
+__device__ __forceinline__ float shifted_phi(float phistar, const float (&pulled)[9], const float (&own)[9]) {
+    float d[9];
+#pragma unroll
+    for (int q = 1; q < 9; ++q) d[q] = pulled[q] - own[q];
+    d[0] = 0.f;
+    return phistar + sum_moving(d);
+}
 template <>
 struct Store<float, ST_F16> : StoreShifted<__half> {};
 template <>
@@ -230,20 +247,6 @@ __device__ __forceinline__ double fmaR(double a, double b, double c) { return __
 // positive bound).
 __device__ __forceinline__ float clip01(float p) { return __builtin_amdgcn_fmed3f(p, 0.f, 1.f); }
 __device__ __forceinline__ double clip01(double p) { return __builtin_fmin(__builtin_fmax(p, 0.0), 1.0); }
-
-// Sums over the populations, in an order that the mirror y -> -y of the
-// lattice (which swaps populations 2 and 4, 5 and 8, 6 and 7) leaves
-// unchanged: a kernel that marches a strip downward in the mirrored frame
-// then rounds exactly like one working in the lattice frame.  sum9 over all
-// nine, sum_moving over 1..8.
-template <typename R>
-__device__ __forceinline__ R sum_moving(const R (&f)[9]) {
-    return ((f[1] + f[3]) + (f[2] + f[4])) + ((f[5] + f[8]) + (f[6] + f[7]));
-}
-template <typename R>
-__device__ __forceinline__ R sum9(const R (&f)[9]) {
-    return f[0] + sum_moving(f);
-}
 
 // Row factor of the velocity tables (Ay or By at row y): the same for the
 // whole workgroup, read through the constant address space so that it is a
@@ -367,9 +370,13 @@ __device__ __forceinline__ void bstore(double v, __amdgpu_buffer_rsrc_t r, uint3
     w.y = (unsigned int)(bits >> 32);
     __builtin_amdgcn_raw_buffer_store_b64(w, r, (int)off, 0, 0);
 }
+// 16-bit store; aux 2 is the non-temporal hint
 template <typename H>
-__device__ __forceinline__ void bstore16(H v, __amdgpu_buffer_rsrc_t r, uint32_t off) {
-    __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
+__device__ __forceinline__ void bstore16(H v, __amdgpu_buffer_rsrc_t r, uint32_t off, int aux) {
+    if (aux == 2)
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 2);
+    else
+        __builtin_amdgcn_raw_buffer_store_b16(__builtin_bit_cast(unsigned short, v), r, (int)off, 0, 0);
 }
 
 template <typename R, int ST>
@@ -410,7 +417,7 @@ struct Io<R, ST_PLAIN> {
     }
     // the same, non-temporal (FP32 only): used where the L2 is better spent
     // on rows that are read again
-    __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9]) const {
+    __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float /*phi*/) const {
         const uint32_t b = on ? off * 4u : kDropOffset;
 #pragma unroll
         for (int q = 0; q < 9; ++q) bstore_nt(v[q], plane_rsrc(d[q]), b);
@@ -422,28 +429,39 @@ struct IoShifted {
     static constexpr bool kShifted = true;
     const char* s[9];  // s[0]: phi* plane (FP32); s[1..8]: g planes (16-bit)
     char* d[9];
-    __device__ __forceinline__ explicit IoShifted(const StepArgs& a) {
+    // mirror: the mirrored frame y -> -y, population q read from and written
+    // to the plane of its mirror image (the phi* plane is its own image)
+    __device__ __forceinline__ explicit IoShifted(const StepArgs& a, bool mirror = false) {
         s[0] = reinterpret_cast<const char*>(a.src_phi);
         d[0] = reinterpret_cast<char*>(a.dst_phi);
 #pragma unroll
         for (int q = 1; q < 9; ++q) {
-            s[q] = static_cast<const char*>(a.src) + (size_t)(q - 1) * a.plane_stride * sizeof(H);
-            d[q] = static_cast<char*>(a.dst) + (size_t)(q - 1) * a.plane_stride * sizeof(H);
+            const int m = mirror ? mirror_q(q) : q;
+            s[q] = static_cast<const char*>(a.src) + (size_t)(m - 1) * a.plane_stride * sizeof(H);
+            d[q] = static_cast<char*>(a.dst) + (size_t)(m - 1) * a.plane_stride * sizeof(H);
         }
     }
-    // v[0] = phi*, v[i] = w_i phi* + g_i
+    // v[0] = phi*, v[i] = w_i phi* + g_i (see StoreShifted)
     __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
         const float ph = *reinterpret_cast<const float*>(s[0] + off * 4u);
         v[0] = ph;
 #pragma unroll
         for (int q = 1; q < 9; ++q) v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(*reinterpret_cast<const H*>(s[q] + off * 2u)));
     }
-    // stores g_i = v_i - w_i phi and phi* = phi when `on`; a lane with on == false stores nothing
+    // stores g_i = v_i - w_i phi and phi* = phi (the sum the collision
+    // conserves) when `on`; a lane with on == false stores nothing
     __device__ __forceinline__ void store(bool on, uint32_t off, const float (&v)[9], float phi) const {
         const uint32_t b2 = on ? off * 2u : kDropOffset, b4 = on ? off * 4u : kDropOffset;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) bstore16(f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q])), plane_rsrc(d[q]), b2);
+        for (int q = 1; q < 9; ++q) bstore16(f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q])), plane_rsrc(d[q]), b2, 0);
         bstore(phi, plane_rsrc(d[0]), b4);
+    }
+    // the same with the non-temporal hint
+    __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float phi) const {
+        const uint32_t b2 = on ? off * 2u : kDropOffset, b4 = on ? off * 4u : kDropOffset;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) bstore16(f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q])), plane_rsrc(d[q]), b2, 2);
+        bstore_nt(phi, plane_rsrc(d[0]), b4);
     }
 };
 template <>
@@ -558,7 +576,8 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
         {
 #pragma unroll
             for (int q = 0; q < 9; ++q) ring[slot][q][lj] = nv[q];
-            // phi at t-1 on this row: the stored sum (plain) or phi* itself (shifted)
+            // phi at t-1 on this row: the sum of the stored values (phi* itself
+            // for shifted storage)
             P0 = Io<R, ST>::kShifted ? nv[0] : sum9(nv);
         }
         // ---- prefetch row r + PF dir into the registers just consumed
@@ -567,24 +586,18 @@ __device__ __forceinline__ void step_tile_lds(const StepArgs& a, int bxi, int sy
 
         // ---- phi (Eq. (12)) and psi (Eq. (13)) on the centre row
         if (it >= 2 && pl) {
+#pragma unroll
+            for (int q = 0; q < 9; ++q) {
+                const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
+                fcur[q] = ring[sl][q][pj - cx(q)];
+            }
             R s;
             if constexpr (Io<R, ST>::kShifted) {
-                // phi = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] in FP64, rounded once
-                double d = (double)ring[slot1][0][pj];
+                R own[9];
 #pragma unroll
-                for (int q = 1; q < 9; ++q) {
-                    const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
-                    fcur[q] = ring[sl][q][pj - cx(q)];
-                    d += (double)fcur[q] - (double)ring[slot1][q][pj];
-                }
-                fcur[0] = R(0);  // the rest population is formed as the remainder after collision
-                s = R(d);
+                for (int q = 0; q < 9; ++q) own[q] = ring[slot1][q][pj];
+                s = shifted_phi(own[0], fcur, own);  // the collision forms the rest population itself
             } else {
-#pragma unroll
-                for (int q = 0; q < 9; ++q) {
-                    const int sl = cy(q) == 1 ? slot_s : (cy(q) == 0 ? slot1 : slot_n);
-                    fcur[q] = ring[sl][q][pj - cx(q)];
-                }
                 s = sum9(fcur);
             }
             phicur = s;
@@ -666,20 +679,24 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 }
 
 // ---------------------------------------------------------------------------
-// S steps per pass over HBM (FP32 storage; S = 2 or 3).
+// S steps per pass over HBM (S = 1, 2 or 3; FP32 collide, FP32 or shifted
+// 16-bit storage).
 //
-// The block owns BX aligned columns [x0, x0 + BX) and marches a strip as the
-// block variant does, with S stages chained in one pipeline.  Stage 0 takes
-// step t from the populations in HBM; stage k takes step t + k from the
-// post-collision populations of stage k - 1, which stay in an LDS ring, and
-// runs three rows behind it; stage S - 1 stores to HBM.  Stage k works on the
-// tile grown by 2 (S - 1 - k) columns on each side (so the block loads 2 S
-// halo columns on each side), and the strip's first and last 2 S rows are
-// loaded and computed by both neighbouring strips.  Each stage does exactly
-// the arithmetic of one step of the block variant on every node, with the
-// same helpers and summation orders, so S steps of this kernel equal S
-// launches of the one-step kernels bit for bit, while HBM is read and
-// written once per S steps.
+// The block owns the w columns [x0, x0 + w) and the hh rows [ys, ys + hh) of
+// a tile and marches the strip as the block variant does, with S stages
+// chained in one pipeline.  Stage 0 takes step t from the populations in HBM;
+// stage k takes step t + k from the post-collision populations of stage
+// k - 1, which stay in an LDS ring, and runs three rows behind it; stage
+// S - 1 stores to HBM.  Stage k works on the tile grown by 2 (S - 1 - k)
+// columns on each side (so the block loads 2 S halo columns on each side),
+// and the strip's first and last 2 S rows are loaded and computed by both
+// neighbouring strips.  Each stage does exactly the arithmetic of one step of
+// the block variant on every node, with the same helpers and summation
+// orders, so with FP32 storage S steps of this kernel equal S launches of the
+// one-step kernels bit for bit, while HBM is read and written once per S
+// steps.  With shifted 16-bit storage the populations pass through 16 bits
+// only at the launch's load and store (the intermediate steps keep them in
+// FP32 in LDS), so that form rounds to its storage precision once per launch.
 //
 // Rows at iteration it (dir = +1 up the strip, -1 down it): row R enters
 // stage 0's ring; stage k forms phi and psi on R - (3k + 1) dir and updates
@@ -695,7 +712,7 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // c_x = 0 stay in the thread's registers.  Pairs are stored c_x = +1 first.  Index j <-> column
 // x0 - 2S - 1 + j; indices 0 and W - 1 are padding, so that every thread's
 // reads at j - 1 and j + 1 stay inside its row, and W - 1 also takes the
-// writes of duplicate threads.
+// writes of threads past the grown tile.
 template <int BX, int S>
 struct TileSLds {
     static constexpr int W = BX + 4 * S + 2;
@@ -705,45 +722,34 @@ struct TileSLds {
     float ps[S][3][W];     // psi of stage k on its last three rows
 };
 
-// Threads of an S-step tile: the BX + 4S columns of the grown tile rounded up
-// to whole wavefronts.  The wavefronts but the last own the tile's first
-// C = threads - 64 columns; the last one takes the 2S left halo columns and
-// then columns C .. BX + 2S - 1 (the rest of the tile and the right halo).
-// Every wavefront but the last thus loads and stores aligned 64-column
-// segments, and for BX a multiple of 64 the last one is a pure halo
-// wavefront.
+// Threads of an S-step tile of at most BX columns: the BX + 4S columns of the
+// grown tile rounded up to whole wavefronts.
 template <int BX, int S>
 __host__ __device__ constexpr int stepS_threads() {
     return (BX + 4 * S + 63) / 64 * 64;
 }
 
-template <int MODEL, int BX, int S>
-__device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int syi, int64_t t, bool down,
-                                               TileSLds<BX, S>& lds) {
-    static_assert(BX + 4 * S <= stepS_threads<BX, S>() && stepS_threads<BX, S>() - 64 <= BX,
-                  "the last wavefront holds the halo and the tile's remaining columns");
-    constexpr int C = stepS_threads<BX, S>() - 64;
+template <int MODEL, int BX, int S, int ST>
+__device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w, int ys, int hh, int64_t t,
+                                               bool down, TileSLds<BX, S>& lds) {
+    // Thread l works on column l - 2S of the grown tile (columns -2S ..
+    // w + 2S - 1 relative to x0; the tile starts on a 128-byte line, so every
+    // line of its rows is written whole by this block).  Threads past the
+    // grown tile (a tile narrower than BX) duplicate its last column: they
+    // load what its owner loads, write their LDS values to the padding column
+    // and store nothing; a wavefront with no column at all only takes part in
+    // the barriers.  act: owns tile column x0 + cxo.
     const int l = threadIdx.x;
-    const int x0 = bxi * BX;
-    const int w = min(BX, a.nx - x0);
-    const int ys = syi * a.strip_h;
-    const int hh = min(a.strip_h, a.ny - ys);
-    // cxo: column of this thread relative to x0.  Threads past the grown tile
-    // (w + 4S columns; fewer than BX + 4S on a narrow last tile) duplicate
-    // its last column: they load what its owner loads, write their LDS values
-    // to the padding column and store nothing.  act: owns tile column x0 + cxo.
-    const int hl = l - C;  // lane in the last wavefront
-    const int craw = l < C ? l : (hl < 2 * S ? hl - 2 * S : C + hl - 2 * S);
-    const bool dup = craw > w + 2 * S - 1;
-    const int cxo = min(craw, w + 2 * S - 1);
-    const bool act = cxo >= 0 && cxo < w && !dup;
+    const int ncol = w + 4 * S;
+    const bool dup = l >= ncol;
+    const int cxo = min(l, ncol - 1) - 2 * S;
+    const bool act = !dup && cxo >= 0 && cxo < w;
     // Stage k forms phi/psi validly on columns -(2(S-k)-1) .. w+2(S-k)-2 and
     // updates -(2(S-k)-2) .. w+2(S-k)-3.  Every thread runs every stage
     // (branching on these ranges would only hold per-lane masks, since every
     // wavefront has lanes inside them): outside them a thread forms values
     // from rows or columns that are not valid yet, which no valid value reads
-    // (each range is the next one's reach plus one column on each side), and
-    // a duplicate thread writes its LDS values to the padding column.
+    // (each range is the next one's reach plus one column on each side).
     const int gcol = wrap_idx(x0 + cxo, a.nx);
     const int j = cxo + 2 * S + 1;                    // LDS column read
     const int jw = dup ? TileSLds<BX, S>::W - 1 : j;  // LDS column written
@@ -754,8 +760,18 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     // direction.  Every node helper rounds mirror-symmetrically (sums in
     // mirror-invariant order, y components that only change sign), so the
     // results equal the lattice-frame computation bit for bit.
-    const Io<float, ST_PLAIN> io(a, down);
+    const Io<float, ST> io(a, down);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
+
+    const int iters = hh + 5 * S - 1;
+    if (__builtin_amdgcn_readfirstlane(l) / kWave * kWave >= ncol) {
+        // no column in this wavefront: the loop's two barriers per iteration only
+        for (int it = 0; it < iters; ++it) {
+            lds_barrier();
+            lds_barrier();
+        }
+        return;
+    }
 
     // FP32 velocity factors: the FP64 table rounded once on the host, as the
     // one-step kernels round it on the device
@@ -768,11 +784,16 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     // the pull of iteration it fills half it & 1, the update of iteration
     // it + 1 reads it
     float fp[S][2][9], ph[S][2], ob[9];
+    float phl = 0.f;  // phi of the last stage's updated node (the shifted store's phi*)
     // Histories, index = age in iterations (0: this iteration).  P[k]: the sum
     // of stage k's input populations at the own node (phi(t + k - 1) as the
     // one-step kernel forms it); z0, zo, zn: the own column's c_x = 0 inputs
     // of stage k (population 0, the old-row one, the new-row one).
     float P[S][4], z0[S][4], zo[S][4], zn[S][4];
+    // shifted storage: the own column's populations 7 and 8 of stage 0's last
+    // two input rows (the rings keep them only where another column pulls them)
+    float o7[2] = {0.f, 0.f}, o8[2] = {0.f, 0.f};
+    constexpr bool kSh = Io<float, ST>::kShifted;
 #pragma unroll
     for (int k = 0; k < S; ++k) {
 #pragma unroll
@@ -787,7 +808,6 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
 #pragma unroll
     for (int q = 0; q < 9; ++q) ob[q] = 0.f;
 
-    const int iters = hh + 5 * S - 1;
     const int dir = down ? -1 : 1;
     auto raw_row = [&](int it) { return down ? ys + hh + 2 * S - 1 - it : ys - 2 * S + it; };
     // lattice row loaded at iteration it (iterations past the last input row
@@ -795,7 +815,13 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, hh + 4 * S - 1)), a.ny); };
     // a stage's input into its ring and histories (v: populations at the own column)
     auto put = [&](int k, int s3, int s2, const float(&v)[9]) __attribute__((always_inline)) {
-        P[k][0] = sum9(v);
+        // phi at t + k - 1: the sum of the stage's input values (phi* itself
+        // for stage 0's shifted input)
+        P[k][0] = kSh && k == 0 ? v[0] : sum9(v);
+        if (kSh && k == 0) {
+            o7[0] = v[7];
+            o8[0] = v[8];
+        }
         lds.ro[k][s3][0][jw] = v[5];
         lds.ro[k][s3][1][jw] = v[6];
         lds.rm[k][s2][0][jw] = v[1];
@@ -835,7 +861,25 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                 f[6] = lds.ro[k][so][1][j + 1];
                 f[7] = lds.rn[k][1][j + 1];
                 f[8] = lds.rn[k][0][j - 1];
-                const float s = sum9(f);
+                float s;
+                if (kSh && k == 0) {
+                    // the own column's values of the centre row: populations 1, 3
+                    // and 5, 6 from the rings, 2, 4 (and phi* in z0) from the
+                    // histories, 7, 8 from o7, o8
+                    float own[9];
+                    own[0] = 0.f;
+                    own[1] = lds.rm[0][sm][0][j];
+                    own[3] = lds.rm[0][sm][1][j];
+                    own[5] = lds.ro[0][(it + 2) % 3][0][j];
+                    own[6] = lds.ro[0][(it + 2) % 3][1][j];
+                    own[2] = zo[0][1];
+                    own[4] = zn[0][1];
+                    own[7] = o7[1];
+                    own[8] = o8[1];
+                    s = shifted_phi(z0[0][1], f, own);  // the collision forms the rest population itself
+                } else {
+                    s = sum9(f);
+                }
                 ph[k][B] = s;
                 lds.ps[k][s3][jw] = normal_source<float, MODEL>(s, kcs[k]);
             }
@@ -868,13 +912,16 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
                                            kc.s_old * uxr, kc.s_old * uyr, kc, Gx, Gy);
                 collide(fp[k][B ^ 1], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
                 if (!last) put(k + 1, s3, s2, ob);
+                else phl = phi;
             }
         }
         // non-temporal: a stored row is not read again in this launch, while
         // the 4S rows each strip shares with its neighbours are (1.5% faster
         // at 8192^2 than plain stores)
-        io.store_nt(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + cxo), ob);
+        io.store_nt(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + cxo), ob, phl);
         // ---- age the histories by one iteration
+        o7[1] = o7[0];
+        o8[1] = o8[0];
 #pragma unroll
         for (int k = 0; k < S; ++k) {
 #pragma unroll
@@ -897,13 +944,15 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int bxi, int s
     }
 }
 
-template <int MODEL, int BX, int S>
+template <int MODEL, int BX, int S, int ST>
 __global__ __launch_bounds__((stepS_threads<BX, S>())) void stepS_kernel_lds(StepArgs a) {
     __shared__ TileSLds<BX, S> lds;
     const int ntile = a.nbx * a.nby;
     const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
     const int bxi = tile % a.nbx, syi = tile / a.nbx;
-    stepS_tile_lds<MODEL, BX, S>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
+    const int x0 = bxi * BX, ys = syi * a.strip_h;
+    stepS_tile_lds<MODEL, BX, S, ST>(a, x0, min(BX, a.nx - x0), ys, min(a.strip_h, a.ny - ys), a.t_dev[0] + a.k,
+                                     (syi & 1) != 0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1158,11 +1207,7 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
         }
 #pragma unroll
         for (int j = D + 1; j > 0; --j) P[j] = P[j - 1];
-        if constexpr (Io<R, ST>::kShifted) {
-            P[0] = r0[0];  // phi* itself
-        } else {
-            P[0] = sum9(r0);
-        }
+        P[0] = Io<R, ST>::kShifted ? r0[0] : sum9(r0);
         // unconditional, like the update's stores below, so that the compiler
         // counts the memory operations in flight exactly (past the strip's
         // end the last row is reloaded and not used)
@@ -1189,16 +1234,10 @@ __device__ __forceinline__ void step_wave_dir(const StepArgs& a, int bxi, int sy
             fc[7] = pulled<R, ST, MODEL, DIR, 7>(r0, r1, r2);
             fc[8] = pulled<R, ST, MODEL, DIR, 8>(r0, r1, r2);
             R s;
-            if constexpr (Io<R, ST>::kShifted) {
-                // phi = phi*(x) + sum_{i>=1} [v_i(x - c_i) - v_i(x)] in FP64, rounded once
-                double d = (double)r1[0];
-#pragma unroll
-                for (int q = 1; q < 9; ++q) d += (double)fc[q] - (double)r1[q];
-                fc[0] = R(0);  // the rest population is formed as the remainder after collision
-                s = R(d);
-            } else {
+            if constexpr (Io<R, ST>::kShifted)
+                s = shifted_phi(r1[0], fh[0], r1);  // r1: the centre row at the own column
+            else
                 s = sum9(fh[0]);
-            }
             ph[0] = s;
             ps[0] = normal_source<R, MODEL>(s, kc);
         }
@@ -1399,26 +1438,24 @@ __global__ void init_kernel(StepArgs a, const double* __restrict__ phi0) {
     }
 }
 
-// phi(x) = sum_i f*_i(x - c_i) from the stored state in a.src, in FP64 (plain
-// storage: summed in the mirror-invariant order of the step).
+// phi(x) = sum_i f*_i(x - c_i) from the stored state in a.src, formed as the
+// step forms it (in R, the populations summed in the step's order).
 template <typename R, int ST>
-__device__ __forceinline__ double pulled_phi(const StepArgs& a, int x, int y) {
-    const int64_t own = (int64_t)y * a.pitch + x;
-    double v[9];
+__device__ __forceinline__ R pulled_phi(const StepArgs& a, int x, int y) {
+    R v[9];
 #pragma unroll
-    for (int q = 0; q < 9; ++q) {
+    for (int q = 1; q < 9; ++q) {
         const int xs = wrap_idx(x - cx(q), a.nx), ys = wrap_idx(y - cy(q), a.ny);
-        v[q] = (double)Store<R, ST>::load_one(a, (int64_t)ys * a.pitch + xs, q);
+        v[q] = Store<R, ST>::load_one(a, (int64_t)ys * a.pitch + xs, q);
     }
-    if constexpr (!Store<R, ST>::kShifted) return sum9(v);
-    // shifted storage: phi = phi* + sum_{i>=1} [v_i(x - c_i) - v_i(x)]
-    double s = 0.0;
-#pragma unroll
-    for (int q = 0; q < 9; ++q) {
-        s += v[q];
-        if (q > 0) s -= (double)Store<R, ST>::load_one(a, own, q);
+    if constexpr (Store<R, ST>::kShifted) {
+        R own[9];
+        Store<R, ST>::load(a, (int64_t)y * a.pitch + x, own);
+        return shifted_phi(own[0], v, own);
+    } else {
+        v[0] = Store<R, ST>::load_one(a, (int64_t)y * a.pitch + x, 0);
+        return sum9(v);
     }
-    return s;
 }
 
 template <typename R, int ST>
@@ -1426,68 +1463,107 @@ __global__ void phi_kernel(StepArgs a, double* __restrict__ out) {
     const int x = blockIdx.x * blockDim.x + threadIdx.x;
     const int y = blockIdx.y;
     if (x >= a.nx) return;
-    out[(int64_t)y * a.nx + x] = pulled_phi<R, ST>(a, x, y);
+    out[(int64_t)y * a.nx + x] = (double)pulled_phi<R, ST>(a, x, y);
 }
 
-// Block partial sums for mass and shape errors: per row y, the four sums
-// sum phi, sum |phi - ref|, sum |ref|, sum (phi - ref)^2, sum ref^2 (5 values).
-// One block per row; the host (or reduce_rows) adds rows in order.
+// Compensated sum in the working precision R (FP32 for the FP32 forms):
+// s carries the rounded sum, c the exact rounding errors of its additions
+// (Knuth's TwoSum), accumulated; the value is s + c.
+template <typename R>
+struct CompSum {
+    R s, c;
+    __device__ __forceinline__ CompSum() : s(R(0)), c(R(0)) {}
+    __device__ __forceinline__ void add(R x) {
+        const R t = s + x;
+        const R z = t - s;
+        c += (s - (t - z)) + (x - z);
+        s = t;
+    }
+    __device__ __forceinline__ void add(const CompSum& o) {
+        add(o.s);
+        c += o.c;
+    }
+    __device__ __forceinline__ R value() const { return s + c; }
+};
+
+// Partial sums for mass and shape errors: per row y, the five sums
+// sum phi, sum |phi - ref|, sum |ref|, sum (phi - ref)^2, sum ref^2, each as a
+// compensated pair (s, c) in R.  One block per row; reduce_rows adds the rows
+// in order.
 constexpr int kRedThreads = 256;
 
-__device__ __forceinline__ double block_sum(double v, double* sh) {
-    // wavefront (64 lanes) tree, then across the block's waves, fixed order
-    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+// Compensated block sum in a fixed order: wavefront tree, then the
+// wavefronts' partial sums in order by thread 0 (valid there only).
+template <typename R>
+__device__ __forceinline__ CompSum<R> block_sum(CompSum<R> v, R* sh) {
+    for (int off = 32; off > 0; off >>= 1) {
+        CompSum<R> o;
+        o.s = __shfl_down(v.s, off, 64);
+        o.c = __shfl_down(v.c, off, 64);
+        v.add(o);
+    }
     const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
     __syncthreads();
-    if (lane == 0) sh[wid] = v;
+    if (lane == 0) {
+        sh[2 * wid] = v.s;
+        sh[2 * wid + 1] = v.c;
+    }
     __syncthreads();
-    double r = 0.0;
+    CompSum<R> r;
     if (threadIdx.x == 0)
-        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) r += sh[i];
+        for (int i = 0; i < (int)(blockDim.x >> 6); ++i) {
+            CompSum<R> o;
+            o.s = sh[2 * i];
+            o.c = sh[2 * i + 1];
+            r.add(o);
+        }
     return r;
 }
 
 template <typename R, int ST>
 __global__ __launch_bounds__(kRedThreads) void row_sums_kernel(StepArgs a, const double* __restrict__ ref,
-                                                                double* __restrict__ rows) {
-    __shared__ double sh[kRedThreads / 64];
+                                                                R* __restrict__ rows) {
+    __shared__ R sh[2 * kRedThreads / 64];
     const int y = blockIdx.x;
-    double s_phi = 0, s_ad = 0, s_ar = 0, s_d2 = 0, s_r2 = 0;
+    CompSum<R> acc[5];
     for (int x = threadIdx.x; x < a.nx; x += blockDim.x) {
-        const double p = pulled_phi<R, ST>(a, x, y);
-        s_phi += p;
+        const R p = pulled_phi<R, ST>(a, x, y);
+        acc[0].add(p);
         if (ref) {
-            const double r = ref[(int64_t)y * a.nx + x];
-            const double d = p - r;
-            s_ad += fabs(d);
-            s_ar += fabs(r);
-            s_d2 += d * d;
-            s_r2 += r * r;
+            const R r = R(ref[(int64_t)y * a.nx + x]);
+            const R d = p - r;
+            acc[1].add(d < R(0) ? -d : d);
+            acc[2].add(r < R(0) ? -r : r);
+            acc[3].add(d * d);
+            acc[4].add(r * r);
         }
     }
-    double* o = rows + 5 * (int64_t)y;
-    double v;
-    v = block_sum(s_phi, sh);
-    if (threadIdx.x == 0) o[0] = v;
-    v = block_sum(s_ad, sh);
-    if (threadIdx.x == 0) o[1] = v;
-    v = block_sum(s_ar, sh);
-    if (threadIdx.x == 0) o[2] = v;
-    v = block_sum(s_d2, sh);
-    if (threadIdx.x == 0) o[3] = v;
-    v = block_sum(s_r2, sh);
-    if (threadIdx.x == 0) o[4] = v;
+    R* o = rows + 10 * (int64_t)y;
+    for (int c = 0; c < 5; ++c) {
+        const CompSum<R> v = block_sum(acc[c], sh);
+        if (threadIdx.x == 0) {
+            o[2 * c] = v.s;
+            o[2 * c + 1] = v.c;
+        }
+    }
 }
 
-// Adds the per-row sums in row order (one block; deterministic).
-static __global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const double* __restrict__ rows, int ny,
-                                                                   double* __restrict__ out5) {
-    __shared__ double sh[kRedThreads / 64];
+// Adds the per-row sums in row order (one block; deterministic) and writes
+// the five totals.
+template <typename R>
+__global__ __launch_bounds__(kRedThreads) void reduce_rows_kernel(const R* __restrict__ rows, int ny,
+                                                                  double* __restrict__ out5) {
+    __shared__ R sh[2 * kRedThreads / 64];
     for (int c = 0; c < 5; ++c) {
-        double s = 0.0;
-        for (int y = threadIdx.x; y < ny; y += blockDim.x) s += rows[5 * (int64_t)y + c];
-        const double v = block_sum(s, sh);
-        if (threadIdx.x == 0) out5[c] = v;
+        CompSum<R> acc;
+        for (int y = threadIdx.x; y < ny; y += blockDim.x) {
+            CompSum<R> o;
+            o.s = rows[10 * (int64_t)y + 2 * c];
+            o.c = rows[10 * (int64_t)y + 2 * c + 1];
+            acc.add(o);
+        }
+        const CompSum<R> v = block_sum(acc, sh);
+        if (threadIdx.x == 0) out5[c] = (double)v.value();
     }
 }
 

@@ -63,7 +63,7 @@ EXPORTS = [
     "lbac_stream", "lbac_strerror", "lbac_last_error",
     "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
     "lbac_batch_set_shape", "lbac_batch_get_shape", "lbac_batch_autotune", "lbac_batch_set_timeout",
-    "lbac_batch_last_error",
+    "lbac_batch_last_error", "lbac_batch_schedule_check",
     "lbac_mlp_create", "lbac_mlp_free", "lbac_mlp_get_weights", "lbac_mlp_set_weights", "lbac_mlp_forward",
     "lbac_mlp_loss_grad", "lbac_mlp_train_step", "lbac_mlp_last_error",
     "lbac_closure_workspace_bytes", "lbac_closure_extract",
@@ -133,6 +133,8 @@ def load():
     L.lbac_batch_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
     L.lbac_batch_set_timeout.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     L.lbac_batch_last_error.argtypes = [C.c_void_p]
+    L.lbac_batch_schedule_check.argtypes = [P(C.c_int32), P(C.c_int32), P(C.c_int64), C.c_int32, C.c_int32,
+                                            C.c_int32, C.c_int32, C.c_uint64, P(C.c_int32), P(C.c_int64)]
     L.lbac_batch_last_error.restype = C.c_char_p
     fp = P(C.c_float)
     L.lbac_mlp_create.argtypes = [fp, C.c_void_p, ctx_pp]
@@ -414,6 +416,23 @@ class Batch:
 
     def set_timeout(self, seconds, test_stall=False):
         self._err(load().lbac_batch_set_timeout(self.h, float(seconds), 1 if test_stall else 0))
+
+
+def batch_schedule_check(shapes, nsteps, strip_h, workers, seed=0, protocol=0):
+    """Runs a slot protocol of the batched schedule on the CPU (no GPU) for
+    instances of the given (nx, ny) shapes and step counts with `workers`
+    workgroups running at once (protocol 0: the library's; 1: without the
+    dependency waits; 2: fixed per-workgroup item lists).  Returns (verdict,
+    slots run): verdict 0 = no deadlock and no hazard, 1 = deadlock, 2 =
+    read or write hazard."""
+    n = len(shapes)
+    nx = (C.c_int32 * n)(*[int(a) for a, _ in shapes])
+    ny = (C.c_int32 * n)(*[int(b) for _, b in shapes])
+    ns = (C.c_int64 * n)(*[int(v) for v in nsteps])
+    verdict, ran = C.c_int32(), C.c_int64()
+    _check(load().lbac_batch_schedule_check(nx, ny, ns, n, int(strip_h), int(workers), int(protocol), int(seed),
+                                            C.byref(verdict), C.byref(ran)), what="lbac_batch_schedule_check")
+    return verdict.value, ran.value
 
 
 def _fp(a):

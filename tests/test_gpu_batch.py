@@ -160,7 +160,9 @@ def test_batch_rejects_short_strips(gpu_lib):
 
 def test_batch_stall_times_out_and_reports(gpu_lib):
     """Every wait asks for a step that never completes; with a 50 ms time-out
-    every workgroup exits and the run reports a device error."""
+    every workgroup exits and the run reports a device error.  The passes that
+    did run overwrote both buffers of some instances, so afterwards the batch
+    and its instances refuse every call with LBAC_ESTATE."""
     say("case: batch forced stall")
     cases, phis, steps = mixed_cases()
     b = gpu_lib.Batch(cases, phis)
@@ -168,4 +170,27 @@ def test_batch_stall_times_out_and_reports(gpu_lib):
     with pytest.raises(gpu_lib.LbacError) as ei:
         b.run([5] * len(cases))
     assert ei.value.code == gpu_lib.LBAC_EDEVICE
+    b.set_timeout(20.0, test_stall=False)
+    with pytest.raises(gpu_lib.LbacError) as ei:
+        b.run([5] * len(cases))
+    assert ei.value.code == gpu_lib.LBAC_ESTATE
+    for call in (lambda i: i.phi(), lambda i: i.mass(), lambda i: i.step(1)):
+        with pytest.raises(gpu_lib.LbacError) as ei:
+            call(b.instance(0))
+        assert ei.value.code == gpu_lib.LBAC_ESTATE
     b.close()
+
+
+def test_batch_runs_with_any_workgroup_count(gpu_lib):
+    """The slot schedule does not depend on how many workgroups are resident:
+    one, two and a prime number of workgroups give the same bitwise results."""
+    say("case: batch with 1, 2 and 7 workgroups")
+    cases, phis, steps = mixed_cases()
+    ref = [single(gpu_lib, c, p, n) for c, p, n in zip(cases, phis, steps)]
+    for wgs in (1, 2, 7):
+        b = gpu_lib.Batch(cases, phis)
+        b.set_shape(16, wgs)
+        b.run(steps)
+        for k in range(len(cases)):
+            assert np.array_equal(b.instance(k).phi(), ref[k]), (wgs, k)
+        b.close()

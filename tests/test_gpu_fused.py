@@ -127,16 +127,83 @@ def test_checkpoint_resume_in_the_middle(gpu_lib, variant):
     assert np.array_equal(a.phi(), b.phi())
 
 
-@pytest.mark.parametrize("prec", ["f64", "f32_f16store", "f32_bf16store"])
-def test_needs_fp32_storage(gpu_lib, prec):
+def test_needs_fp32_collision(gpu_lib):
     case = W.single_vortex_case(32)
-    sim = gpu_lib.Simulation({**case, "precision": prec}, W.circle(32, 1.0))
+    sim = gpu_lib.Simulation({**case, "precision": "f64"}, W.circle(32, 1.0))
     for variant in VARIANTS:
         with pytest.raises(gpu_lib.LbacError):
             sim.set_launch(128, 16, variant)
     with pytest.raises(gpu_lib.LbacError):
         sim.set_launch(128, 16, 5)
     sim.close()
+
+
+# ---- shifted 16-bit storage with the multi-step kernel ------------------------
+# The populations pass through 16 bits at the launch's load and store only; the
+# S - 1 steps in between keep them in FP32 in LDS.  So the result depends on S
+# (how often the storage rounds) but on nothing else: every tile shape and
+# strip height of one variant gives the same bits.
+
+def run16(lb, prec, case, phi0, steps, launch):
+    sim = lb.Simulation({**case, "precision": prec}, phi0)
+    sim.set_launch(*launch)
+    sim.step(steps)
+    return sim
+
+
+@pytest.mark.parametrize("prec", ["f32_f16store", "f32_bf16store"])
+@pytest.mark.parametrize("variant", VARIANTS)
+def test_shifted_storage_bitwise_over_launch_shapes(gpu_lib, prec, variant):
+    say("case: multi-step variant", variant, prec, "over launch shapes")
+    case = W.single_vortex_case(320, U=0.05, period_T=100.0)
+    phi0 = W.circle(320, 1.0)
+    base = run16(gpu_lib, prec, case, phi0, 12, (224, 40, variant)).phi()
+    for bx, strip in ((256, 64), (64, 5), (128, 320), (96, 1), (160, 9), (320, 7), (192, 3)):
+        phi = run16(gpu_lib, prec, case, phi0, 12, (bx, strip, variant)).phi()
+        assert np.array_equal(phi, base), (bx, strip)
+
+
+@pytest.mark.parametrize("prec,tol10", [("f32_f16store", 3e-4), ("f32_bf16store", 3e-3)])
+def test_shifted_storage_short_run_against_oracle(gpu_lib, prec, tol10):
+    """The bounds of the one-step 16-bit kernels (test_gpu_parity): nine steps
+    as three launches of three, plus one one-step launch."""
+    say("case: 10 steps", prec, "three-step kernel")
+    case = W.single_vortex_case(128, eps=1.0, U=0.05, period_T=200.0)
+    phi0 = W.circle(128, 1.0)
+    ref = O.run(O.Params(128, 128, eps=1.0, tau=0.8, delta=1e-10, vel_kind=O.VEL_VORTEX, U=0.05, period_T=200.0),
+                phi0, 10)
+    sim = run16(gpu_lib, prec, case, phi0, 10, (224, 16, FUSED3))
+    assert float(np.linalg.norm(sim.phi() - ref) / np.linalg.norm(ref)) <= tol10
+
+
+@pytest.mark.parametrize("prec", ["f32_f16store", "f32_bf16store"])
+def test_shifted_storage_mass_and_bytes(gpu_lib, prec):
+    """Mass drift over 999 steps (333 launches) within the bound of the
+    one-step 16-bit kernels; 40 bytes per node per launch (8 16-bit planes and
+    the FP32 phi* plane, read and written once)."""
+    say("case: mass", prec, "three-step kernel")
+    case = W.single_vortex_case(256, eps=1.0, period_T=2048.0)
+    sim = gpu_lib.Simulation({**case, "precision": prec}, W.circle(256, 1.0))
+    sim.set_launch(224, 40, FUSED3)
+    assert sim.steps_per_launch() == 3 and sim.bytes_per_node() == 40.0
+    m0 = sim.mass()
+    sim.step(999)
+    assert abs(sim.mass() - m0) / m0 <= 1e-6
+    sim.close()
+
+
+@pytest.mark.parametrize("prec", ["f32_f16store", "f32_bf16store"])
+def test_shifted_storage_reflection_symmetry(gpu_lib, prec):
+    """The mirrored frame of downward strips with 16-bit planes: the run from
+    the mirrored field is the mirror image bit for bit."""
+    say("case: reflection symmetry,", prec, "three-step kernel")
+    nx, ny = 150, 97
+    rng = np.random.default_rng(7)
+    phi0 = W.circle(160, 1.5, R_frac=0.25, yc_frac=0.4)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
+    case = dict(nx=nx, ny=ny, eps=1.0, tau=0.7, delta=1e-10, vel="uniform", ux=0.03, uy=0.021)
+    a = run16(gpu_lib, prec, case, phi0, 15, (224, 12, FUSED3))
+    b = run16(gpu_lib, prec, {**case, "uy": -0.021}, np.ascontiguousarray(phi0[::-1]), 15, (224, 12, FUSED3))
+    assert np.array_equal(b.phi(), a.phi()[::-1])
 
 
 def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
