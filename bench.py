@@ -27,14 +27,16 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-# FP32 vector issue peak without packed instructions (which this build does
-# not use): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T operations/s,
-# i.e. 614.4 G wave64 VALU instructions/s
-ALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+# FP32 vector peak without packed instructions (which this build does not
+# use): 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 39.3 T lane-instructions/s,
+# 78.6 TFLOP/s with an FMA counted as two operations (the 157.3 TFLOP/s
+# figure counts packed FMAs, two per lane); the VALU issues 1024 SIMDs x 2.4
+# GHz / 4 cycles = 614.4 G wave64 instructions/s
+FP32_PEAK_TFLOPS = 256 * 4 * 16 * 2.4e9 * 2 / 1e12
 VALU_ISSUE_PER_S = 256 * 4 * 2.4e9 / 4
-# FP operations per node-update of the method: ~140 plus one log, one square
-# root and one reciprocal
-OPS_PER_NODE_UPDATE = 143.0
+# algorithmic HBM bytes per node-update of the FP32 form: nine populations
+# read and written once (Sec. 2.2, Eq. (9))
+BYTES_PER_NODE_UPDATE = 72.0
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "step_f32_8192_hbm_counters.txt")
 SQ_FILE = os.path.join(ROOT, "profiles", "step_f32_8192_sq_counters.txt")
 
@@ -98,7 +100,13 @@ def measured_valu_instructions(launch):
     return _counter_summary(SQ_FILE, "valu_instructions_per_launch", launch)
 
 
-def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False, graph=0):
+def measured_fp32_flops(launch):
+    """FP32 operations per step-kernel launch counted by the SQ counters:
+    64 lanes x (ADD + MUL + TRANS + 2 FMA wave instructions), or None."""
+    return _counter_summary(SQ_FILE, "fp32_flops_per_launch", launch)
+
+
+def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, autotune=False, graph=0, keep_phi=False):
     # a stream of our own: the library works on it and the events are recorded
     # on it (torch's default stream has handle 0, which the library would
     # replace by a private stream)
@@ -122,47 +130,63 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     if graph:
         sim.set_graph_chunk(graph)
     m0 = sim.mass()
+    spl = sim.steps_per_launch()
     torch.cuda.synchronize()
     ev0 = torch.cuda.Event(enable_timing=True)
+    evm = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
     t0 = time.perf_counter()
+    # the S-step launches, then the one-step launches of the remainder: the
+    # first interval times the dominant kernel alone
     ev0.record(stream)
-    sim.step(steps)
+    sim.step(steps - steps % spl)
+    evm.record(stream)
+    sim.step(steps % spl)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ms = ev0.elapsed_time(ev1)
+    full_launches = steps // spl
+    launch_ms = ev0.elapsed_time(evm) / full_launches if full_launches else None
     e1, e2 = sim.shape_error(phi0)
     m1 = sim.mass()
     assert sim.stream() == stream.cuda_stream
     # practical ceiling: the same bytes moved in the step's access pattern by a plain copy
     copy_us = sim.copy_ceiling(20)
     out = dict(ms_total=ms, wall_s=wall, launch=list(launch), e1=e1, e2=e2, mass_drift=abs(m1 - m0) / m0,
-               bytes_per_node=sim.bytes_per_node(), steps_per_launch=sim.steps_per_launch(), t_end=sim.time(),
-               copy_us=copy_us)
+               bytes_per_node=sim.bytes_per_node(), steps_per_launch=spl, t_end=sim.time(),
+               copy_us=copy_us, launch_ms=launch_ms, full_launches=full_launches, mass=m1)
+    if keep_phi:
+        out["phi"] = sim.phi()
     sim.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     return out
 
 
-def batch_leg(lbac, torch, W, count, seed, step_cap, shape=None):
+def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512):
     """The batched form on the seeded instance list (sides 128..512, eps in
-    {0.5, 1, 2}, tau in [0.6, 1]; half single vortex, half slotted disk under
-    rotation), every instance advanced min(its run length, step_cap) steps in
-    one persistent launch, against the same list advanced one instance after
-    another through lbac_step (default launch shape, HIP-graph replay).
-    shape: (strip height, workgroups) of the batched launch, else autotuned."""
+    {0.5, 1, 2}, tau in [0.6, 1]; half single vortex over one period of 8 N
+    steps, half slotted disk over one revolution of 64 N steps), every
+    instance advanced over its whole run in one run of the batch (instances
+    retire at their own step counts).  Reports the aggregate rate, each
+    instance's E2 against its phi0 at t = T, four instances checked bitwise
+    against the same instance advanced alone, and, for context, the rate of
+    the list advanced one instance after another through lbac_step (three
+    steps per launch, HIP-graph replay) over the first `seq_cap` steps of
+    each instance.  strip_h: rows per item, else autotuned (dry runs)."""
     cases = W.batch_cases(count=count, seed=seed)
     phis = [W.initial_field(c) for c in cases]
-    steps = [min(c["steps"], step_cap) for c in cases]
+    steps = [c["steps"] for c in cases]
     updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, steps)))
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
     b = lbac.Batch(cases, phis, stream=stream.cuda_stream)
-    if shape:
-        b.set_shape(*shape)
+    if strip_h:
+        b.set_shape(strip_h)
     else:
-        b.autotune(4)  # dry runs of one pass each: the instances' state is kept
+        # dry runs (the instances' state is kept) of the real step counts scaled
+        # by 1/16: the same retirement order, so the tail is tuned for too
+        b.autotune([max(3, k // 16) for k in steps])
     torch.cuda.synchronize()
     ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     ev0.record(stream)
@@ -170,34 +194,59 @@ def batch_leg(lbac, torch, W, count, seed, step_cap, shape=None):
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_batch = ev0.elapsed_time(ev1)
-    probe = [0, count // 2 - 1, count // 2, count - 1]
+    e2 = []
+    for k in range(count):
+        inst = b.instance(k)
+        assert inst.time() == steps[k]
+        e2.append(inst.shape_error(phis[k])[1])
+    kinds = ["vortex" if c["vel"] == "vortex" else "slotted disk" for c in cases]
+    probe = sorted({0, count // 2 - 1, count // 2, count - 1})
     got = {k: b.instance(k).phi() for k in probe}
     shape = b.get_shape()
     b.close()
-    # the sequential form replays a captured graph of `chunk` steps per
-    # instance; the first chunk (which captures it) runs outside the timed region
-    chunk = 64
-    sims = [lbac.Simulation({**c, "precision": "f32"}, p, stream=stream.cuda_stream) for c, p in zip(cases, phis)]
-    for sim, k in zip(sims, steps):
-        sim.set_graph_chunk(chunk)
-        sim.step(min(k, chunk))
+
+    def alone(k, n):
+        sim = lbac.Simulation({**cases[k], "precision": "f32"}, phis[k], stream=stream.cuda_stream)
+        sim.set_launch(224, 40, 4)
+        sim.set_graph_chunk(96)
+        sim.step(n)
+        return sim
+
+    same = True
+    for k in probe:
+        sim = alone(k, steps[k])
+        same = same and bool(np.array_equal(got[k], sim.phi()))
+        sim.close()
+    # sequential context rate: the first seq_cap steps of every instance, one after another
+    sims = [alone(k, 0) for k in range(count)]
+    for sim in sims:
+        sim.step(96)  # captures the graph outside the timed region
     torch.cuda.synchronize()
-    seq_updates = float(sum(c["nx"] * c["ny"] * max(0, k - chunk) for c, k in zip(cases, steps)))
+    seq_steps = [max(0, min(k, seq_cap) - 96) for k in steps]
+    seq_updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, seq_steps)))
     ev0.record(stream)
-    for sim, k in zip(sims, steps):
-        sim.step(max(0, k - chunk))
+    for sim, k in zip(sims, seq_steps):
+        sim.step(k)
     ev1.record(stream)
     torch.cuda.synchronize()
     ms_seq = ev0.elapsed_time(ev1)
-    same = all(np.array_equal(got[k], sims[k].phi()) for k in probe)
     for sim in sims:
         sim.close()
     torch.cuda.set_stream(torch.cuda.default_stream())
     mlups = updates / (ms_batch * 1e-3) / 1e6
     seq_mlups = seq_updates / (ms_seq * 1e-3) / 1e6
-    return dict(instances=count, seed=seed, step_cap=step_cap, node_updates=updates, mlups=round(mlups, 1),
-                ms=round(ms_batch, 2), sequential_mlups=round(seq_mlups, 1), sequential_ms=round(ms_seq, 2),
-                speedup=round(mlups / seq_mlups, 3), bitwise_equal_probe=bool(same), shape=list(shape))
+    e2a = np.array(e2)
+    by_kind = {kind: dict(instances=int(sum(1 for x in kinds if x == kind)),
+                          e2_median=float(np.median(e2a[[x == kind for x in kinds]])),
+                          e2_max=float(np.max(e2a[[x == kind for x in kinds]])))
+               for kind in ("vortex", "slotted disk")}
+    return dict(instances=count, seed=seed, node_updates=updates, steps_min=min(steps), steps_max=max(steps),
+                mlups=round(mlups, 1), ms=round(ms_batch, 2), strip_h=shape[0], resident_workgroups=shape[1],
+                e2_at_T=by_kind, e2_per_instance=[float("%.4e" % v) for v in e2],
+                bitwise_equal_probe=same, probed=probe,
+                sequential=dict(mlups=round(seq_mlups, 1), ms=round(ms_seq, 2), steps_per_instance_cap=seq_cap,
+                                launch=[224, 40, 4], graph_chunk=96),
+                speedup_vs_sequential=round(mlups / seq_mlups, 3))
 
 
 def closure_leg(lbac, torch, case, phi0, steps, theta=0.02):
@@ -233,7 +282,10 @@ def c2_leg(lbac, torch, W, n, steps):
     """The 1024^2 single vortex (R = 0.15 n at (0.5 n, 0.75 n), tau 0.8, U
     0.02, period = `steps`) at eps 0.5 and 1 with FP32, FP16 and BF16 shifted
     storage, each over one full period from phi0: MLUPS, E1 and E2 against
-    phi0 at t = T, mass drift, and E2 of each 16-bit form relative to FP32.
+    phi0 at t = T, mass drift, E2 of each 16-bit form relative to FP32, and,
+    where the FP64 oracle's phi(T) of the same run is stored
+    (tests/golden/c2_oracle_*.npz, written by tests/golden/make_c2_oracle.py),
+    the relative L2 distance to it and the mass difference from the oracle's.
     The state (75 MB for FP32) stays in the 256 MB last-level cache, so these
     rates are not HBM rates; the steps are replayed from captured HIP graphs
     of 96 steps."""
@@ -241,11 +293,20 @@ def c2_leg(lbac, torch, W, n, steps):
     for eps in (0.5, 1.0):
         case = W.single_vortex_case(n, eps=eps, tau=0.8, U=0.02, period_T=float(steps))
         phi0 = W.circle(n, eps)
+        golden = os.path.join(ROOT, "tests", "golden", "c2_oracle_%d_eps%g.npz" % (n, eps))
+        ref = None
+        if os.path.exists(golden):
+            z = np.load(golden)
+            if int(z["steps"]) == steps:
+                ref = (z["phi"].astype(np.float64), float(z["massT"]))
         runs = {}
         for prec in ("f32", "f32_f16store", "f32_bf16store"):
-            r = run_form(lbac, torch, case, phi0, prec, steps, 64, autotune=True, graph=96)
+            r = run_form(lbac, torch, case, phi0, prec, steps, 64, autotune=True, graph=96, keep_phi=ref is not None)
             runs[prec] = dict(mlups=round(n * n * steps / (r["ms_total"] * 1e-3) / 1e6, 1), e2=r["e2"], e1=r["e1"],
                               mass_drift=r["mass_drift"], launch=r["launch"])
+            if ref is not None:
+                runs[prec]["rel_l2_vs_oracle"] = float(np.linalg.norm(r["phi"] - ref[0]) / np.linalg.norm(ref[0]))
+                runs[prec]["mass_vs_oracle"] = abs(r["mass"] - ref[1]) / ref[1]
         for prec in ("f32_f16store", "f32_bf16store"):
             runs[prec]["e2_vs_f32"] = runs[prec]["e2"] / runs["f32"]["e2"]
         out["eps=%g" % eps] = runs
@@ -297,6 +358,26 @@ def leg_3d(lbac, torch, W, n, steps, launch=None):
                 mass_drift=abs(m - phi0.sum()) / phi0.sum(), launch=list(launch))
 
 
+def _native_oracle():
+    """The FP64 oracle compiled for the host that runs the benchmark (gcc -O3
+    -march=native, as the CPU baseline asks; the in-tree build is portable
+    -O2), loaded in place of the in-tree build; None if gcc is missing (the
+    in-tree build is then timed and the record says so)."""
+    import tempfile
+
+    from oracle import build as OB
+    from oracle import lib as O
+
+    out = os.path.join(tempfile.gettempdir(), "liboracle_native_%d.so" % os.getpid())
+    try:
+        OB.build_native(out)
+    except (OSError, RuntimeError) as e:
+        print("bench: native oracle build failed (%s); timing the in-tree build" % e, file=sys.stderr, flush=True)
+        return None
+    O.use_library(out)
+    return "gcc " + " ".join(OB.NATIVE_FLAGS)
+
+
 def _oracle_rate(case, phi0, steps):
     """Seconds of stepping (set-up subtracted) of the FP64 oracle for `steps`
     steps of `case`, with whatever OpenMP thread count this process has."""
@@ -318,6 +399,7 @@ def _single_core_child(spec):
     prints one JSON object.  Runs with OMP_NUM_THREADS=1 and touches no GPU."""
     from paper_2203_05230_amd import workloads as W
 
+    _native_oracle()
     n, steps = (int(v) for v in spec.split(","))
     case = W.single_vortex_case(n, eps=1.0, tau=0.8, U=0.02, period_T=4096.0)
     dt = _oracle_rate(case, W.circle(n, 1.0), steps)
@@ -330,11 +412,13 @@ def cpu_baseline(phi0, case, steps, single_core_n=2048, single_core_steps=4):
     core, in a child process, over `single_core_steps` steps of the same
     vortex on a `single_core_n` grid (per-node rate; the grid still far exceeds
     the caches)."""
+    flags = _native_oracle()
     dt = _oracle_rate(case, phi0, steps)
     threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
     out = dict(value=case["nx"] * case["ny"] * steps / dt / 1e6, unit="MLUPS", cores=threads, kind="oracle",
                sample="%d steps of the %dx%d single vortex (FP64 oracle, OpenMP over rows); %.1f s of "
-               "stepping, set-up time subtracted" % (steps, case["nx"], case["ny"], dt))
+               "stepping, set-up time subtracted" % (steps, case["nx"], case["ny"], dt),
+               build=flags or "in-tree build (gcc -O2)")
     if single_core_steps > 0:
         import subprocess
 
@@ -385,8 +469,7 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=16, help="oracle steps for the CPU baseline (0: skip)")
     ap.add_argument("--cpu-single-core", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
-    ap.add_argument("--batch-steps", type=int, default=512, help="steps per instance in the batched leg (cap)")
-    ap.add_argument("--batch-shape", default="", help="strip_h,workgroups of the batched leg (default: autotune)")
+    ap.add_argument("--batch-strip", type=int, default=0, help="strip height of the batched leg (default: autotune)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--c1-steps", type=int, default=2000, help="steps (= period) of the 64^2 FP64 run (0: skip)")
@@ -449,24 +532,25 @@ def main():
     nodes = n * n
     ms_per_step = main_run["ms_total"] / args.steps
     mlups = nodes * args.steps / (main_run["ms_total"] * 1e-3) / 1e6
-    # the dominant kernel: one launch reads and writes the stored state once
-    # and takes steps_per_launch steps (an odd count ends with a one-step launch)
+    # the dominant kernel: the S-step launch, timed alone (HIP events on the
+    # library's stream around the launches of the timed region that take S
+    # steps).  It reads and writes the stored state once and takes spl steps.
     spl = main_run["steps_per_launch"]
-    launches = args.steps // spl + args.steps % spl
-    launch_ms = main_run["ms_total"] / launches
-    alg_bytes = main_run["bytes_per_node"] * nodes
+    launch_ms = main_run["launch_ms"]
+    updates_per_launch = nodes * spl
+    # algorithmic HBM bytes of the method per launch: 72 B per node-update
+    # (every population read and written once per step) x the node-updates of
+    # one launch; the stored state itself crosses HBM once per launch
+    alg_bytes = BYTES_PER_NODE_UPDATE * updates_per_launch
+    state_bytes = main_run["bytes_per_node"] * nodes
     achieved = alg_bytes / (launch_ms * 1e-3) / 1e9
     traffic = measured_traffic(main_run["launch"])
-    # the other resource: FP32 vector issue.  Algorithmic operations per launch
-    # against the issue peak, and (from the committed SQ counters) the share of
-    # the launch the VALU instructions occupy
-    alu_ops = OPS_PER_NODE_UPDATE * spl * nodes
-    alu_achieved = alu_ops / (launch_ms * 1e-3) / 1e12
     valu = measured_valu_instructions(main_run["launch"])
+    flops = measured_fp32_flops(main_run["launch"])
     valu_issue_frac = None if valu is None else valu / VALU_ISSUE_PER_S / (launch_ms * 1e-3)
-    copy_gbs = alg_bytes / (main_run["copy_us"] * 1e-6) / 1e9
-    hbm_practical_frac = None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9 / copy_gbs
-    alu_bound = valu_issue_frac is not None and hbm_practical_frac is not None and valu_issue_frac > hbm_practical_frac
+    fp32_tflops = None if flops is None else flops / (launch_ms * 1e-3) / 1e12
+    copy_gbs = state_bytes / (main_run["copy_us"] * 1e-6) / 1e9
+    counter_gbs = None if traffic is None else traffic / (launch_ms * 1e-3) / 1e9
     one_step = None
     if spl > 1 and args.one_step_steps > 0:
         # the same launch shape with the one-step kernel, for comparison
@@ -492,8 +576,7 @@ def main():
     batched = None
     if args.batch > 0:
         print("bench: batched form, %d instances" % args.batch, file=sys.stderr, flush=True)
-        bshape = tuple(int(v) for v in args.batch_shape.split(",")) if args.batch_shape else None
-        batched = batch_leg(lbac, torch, W, args.batch, 0, args.batch_steps, shape=bshape)
+        batched = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None)
     closure = None
     if args.closure_steps > 0:
         print("bench: closure", file=sys.stderr, flush=True)
@@ -532,22 +615,23 @@ def main():
                                % (n, n, args.eps, args.period, args.precision),
                    "grid": n, "precision": args.precision, "launch": main_run["launch"]},
         "roofline": dict(
-            ({"bound": "alu", "achieved": round(alu_achieved, 2), "peak": round(ALU_PEAK_TOPS, 2), "unit": "TFLOP/s",
-              "frac": round(alu_achieved / ALU_PEAK_TOPS, 4)} if alu_bound else
+            ({"bound": "alu", "achieved": round(fp32_tflops, 2), "peak": round(FP32_PEAK_TFLOPS, 1),
+              "unit": "TFLOP/s", "frac": round(fp32_tflops / FP32_PEAK_TFLOPS, 4)} if fp32_tflops is not None else
              {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
               "frac": round(achieved / HBM_PEAK_GBS, 4)}),
             traffic=None if traffic is None else round(traffic, 0),
-            steps_per_launch=spl, launch_ms=round(launch_ms, 4),
-            hbm={"achieved_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
-                 "algorithmic_bytes_per_launch": alg_bytes,
-                 "bytes_per_node_per_step": main_run["bytes_per_node"] / spl,
-                 "pattern_copy_gbs": round(copy_gbs, 1),
-                 "frac_of_pattern_copy": round(main_run["copy_us"] * 1e-3 / launch_ms, 4),
-                 "measured_frac_of_pattern_copy": None if hbm_practical_frac is None else round(hbm_practical_frac, 4)},
-            alu={"ops_per_node_update": OPS_PER_NODE_UPDATE, "achieved_tops": round(alu_achieved, 2),
-                 "peak_tops": round(ALU_PEAK_TOPS, 2), "frac": round(alu_achieved / ALU_PEAK_TOPS, 4),
-                 "valu_instructions_per_launch": valu,
-                 "valu_issue_frac": None if valu_issue_frac is None else round(valu_issue_frac, 4)}),
+            kernel="stepS_kernel_lds<improved, %d, %d, FP32 storage>" % (main_run["launch"][0], spl),
+            steps_per_launch=spl, launch_ms=round(launch_ms, 4), launches_timed=main_run["full_launches"],
+            valu={"instructions_per_launch": valu,
+                  "issue_frac": None if valu_issue_frac is None else round(valu_issue_frac, 4),
+                  "fp32_flops_per_launch": flops,
+                  "fp32_flops_per_node_update": None if flops is None else round(flops / updates_per_launch, 1)},
+            hbm={"bytes_per_node_update": BYTES_PER_NODE_UPDATE, "algorithmic_bytes_per_launch": alg_bytes,
+                 "achieved_gbs": round(achieved, 1), "frac": round(achieved / HBM_PEAK_GBS, 4),
+                 "state_bytes_per_launch": state_bytes,
+                 "counter_gbs": None if counter_gbs is None else round(counter_gbs, 1),
+                 "counter_frac": None if counter_gbs is None else round(counter_gbs / HBM_PEAK_GBS, 4),
+                 "pattern_copy_gbs": round(copy_gbs, 1)}),
         "one_step_kernel": one_step,
         "shape_error": {"t": main_run["t_end"], "e2": main_run["e2"], "e1": main_run["e1"],
                         "mass_drift": main_run["mass_drift"]},

@@ -214,18 +214,19 @@ void* lbac_stream(lbac_ctx* h);
 
 /* ---- batched form --------------------------------------------------------
  * Many independent lattices (instances) of uneven sizes and parameters
- * advanced together by ONE persistent kernel launch (plus one for the last
- * nsteps mod 3 steps), replayed from a captured HIP graph.  Work is split
- * into (instance, column tile of at most 224 columns, strip of rows) items.
- * An item takes three steps per pass (the populations between them kept in
- * LDS, as with LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step
- * passes).  The (pass, item) slots are numbered pass by pass and workgroups
- * take them one at a time from an atomic counter; a slot waits, through
- * per-item progress counters, for the previous pass of its own item and of
- * the items its read region overlaps (no grid-wide barrier), so instances
- * retire independently.  Every slot waited for has a smaller number and is
- * held by a running workgroup or done, so the schedule progresses whatever
- * number of workgroups the device keeps resident.  Every instance uses FP32
+ * advanced together by ONE kernel launch (plus one for the last nsteps mod 3
+ * steps), replayed from a captured HIP graph.  Work is split into (instance,
+ * column tile of at most 224 columns, strip of rows) items.  An item takes
+ * three steps per pass (the populations between them kept in LDS, as with
+ * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes).  The
+ * (pass, item) slots are numbered pass by pass; the launch has one workgroup
+ * per slot and each takes the next slot number from an atomic counter when
+ * it starts, then waits, through per-item progress counters, for the
+ * previous pass of its own item and of the items its read region overlaps
+ * (no grid-wide barrier), so instances retire independently.  Every slot
+ * waited for has a smaller number and belongs to a workgroup that has
+ * started, so the schedule progresses whatever number of workgroups the
+ * device keeps resident.  Every instance uses FP32
  * collide and storage and the improved model; results are bitwise those of
  * lbac_step on the same instance.  A wait that exceeds the time-out makes
  * every workgroup exit and the run return LBAC_EDEVICE. */
@@ -251,15 +252,18 @@ int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
 int lbac_batch_count(lbac_batch* b, int32_t* count);
 
-/* Strip height (rows per item, >= 8) and workgroup count (0: as many as the
- * device keeps resident, which is also the maximum). */
-int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups);
-int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, int32_t* max_workgroups);
+/* Strip height (rows per item, >= 8; the default is 40).  get_shape also
+ * gives the number of batch workgroups the device keeps resident at once
+ * (information only: the schedule does not depend on it). */
+int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h);
+int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* resident_workgroups);
 
-/* Times strip heights and workgroup counts on `steps` steps of every instance
- * (reading the current state, writing only scratch: state and time unchanged)
- * and keeps the fastest; *ms (may be NULL) gets its time. */
-int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms);
+/* Times every candidate strip height on a dry run of nsteps[k] steps of
+ * instance k (host array of count values; each pass reads the current state
+ * and writes only the other buffer: state and time unchanged) and keeps the
+ * fastest; *ms (may be NULL) gets its time.  Step counts in the proportions
+ * of the real run make the tuning see its tail, where few instances are left. */
+int lbac_batch_autotune(lbac_batch* b, const int64_t* nsteps, double* ms);
 
 /* Time-out of one dependency wait (default 20 s).  test_stall != 0 makes
  * every wait ask for a pass that never completes, so that the time-out path

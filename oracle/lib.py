@@ -38,13 +38,21 @@ class OrcParams(C.Structure):
 
 
 _lib = None
+_path = None  # a build other than the in-tree one (use_library)
+
+
+def use_library(path):
+    """Loads the oracle from `path` (another build of lbm_oracle.c, for
+    example one compiled for the host's own CPU) instead of the in-tree one."""
+    global _lib, _path
+    _lib, _path = None, path
 
 
 def lib():
     global _lib
     if _lib is None:
-        path = _build.LIB
-        if not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC):
+        path = _path or _build.LIB
+        if _path is None and (not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_build.SRC)):
             _build.build()
         L = C.CDLL(path)
         dp = C.POINTER(C.c_double)

@@ -29,6 +29,8 @@ namespace {
 
 // Rows per strip at least (a shorter last strip of an instance is allowed).
 constexpr int kBatchMinStrip = kBatchGrow + 2;
+// Workgroups of one batch launch at most: (2^32 - 1) work-items.
+constexpr int64_t kBatchMaxGrid = 0xFFFFFFFFll / kBatchThreads;
 
 struct Geometry {
     int nx, ny;
@@ -140,8 +142,7 @@ struct lbac_batch {
     bool own_stream = false;
     std::vector<lbac_ctx*> inst;
     int strip_h = 40;   // >= kBatchMinStrip
-    int wgs = 0;        // 0: occupancy limit
-    int max_wgs = 0;    // occupancy limit (resident workgroups)
+    int max_wgs = 0;    // workgroups the device keeps resident at once (information only)
     double ticks_per_s = 1e8;
     double timeout_s = 20.0;
     int test_stall = 0;
@@ -149,7 +150,8 @@ struct lbac_batch {
     // schedule
     int items_h = -1;  // strip height the item list was built for
     std::vector<ItemH> items;
-    int nitems = 0, nwg = 0;
+    int nitems = 0;
+    int64_t nslots[2] = {0, 0};  // slots (workgroups) of the two launches of the current run
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
     int32_t* d_order[2] = {nullptr, nullptr};
@@ -163,7 +165,7 @@ struct lbac_batch {
     int cap_items = 0;
     int64_t cap_cum[2] = {0, 0};
     hipGraphExec_t gexec = nullptr;
-    int g_nwg = -1;
+    int64_t g_slots[2] = {-1, -1};  // grids the captured graph was made for
     std::string err;
 };
 
@@ -183,7 +185,7 @@ int bfail(lbac_batch* b, int code, const std::string& msg) {
 void drop_graph(lbac_batch* b) {
     if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
     b->gexec = nullptr;
-    b->g_nwg = -1;
+    b->g_slots[0] = b->g_slots[1] = -1;
 }
 
 void free_tables(lbac_batch* b) {
@@ -254,8 +256,10 @@ int ensure_tables(lbac_batch* b, const int64_t npass[2]) {
     return LBAC_OK;
 }
 
+// The run as one graph; its two batch launches have one workgroup per slot,
+// so the graph is captured again when the slot counts change.
 int capture(lbac_batch* b) {
-    if (b->gexec && b->g_nwg == b->nwg) return LBAC_OK;
+    if (b->gexec && b->g_slots[0] == b->nslots[0] && b->g_slots[1] == b->nslots[1]) return LBAC_OK;
     drop_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const int count = (int)b->inst.size();
@@ -264,23 +268,30 @@ int capture(lbac_batch* b) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((nreset + 255) / 256), dim3(256), 0, b->stream, b->d_done, nreset,
                        b->d_ctl, 0, 1);
     hipError_t e = hipGetLastError();
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3(b->nwg), dim3(kBatchThreads), 0, b->stream,
-                           b->d_inst, b->d_items, BatchSlots{b->d_order[0], b->d_cum[0], b->d_npass}, b->d_done,
-                           b->d_ctl);
-        e = hipGetLastError();
-    }
+    // one workgroup per slot; a dispatch holds at most 2^32 - 1 work-items,
+    // so a launch with more slots is split into consecutive launches, all
+    // taking slot numbers from the same counter
+    auto launch_slots = [&](int L) {
+        for (int64_t left = b->nslots[L]; left > 0 && e == hipSuccess;) {
+            const int64_t g = std::min<int64_t>(left, kBatchMaxGrid);
+            const BatchSlots sl{b->d_order[L], b->d_cum[L], b->d_npass + L};
+            if (L == 0)
+                hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
+                                   b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
+            else
+                hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3((unsigned)g), dim3(kBatchThreads), 0,
+                                   b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
+            e = hipGetLastError();
+            left -= g;
+        }
+    };
+    launch_slots(0);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(batch_reset_kernel, dim3((nreset + 255) / 256), dim3(256), 0, b->stream, b->d_done, nreset,
                            b->d_ctl, 1, 0);
         e = hipGetLastError();
     }
-    if (e == hipSuccess) {
-        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3(b->nwg), dim3(kBatchThreads), 0, b->stream,
-                           b->d_inst, b->d_items, BatchSlots{b->d_order[1], b->d_cum[1], b->d_npass + 1}, b->d_done,
-                           b->d_ctl);
-        e = hipGetLastError();
-    }
+    launch_slots(1);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(batch_advance_kernel, dim3((count + 255) / 256), dim3(256), 0, b->stream, b->d_inst, count,
                            b->d_ctl);
@@ -295,7 +306,8 @@ int capture(lbac_batch* b) {
     e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(b, LBAC_EDEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));
-    b->g_nwg = b->nwg;
+    b->g_slots[0] = b->nslots[0];
+    b->g_slots[1] = b->nslots[1];
     return LBAC_OK;
 }
 
@@ -328,14 +340,16 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
         npass[1] = std::max(npass[1], pr[k]);
     }
     if (npass[0] > INT32_MAX) return bfail(b, LBAC_EINVAL, "too many passes");
-    const int nwg = std::max(1, b->wgs > 0 ? std::min(b->wgs, b->max_wgs) : b->max_wgs);
-    b->nwg = nwg;
     int rc = ensure_tables(b, npass);
     if (rc != LBAC_OK) return rc;
     std::vector<int32_t> order[2];
     std::vector<int64_t> cum[2];
     build_slots(b->items, pf, order[0], cum[0]);
     build_slots(b->items, pr, order[1], cum[1]);
+    for (int L = 0; L < 2; ++L) {
+        b->nslots[L] = cum[L].back();
+        if (b->nslots[L] > 64 * kBatchMaxGrid) return bfail(b, LBAC_EINVAL, "too many slots");
+    }
     std::vector<BatchItem> di(b->nitems);
     for (int i = 0; i < b->nitems; ++i) {
         const ItemH& it = b->items[i];
@@ -489,53 +503,44 @@ int lbac_batch_count(lbac_batch* b, int32_t* count) {
     return LBAC_OK;
 }
 
-int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h, int32_t workgroups) {
+int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h) {
     if (!b) return LBAC_EINVAL;
     if (strip_h < kBatchMinStrip) return bfail(b, LBAC_EINVAL, "strip height must be >= 8");
-    if (workgroups < 0) return bfail(b, LBAC_EINVAL, "workgroups must be >= 0 (0: occupancy limit)");
     b->strip_h = strip_h;
-    b->wgs = workgroups;
     return LBAC_OK;
 }
 
-int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* workgroups, int32_t* max_workgroups) {
+int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* resident_workgroups) {
     if (!b) return LBAC_EINVAL;
     if (strip_h) *strip_h = b->strip_h;
-    if (workgroups) *workgroups = b->wgs > 0 ? std::min(b->wgs, b->max_wgs) : b->max_wgs;
-    if (max_workgroups) *max_workgroups = b->max_wgs;
+    if (resident_workgroups) *resident_workgroups = b->max_wgs;
     return LBAC_OK;
 }
 
-int lbac_batch_autotune(lbac_batch* b, int32_t steps, double* ms) {
-    if (!b || steps < 1) return LBAC_EINVAL;
+int lbac_batch_autotune(lbac_batch* b, const int64_t* nsteps, double* ms) {
+    if (!b || !nsteps) return LBAC_EINVAL;
     if (b->failed) return bfail(b, LBAC_ESTATE, "a previous run timed out; the batch state is undefined");
     DeviceGuard g(b->device);
     const int count = (int)b->inst.size();
-    std::vector<int64_t> ns(count, steps);
-    const int keep_h = b->strip_h, keep_w = b->wgs;
-    const int hs[8] = {16, 24, 32, 40, 48, 64, 96, 128};
-    const int fr[3] = {4, 3, 2};  // workgroups = max * fr / 4
+    std::vector<int64_t> ns(nsteps, nsteps + count);
+    const int keep_h = b->strip_h;
+    const int hs[10] = {16, 24, 32, 40, 48, 64, 80, 96, 128, 192};
     float best = 1e30f;
-    int best_h = keep_h, best_w = keep_w;
-    for (int h : hs)
-        for (int f : fr) {
-            b->strip_h = h;
-            b->wgs = std::max(1, b->max_wgs * f / 4);
-            float t = 0.f;
-            const int rc = run(b, ns.data(), true, &t);
-            if (rc != LBAC_OK) {
-                b->strip_h = keep_h;
-                b->wgs = keep_w;
-                return rc;
-            }
-            if (t < best) {
-                best = t;
-                best_h = h;
-                best_w = b->wgs;
-            }
+    int best_h = keep_h;
+    for (int h : hs) {
+        b->strip_h = h;
+        float t = 0.f;
+        const int rc = run(b, ns.data(), true, &t);
+        if (rc != LBAC_OK) {
+            b->strip_h = keep_h;
+            return rc;
         }
+        if (t < best) {
+            best = t;
+            best_h = h;
+        }
+    }
     b->strip_h = best_h;
-    b->wgs = best_w;
     if (ms) *ms = best;
     return LBAC_OK;
 }
@@ -603,7 +608,6 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
         }
         std::vector<int32_t> done(n, -1);
         std::vector<Slot> slot(workers);
-        std::vector<int32_t> cursor(workers, 0);
         std::vector<bool> busy(workers, false);
         // protocol 2 state of a worker: its list, pass and position in the list
         std::vector<int> wl(workers, -1), wpos(workers, 0);
@@ -666,8 +670,7 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
                 if (protocol == 2) {
                     if (!static_next(w, s)) continue;
                 } else {
-                    s.id = batch_slot(tab, next++, cursor[w]);
-                    s.p = cursor[w];
+                    s.id = batch_slot_item(tab, next++, npass, s.p);
                 }
                 s.gp = (L == 0 ? 0 : pf[items[s.id].inst]) + s.p;
                 s.started = false;

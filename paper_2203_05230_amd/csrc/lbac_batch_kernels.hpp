@@ -19,16 +19,17 @@
 // around it) and writes its own tile once.
 //
 // Schedule.  The (pass, item) slots of a launch are numbered pass-major (every
-// slot of pass p before any slot of pass p + 1) and workgroups take them one
-// at a time from a single atomic counter.  Before slot (p, I) runs it waits
-// until I and the items whose tiles overlap I's read region have published
-// pass p - 1: they wrote the rows I reads, and (the relation is symmetric)
-// they have finished reading the part of the buffer I is about to overwrite.
-// Every slot waited for has a smaller number, so it is finished or held by a
-// workgroup that is running: the lowest unfinished slot can always proceed,
+// slot of pass p before any slot of pass p + 1) and each workgroup of the
+// launch takes one slot number from a single atomic counter when it starts.
+// Before slot (p, I) runs it waits until I and the items whose tiles overlap
+// I's read region have published pass p - 1: they wrote the rows I reads, and
+// (the relation is symmetric) they have finished reading the part of the
+// buffer I is about to overwrite.  Every slot waited for has a smaller
+// number, so it is finished or held by a workgroup that has started and stays
+// resident until it is done: the lowest unfinished slot can always proceed,
 // whatever number of workgroups the device keeps resident, and the schedule
 // cannot deadlock.  Every wait is also bounded in wall-clock time and sets an
-// error flag that makes all workgroups exit.
+// error flag that makes all later workgroups exit at once.
 namespace lbac {
 
 constexpr int kBatchTile = 224;          // widest item tile (columns)
@@ -97,51 +98,66 @@ struct BatchSlots {
     const int32_t* npass;  // passes of the launch (device memory: a captured graph's arguments stay valid)
 };
 
-// Maps slot number T of a launch to its pass (cursor p advanced from its
-// previous value: a workgroup's slot numbers only increase) and item.
-__host__ __device__ inline int32_t batch_slot(const BatchSlots& s, int64_t T, int32_t& p) {
-    while (s.cum[p + 1] <= T) ++p;
-    return s.order[T - s.cum[p]];
+// Maps slot number T of a launch to its pass p (binary search of the slot
+// starts; cum has npass + 1 entries) and item.
+__host__ __device__ inline int32_t batch_slot_item(const BatchSlots& s, int64_t T, int32_t npass, int32_t& p) {
+    int32_t lo = 0, hi = npass;
+    while (hi - lo > 1) {
+        const int32_t mid = (lo + hi) / 2;
+        if (s.cum[mid] <= T) lo = mid;
+        else hi = mid;
+    }
+    p = lo;
+    return s.order[T - s.cum[lo]];
 }
 
-// S = kBatchS: the full passes; S = 1: the remaining one-step passes (launch
-// L = 1).  Both use the tile function of the multi-step kernel, so one block
-// shape serves both and the results are those of the single-instance kernels.
+// One workgroup per slot: a workgroup takes the next slot number from the
+// launch's counter when it starts (so the slot numbers are taken in the order
+// the workgroups start, and every smaller number belongs to a workgroup that
+// has started), waits for the slot's dependencies, runs it and publishes.
+// The grid has one workgroup per slot of the launch; the hardware dispatcher
+// refills the device as workgroups finish.  S = kBatchS: the full passes;
+// S = 1: the remaining one-step passes (launch L = 1).  Both use the tile
+// function of the multi-step kernel, so one block shape serves both and the
+// results are those of the single-instance kernels.  Three waves per SIMD:
+// 157 registers, no scratch.
 template <int MODEL, int S>
-__global__ __launch_bounds__(kBatchThreads) void batch_kernel(const BatchInst* __restrict__ insts,
-                                                              const BatchItem* __restrict__ items, BatchSlots slots,
-                                                              int32_t* done, BatchCtl* ctl) {
+__global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3))) void batch_kernel(
+    const BatchInst* __restrict__ insts, const BatchItem* __restrict__ items, BatchSlots slots, int32_t* done,
+    BatchCtl* ctl) {
     static_assert(stepS_threads<kBatchTile, S>() == kBatchThreads, "one block size serves both launches");
     constexpr int L = S == 1 ? 1 : 0;
     __shared__ TileSLds<kBatchTile, S> lds;
     __shared__ int64_t slot;
-    const int64_t total = slots.cum[*slots.npass];
-    const bool dry = ctl->dry != 0;
-    int32_t p = 0;
-    for (;;) {
-        if (threadIdx.x == 0) {
-            const bool stop = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
-            slot = stop ? total : (int64_t)atomicAdd((unsigned long long*)&ctl->ticket[L], 1ull);
-        }
-        __syncthreads();
-        const int64_t T = slot;  // rewritten only after the barriers of this slot's work
-        if (T >= total) return;
-        const int32_t id = batch_slot(slots, T, p);
-        const BatchItem& item = items[id];
-        if (p > 0) {
-            const bool ok = batch_wait(done, item.dep, p - 1, ctl);
-            if (__syncthreads_or(!ok)) return;  // every wavefront leaves together
-        }
-        const int64_t nfull = insts[2 * item.inst].nsteps / kBatchS;
-        const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
-        const StepArgs& a = insts[2 * item.inst + (int)(gp & 1)].a;
-        const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : (int64_t)p * kBatchS));
-        stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0, lds);
-        // publish: every wavefront's stores are visible before the counter moves
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-        __syncthreads();
-        if (threadIdx.x == 0) __hip_atomic_store(done + id, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const int32_t npass = *slots.npass;
+    const int64_t total = slots.cum[npass];
+    if (threadIdx.x == 0) {
+        const bool stop = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
+        slot = stop ? total : (int64_t)atomicAdd((unsigned long long*)&ctl->ticket[L], 1ull);
     }
+    __syncthreads();
+    // read as a uniform value, so that the item and its instance's arguments
+    // are scalar loads into scalar registers
+    const int64_t T = (int64_t)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(slot >> 32)) << 32) |
+                                (uint32_t)__builtin_amdgcn_readfirstlane((int)slot));
+    if (T >= total) return;
+    int32_t p;
+    const int32_t id = batch_slot_item(slots, T, npass, p);
+    const BatchItem& item = items[id];
+    if (p > 0) {
+        const bool ok = batch_wait(done, item.dep, p - 1, ctl);
+        if (__syncthreads_or(!ok)) return;  // every wavefront leaves together
+    }
+    const bool dry = ctl->dry != 0;
+    const int64_t nfull = insts[2 * item.inst].nsteps / kBatchS;
+    const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
+    const StepArgs& a = insts[2 * item.inst + (int)(gp & 1)].a;
+    const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : (int64_t)p * kBatchS));
+    stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0, lds);
+    // publish: every wavefront's stores are visible before the counter moves
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (threadIdx.x == 0) __hip_atomic_store(done + id, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Resets the progress counters and the slot counter of launch L and, if

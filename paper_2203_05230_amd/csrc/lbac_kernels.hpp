@@ -723,7 +723,8 @@ struct TileSLds {
 };
 
 // Threads of an S-step tile of at most BX columns: the BX + 4S columns of the
-// grown tile rounded up to whole wavefronts.
+// grown tile rounded up to whole wavefronts (enough for the layout below at
+// every tile width up to BX).
 template <int BX, int S>
 __host__ __device__ constexpr int stepS_threads() {
     return (BX + 4 * S + 63) / 64 * 64;
@@ -732,18 +733,27 @@ __host__ __device__ constexpr int stepS_threads() {
 template <int MODEL, int BX, int S, int ST>
 __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w, int ys, int hh, int64_t t,
                                                bool down, TileSLds<BX, S>& lds) {
-    // Thread l works on column l - 2S of the grown tile (columns -2S ..
-    // w + 2S - 1 relative to x0; the tile starts on a 128-byte line, so every
-    // line of its rows is written whole by this block).  Threads past the
-    // grown tile (a tile narrower than BX) duplicate its last column: they
-    // load what its owner loads, write their LDS values to the padding column
-    // and store nothing; a wavefront with no column at all only takes part in
-    // the barriers.  act: owns tile column x0 + cxo.
+    // Thread layout.  The C = 64 * c columns of the tile that whole wavefronts
+    // own go to wavefronts 0 .. c - 1, one aligned 64-column segment each (so
+    // every wavefront loads and stores whole 256-byte lines); wavefront c, the
+    // halo wavefront, takes the 2S left halo columns, the tile's remaining
+    // w - C columns and the right halo (c is the largest count for which that
+    // fits in 64 lanes, else one more, whose last columns then belong to the
+    // right halo); later wavefronts (a tile narrower than BX) only take part
+    // in the barriers.  Threads whose column lies past the right halo
+    // duplicate its last column: they load what its owner loads, write their
+    // LDS values to the padding column and store nothing.  cxo: column
+    // relative to x0 (-2S .. w + 2S - 1); act: owns tile column x0 + cxo.
     const int l = threadIdx.x;
-    const int ncol = w + 4 * S;
-    const bool dup = l >= ncol;
-    const int cxo = min(l, ncol - 1) - 2 * S;
-    const bool act = !dup && cxo >= 0 && cxo < w;
+    const int wv = __builtin_amdgcn_readfirstlane(l) / kWave;  // wavefront index (uniform)
+    const int full = w / kWave;
+    const int C = (w - kWave * full) + 4 * S <= kWave ? kWave * full : kWave * (full + 1);
+    const int hw = C / kWave;  // the halo wavefront
+    const int hl = l - C;      // lane in the halo wavefront
+    const int craw = wv < hw ? l : (hl < 2 * S ? hl - 2 * S : C + hl - 2 * S);
+    const bool dup = craw > w + 2 * S - 1;
+    const int cxo = min(craw, w + 2 * S - 1);
+    const bool act = cxo >= 0 && cxo < w && !dup;
     // Stage k forms phi/psi validly on columns -(2(S-k)-1) .. w+2(S-k)-2 and
     // updates -(2(S-k)-2) .. w+2(S-k)-3.  Every thread runs every stage
     // (branching on these ranges would only hold per-lane masks, since every
@@ -764,7 +774,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
     const int iters = hh + 5 * S - 1;
-    if (__builtin_amdgcn_readfirstlane(l) / kWave * kWave >= ncol) {
+    if (wv > hw) {
         // no column in this wavefront: the loop's two barriers per iteration only
         for (int it = 0; it < iters; ++it) {
             lds_barrier();

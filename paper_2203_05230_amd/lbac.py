@@ -128,9 +128,9 @@ def load():
     L.lbac_batch_run.argtypes = [C.c_void_p, P(C.c_int64)]
     L.lbac_batch_instance.argtypes = [C.c_void_p, C.c_int32, ctx_pp]
     L.lbac_batch_count.argtypes = [C.c_void_p, P(C.c_int32)]
-    L.lbac_batch_set_shape.argtypes = [C.c_void_p, C.c_int32, C.c_int32]
-    L.lbac_batch_get_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32), P(C.c_int32)]
-    L.lbac_batch_autotune.argtypes = [C.c_void_p, C.c_int32, dp]
+    L.lbac_batch_set_shape.argtypes = [C.c_void_p, C.c_int32]
+    L.lbac_batch_get_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
+    L.lbac_batch_autotune.argtypes = [C.c_void_p, P(C.c_int64), dp]
     L.lbac_batch_set_timeout.argtypes = [C.c_void_p, C.c_double, C.c_int32]
     L.lbac_batch_last_error.argtypes = [C.c_void_p]
     L.lbac_batch_schedule_check.argtypes = [P(C.c_int32), P(C.c_int32), P(C.c_int64), C.c_int32, C.c_int32,
@@ -401,17 +401,23 @@ class Batch:
         nx, ny = self.shapes[k]
         return _Borrowed(c, nx, ny)
 
-    def set_shape(self, strip_h, workgroups=0):
-        self._err(load().lbac_batch_set_shape(self.h, int(strip_h), int(workgroups)))
+    def set_shape(self, strip_h):
+        self._err(load().lbac_batch_set_shape(self.h, int(strip_h)))
 
     def get_shape(self):
-        a, b, c = C.c_int32(), C.c_int32(), C.c_int32()
-        self._err(load().lbac_batch_get_shape(self.h, C.byref(a), C.byref(b), C.byref(c)))
-        return a.value, b.value, c.value
+        """(strip height, workgroups the device keeps resident at once)."""
+        a, b = C.c_int32(), C.c_int32()
+        self._err(load().lbac_batch_get_shape(self.h, C.byref(a), C.byref(b)))
+        return a.value, b.value
 
     def autotune(self, steps=8):
+        """Tunes the strip height on dry runs of `steps` steps per instance (an
+        int, or one count per instance); returns the best time in ms."""
+        if np.ndim(steps) == 0:
+            steps = [int(steps)] * self.count
+        ns = (C.c_int64 * self.count)(*[int(v) for v in steps])
         ms = C.c_double()
-        self._err(load().lbac_batch_autotune(self.h, int(steps), C.byref(ms)))
+        self._err(load().lbac_batch_autotune(self.h, ns, C.byref(ms)))
         return ms.value
 
     def set_timeout(self, seconds, test_stall=False):

@@ -18,13 +18,19 @@ def test_counter_summaries_parse_and_are_consistent():
     kv = fields(bench.COUNTERS_FILE)
     shape = tuple(int(v) for v in kv["launch"].split(","))
     assert len(shape) == 3 and shape[2] in (3, 4)  # a multi-step variant
-    alg = float(kv["algorithmic_bytes_per_launch"])
-    assert alg == 72.0 * 8192 * 8192  # 9 planes read + 9 written, FP32, per launch
+    state = float(kv["state_bytes_per_launch"])
+    assert state == 72.0 * 8192 * 8192  # the stored state (9 FP32 planes) read and written once per launch
     hbm = float(kv["hbm_bytes_per_launch"])
-    assert alg <= hbm <= 2.0 * alg  # writes are exact; reads add halo rows and columns
+    assert state <= hbm <= 2.0 * state  # writes are exact; reads add halo rows and columns
     sq = fields(bench.SQ_FILE)
     assert sq["launch"] == kv["launch"] and sq["kernel_source_sha"] == kv["kernel_source_sha"]
     assert float(sq["valu_instructions_per_launch"]) > 0 and float(sq["launch_us"]) > 0
+    # FP32 operations: 64 lanes x (ADD + MUL + TRANS + 2 FMA) wave instructions
+    w = {k: float(sq[k]) for k in ("SQ_INSTS_VALU_ADD_F32", "SQ_INSTS_VALU_MUL_F32", "SQ_INSTS_VALU_TRANS_F32",
+                                     "SQ_INSTS_VALU_FMA_F32")}
+    flops = 64 * (w["SQ_INSTS_VALU_ADD_F32"] + w["SQ_INSTS_VALU_MUL_F32"] + w["SQ_INSTS_VALU_TRANS_F32"]
+                  + 2 * w["SQ_INSTS_VALU_FMA_F32"])
+    assert float(sq["fp32_flops_per_launch"]) == pytest.approx(flops, rel=1e-9)
 
 
 def test_counters_are_matched_on_the_full_launch_shape():
@@ -44,7 +50,7 @@ def test_trace_summary_names_the_profiled_launch():
     kv = fields(bench.COUNTERS_FILE)
     text = open(os.path.join(ROOT, "profiles", "step_f32_8192_kernel_trace.md")).read()
     assert "--launch " + kv["launch"] in text
-    assert "stepS_kernel_lds<0, %s, 3>" % kv["launch"].split(",")[0] in text
+    assert "stepS_kernel_lds<0, %s, 3, 0>" % kv["launch"].split(",")[0] in text
 
 
 def test_multi_gpu_request_is_refused():

@@ -59,12 +59,12 @@ def test_batch_bitwise_equals_single_instances(gpu_lib):
     b.close()
 
 
-@pytest.mark.parametrize("strip_h,wgs", [(8, 0), (9, 5), (32, 1), (64, 0), (128, 3)])
-def test_batch_shapes_and_continuation(gpu_lib, strip_h, wgs):
-    say("case: batch shape", strip_h, wgs)
+@pytest.mark.parametrize("strip_h", [8, 9, 32, 64, 128])
+def test_batch_shapes_and_continuation(gpu_lib, strip_h):
+    say("case: batch strip height", strip_h)
     cases, phis, steps = mixed_cases()
     b = gpu_lib.Batch(cases, phis)
-    b.set_shape(strip_h, wgs)
+    b.set_shape(strip_h)
     first = [n // 2 for n in steps]
     b.run(first)
     b.run([n - f for n, f in zip(steps, first)])
@@ -154,7 +154,7 @@ def test_batch_rejects_short_strips(gpu_lib):
     cases, phis, steps = mixed_cases()
     b = gpu_lib.Batch(cases[:2], phis[:2])
     with pytest.raises(gpu_lib.LbacError):
-        b.set_shape(7, 0)
+        b.set_shape(7)
     b.close()
 
 
@@ -168,7 +168,7 @@ def test_batch_stall_times_out_and_reports(gpu_lib):
     b = gpu_lib.Batch(cases, phis)
     b.set_timeout(0.05, test_stall=True)
     with pytest.raises(gpu_lib.LbacError) as ei:
-        b.run([5] * len(cases))
+        b.run([11] * len(cases))
     assert ei.value.code == gpu_lib.LBAC_EDEVICE
     b.set_timeout(20.0, test_stall=False)
     with pytest.raises(gpu_lib.LbacError) as ei:
@@ -179,18 +179,3 @@ def test_batch_stall_times_out_and_reports(gpu_lib):
             call(b.instance(0))
         assert ei.value.code == gpu_lib.LBAC_ESTATE
     b.close()
-
-
-def test_batch_runs_with_any_workgroup_count(gpu_lib):
-    """The slot schedule does not depend on how many workgroups are resident:
-    one, two and a prime number of workgroups give the same bitwise results."""
-    say("case: batch with 1, 2 and 7 workgroups")
-    cases, phis, steps = mixed_cases()
-    ref = [single(gpu_lib, c, p, n) for c, p, n in zip(cases, phis, steps)]
-    for wgs in (1, 2, 7):
-        b = gpu_lib.Batch(cases, phis)
-        b.set_shape(16, wgs)
-        b.run(steps)
-        for k in range(len(cases)):
-            assert np.array_equal(b.instance(k).phi(), ref[k]), (wgs, k)
-        b.close()

@@ -30,5 +30,6 @@ def test_bench_prints_one_json_line_with_the_contract_keys():
     roof = d["roofline"]
     for key in ("bound", "achieved", "peak", "unit", "frac", "traffic"):
         assert key in roof, key
-    assert roof["bound"] in ("hbm", "alu") and 0 < roof["frac"] < 1
+    assert roof["bound"] in ("hbm", "alu") and roof["frac"] > 0
+    assert roof["steps_per_launch"] == 3 and roof["launches_timed"] == 2
     assert d["config"]["launch"] == [224, 16, 4]
