@@ -112,25 +112,44 @@ bool build_items(const std::vector<Geometry>& geo, int strip_h, std::vector<Item
     return true;
 }
 
-// Pass-major slot tables of a launch: items ordered by decreasing passes
-// (stable), cum[p] = first slot of pass p, cum[npass] = slot count.
-void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, std::vector<int32_t>& order,
-                 std::vector<int64_t>& cum) {
-    const int n = (int)items.size();
-    order.resize(n);
-    std::iota(order.begin(), order.end(), 0);
-    std::stable_sort(order.begin(), order.end(),
-                     [&](int a, int b) { return passes[items[a].inst] > passes[items[b].inst]; });
-    int64_t npass = 0;
-    for (int64_t p : passes) npass = std::max(npass, p);
-    cum.assign(npass + 1, 0);
-    // items with pass p: those whose instance has more than p passes
-    std::vector<int64_t> cnt(npass + 1, 0);
-    for (const ItemH& it : items) cnt[passes[it.inst]] += 1;  // count per exact pass count
-    int64_t with_more = n;  // items whose instance has > p passes, for p = 0
-    for (int64_t p = 0; p < npass; ++p) {
-        with_more -= cnt[p];  // drop the items with exactly p passes
-        cum[p + 1] = cum[p] + with_more;
+// Slot tables of a launch (see BatchSlots): the entries (instance, pass) in
+// the order of the fraction of its run the instance has done after the pass,
+// (p + 1) / passes[k], ties by instance (a merge of the instances' pass
+// sequences; the fractions are compared exactly in integers), the first slot
+// of each entry, and the first item of each instance.
+struct Slots {
+    std::vector<int32_t> entry;       // 2 per entry: instance, pass
+    std::vector<int64_t> start;       // entries + 1
+    std::vector<int32_t> first_item;  // instances + 1
+};
+
+void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, Slots& sl) {
+    const int count = (int)passes.size();
+    sl.first_item.assign(count + 1, 0);
+    for (const ItemH& it : items) sl.first_item[it.inst + 1] += 1;
+    for (int k = 0; k < count; ++k) sl.first_item[k + 1] += sl.first_item[k];
+    // merge: the next pass of instance k is due at fraction (next[k] + 1) / passes[k]
+    std::vector<int64_t> next(count, 0);
+    auto later = [&](int a, int b) {  // heap order: the smallest fraction on top
+        const __int128 fa = (__int128)(next[a] + 1) * passes[b], fb = (__int128)(next[b] + 1) * passes[a];
+        return fa != fb ? fa > fb : a > b;
+    };
+    std::vector<int> heap;
+    for (int k = 0; k < count; ++k)
+        if (passes[k] > 0 && sl.first_item[k + 1] > sl.first_item[k]) heap.push_back(k);
+    std::make_heap(heap.begin(), heap.end(), later);
+    sl.entry.clear();
+    sl.start.assign(1, 0);
+    while (!heap.empty()) {
+        std::pop_heap(heap.begin(), heap.end(), later);
+        const int k = heap.back();
+        sl.entry.push_back(k);
+        sl.entry.push_back((int32_t)next[k]);
+        sl.start.push_back(sl.start.back() + (sl.first_item[k + 1] - sl.first_item[k]));
+        if (++next[k] < passes[k])
+            std::push_heap(heap.begin(), heap.end(), later);
+        else
+            heap.pop_back();
     }
 }
 
@@ -154,16 +173,17 @@ struct lbac_batch {
     int64_t nslots[2] = {0, 0};  // slots (workgroups) of the two launches of the current run
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
-    int32_t* d_order[2] = {nullptr, nullptr};
-    int64_t* d_cum[2] = {nullptr, nullptr};
+    int32_t* d_entry[2] = {nullptr, nullptr};
+    int64_t* d_start[2] = {nullptr, nullptr};
+    int32_t* d_first = nullptr;   // first item of each instance
     int32_t* d_done = nullptr;
     BatchCtl* d_ctl = nullptr;
     BatchCtl* h_ctl = nullptr;    // pinned
     BatchInst* h_inst = nullptr;  // pinned
-    int32_t* d_npass = nullptr;   // passes of the two launches (read by the kernels)
-    int32_t* h_npass = nullptr;   // pinned
+    int32_t* d_nent = nullptr;    // entries of the two launches (read by the kernels)
+    int32_t* h_nent = nullptr;    // pinned
     int cap_items = 0;
-    int64_t cap_cum[2] = {0, 0};
+    int64_t cap_ent[2] = {0, 0};
     hipGraphExec_t gexec = nullptr;
     int64_t g_slots[2] = {-1, -1};  // grids the captured graph was made for
     std::string err;
@@ -196,11 +216,11 @@ void free_tables(lbac_batch* b) {
     b->d_done = nullptr;
     b->cap_items = 0;
     for (int L = 0; L < 2; ++L) {
-        (void)hipFree(b->d_order[L]);
-        (void)hipFree(b->d_cum[L]);
-        b->d_order[L] = nullptr;
-        b->d_cum[L] = nullptr;
-        b->cap_cum[L] = 0;
+        (void)hipFree(b->d_entry[L]);
+        (void)hipFree(b->d_start[L]);
+        b->d_entry[L] = nullptr;
+        b->d_start[L] = nullptr;
+        b->cap_ent[L] = 0;
     }
 }
 
@@ -209,10 +229,11 @@ void release(lbac_batch* b) {
     free_tables(b);
     (void)hipFree(b->d_inst);
     (void)hipFree(b->d_ctl);
-    (void)hipFree(b->d_npass);
+    (void)hipFree(b->d_nent);
+    (void)hipFree(b->d_first);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
-    if (b->h_npass) (void)hipHostFree(b->h_npass);
+    if (b->h_nent) (void)hipHostFree(b->h_nent);
     for (lbac_ctx* c : b->inst) {
         if (c) {
             c->in_batch = false;
@@ -223,9 +244,10 @@ void release(lbac_batch* b) {
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// Device tables large enough for the items and for npass + 1 slot starts per
-// launch; a reallocation invalidates the captured graph (its kernel arguments).
-int ensure_tables(lbac_batch* b, const int64_t npass[2]) {
+// Device tables large enough for the items and for the entries of each
+// launch; a reallocation invalidates the captured graph (its kernel
+// arguments).
+int ensure_tables(lbac_batch* b, const int64_t nent[2]) {
     if (b->cap_items < b->nitems) {
         drop_graph(b);
         (void)hipFree(b->d_items);
@@ -233,25 +255,23 @@ int ensure_tables(lbac_batch* b, const int64_t npass[2]) {
         b->d_items = nullptr;
         b->d_done = nullptr;
         b->cap_items = 0;
-        for (int L = 0; L < 2; ++L) {
-            (void)hipFree(b->d_order[L]);
-            b->d_order[L] = nullptr;
-        }
         const int ci = std::max(b->nitems, 1);
         BHIP(b, hipMalloc(&b->d_items, sizeof(BatchItem) * ci));
         BHIP(b, hipMalloc(&b->d_done, sizeof(int32_t) * ci));
-        for (int L = 0; L < 2; ++L) BHIP(b, hipMalloc(&b->d_order[L], sizeof(int32_t) * ci));
         b->cap_items = ci;
     }
     for (int L = 0; L < 2; ++L)
-        if (b->cap_cum[L] < npass[L] + 1) {
+        if (b->cap_ent[L] < nent[L] + 1) {
             drop_graph(b);
-            (void)hipFree(b->d_cum[L]);
-            b->d_cum[L] = nullptr;
-            b->cap_cum[L] = 0;
-            const int64_t cc = std::max<int64_t>(npass[L] + 1, 64);
-            BHIP(b, hipMalloc(&b->d_cum[L], sizeof(int64_t) * cc));
-            b->cap_cum[L] = cc;
+            (void)hipFree(b->d_entry[L]);
+            (void)hipFree(b->d_start[L]);
+            b->d_entry[L] = nullptr;
+            b->d_start[L] = nullptr;
+            b->cap_ent[L] = 0;
+            const int64_t c = std::max<int64_t>(nent[L] + 1, 64);
+            BHIP(b, hipMalloc(&b->d_entry[L], 2 * sizeof(int32_t) * c));
+            BHIP(b, hipMalloc(&b->d_start[L], sizeof(int64_t) * c));
+            b->cap_ent[L] = c;
         }
     return LBAC_OK;
 }
@@ -274,7 +294,7 @@ int capture(lbac_batch* b) {
     auto launch_slots = [&](int L) {
         for (int64_t left = b->nslots[L]; left > 0 && e == hipSuccess;) {
             const int64_t g = std::min<int64_t>(left, kBatchMaxGrid);
-            const BatchSlots sl{b->d_order[L], b->d_cum[L], b->d_npass + L};
+            const BatchSlots sl{b->d_entry[L], b->d_start[L], b->d_first, b->d_nent + L};
             if (L == 0)
                 hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
                                    b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
@@ -332,24 +352,22 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
         b->items_h = b->strip_h;
     }
     std::vector<int64_t> pf(count), pr(count);
-    int64_t npass[2] = {0, 0};
     for (int k = 0; k < count; ++k) {
         pf[k] = nsteps[k] / kBatchS;
         pr[k] = nsteps[k] % kBatchS;
-        npass[0] = std::max(npass[0], pf[k]);
-        npass[1] = std::max(npass[1], pr[k]);
     }
-    if (npass[0] > INT32_MAX) return bfail(b, LBAC_EINVAL, "too many passes");
-    int rc = ensure_tables(b, npass);
-    if (rc != LBAC_OK) return rc;
-    std::vector<int32_t> order[2];
-    std::vector<int64_t> cum[2];
-    build_slots(b->items, pf, order[0], cum[0]);
-    build_slots(b->items, pr, order[1], cum[1]);
+    Slots sl[2];
+    build_slots(b->items, pf, sl[0]);
+    build_slots(b->items, pr, sl[1]);
+    int64_t nent[2];
     for (int L = 0; L < 2; ++L) {
-        b->nslots[L] = cum[L].back();
-        if (b->nslots[L] > 64 * kBatchMaxGrid) return bfail(b, LBAC_EINVAL, "too many slots");
+        nent[L] = (int64_t)sl[L].entry.size() / 2;
+        b->nslots[L] = sl[L].start.back();
+        if (nent[L] > INT32_MAX || b->nslots[L] > 64 * kBatchMaxGrid)
+            return bfail(b, LBAC_EINVAL, "too many slots");
     }
+    int rc = ensure_tables(b, nent);
+    if (rc != LBAC_OK) return rc;
     std::vector<BatchItem> di(b->nitems);
     for (int i = 0; i < b->nitems; ++i) {
         const ItemH& it = b->items[i];
@@ -377,17 +395,20 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
     b->h_ctl->dry = dry ? 1 : 0;
     b->h_ctl->err = 0;
     b->h_ctl->test_stall = b->test_stall;
-    b->h_npass[0] = (int32_t)npass[0];
-    b->h_npass[1] = (int32_t)npass[1];
+    b->h_nent[0] = (int32_t)nent[0];
+    b->h_nent[1] = (int32_t)nent[1];
     BHIP(b, hipMemcpyAsync(b->d_inst, b->h_inst, sizeof(BatchInst) * 2 * count, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
-    BHIP(b, hipMemcpyAsync(b->d_npass, b->h_npass, 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_nent, b->h_nent, 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
+    BHIP(b, hipMemcpyAsync(b->d_first, sl[0].first_item.data(), sizeof(int32_t) * (count + 1), hipMemcpyHostToDevice,
+                           b->stream));
     BHIP(b, hipMemcpyAsync(b->d_items, di.data(), sizeof(BatchItem) * b->nitems, hipMemcpyHostToDevice, b->stream));
     for (int L = 0; L < 2; ++L) {
-        BHIP(b, hipMemcpyAsync(b->d_order[L], order[L].data(), sizeof(int32_t) * b->nitems, hipMemcpyHostToDevice,
-                               b->stream));
-        BHIP(b, hipMemcpyAsync(b->d_cum[L], cum[L].data(), sizeof(int64_t) * cum[L].size(), hipMemcpyHostToDevice,
-                               b->stream));
+        if (nent[L] > 0)
+            BHIP(b, hipMemcpyAsync(b->d_entry[L], sl[L].entry.data(), sizeof(int32_t) * sl[L].entry.size(),
+                                   hipMemcpyHostToDevice, b->stream));
+        BHIP(b, hipMemcpyAsync(b->d_start[L], sl[L].start.data(), sizeof(int64_t) * sl[L].start.size(),
+                               hipMemcpyHostToDevice, b->stream));
     }
     rc = capture(b);
     if (rc != LBAC_OK) return rc;
@@ -467,9 +488,10 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         b->ticks_per_s = 1000.0 * khz;
     b->max_wgs = std::max(1, per_cu * cus);
     if (hipMalloc(&b->d_inst, sizeof(BatchInst) * 2 * count) != hipSuccess ||
-        hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess || hipMalloc(&b->d_npass, 64) != hipSuccess ||
+        hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess || hipMalloc(&b->d_nent, 64) != hipSuccess ||
+        hipMalloc(&b->d_first, sizeof(int32_t) * (count + 1)) != hipSuccess ||
         hipHostMalloc((void**)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void**)&b->h_npass, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_nent, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_inst, sizeof(BatchInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
         return bail(LBAC_ENOMEM);
     std::memset(b->h_ctl, 0, sizeof(BatchCtl));
@@ -585,12 +607,13 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
     };
     for (int L = 0; L < 2 && *verdict == 0; ++L) {
         const std::vector<int64_t>& passes = L == 0 ? pf : pr;
-        std::vector<int32_t> order;
-        std::vector<int64_t> cum;
-        build_slots(items, passes, order, cum);
-        const int32_t npass = (int32_t)(cum.size() - 1);
-        const int64_t total = cum[npass];
-        const BatchSlots tab{order.data(), cum.data(), &npass};
+        Slots sl;
+        build_slots(items, passes, sl);
+        const int32_t nent = (int32_t)(sl.entry.size() / 2);
+        const int64_t total = sl.start.back();
+        const BatchSlots tab{sl.entry.data(), sl.start.data(), sl.first_item.data(), &nent};
+        int32_t npass = 0;
+        for (int64_t v : passes) npass = std::max<int32_t>(npass, (int32_t)v);
         // protocol 2: fixed item lists of 2 * workers workgroups (items dealt
         // longest-first to the least loaded list, each list walked pass by
         // pass), of which `workers` run at once; a list's workgroup starts
@@ -598,6 +621,10 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
         const int lists = 2 * workers;
         std::vector<std::vector<int32_t>> list(lists);
         if (protocol == 2) {
+            std::vector<int32_t> order(n);
+            std::iota(order.begin(), order.end(), 0);
+            std::stable_sort(order.begin(), order.end(),
+                             [&](int a, int b) { return passes[items[a].inst] > passes[items[b].inst]; });
             std::vector<double> load(lists, 0.0);
             for (int32_t id : order) {
                 const int m = (int)(std::min_element(load.begin(), load.end()) - load.begin());
@@ -670,7 +697,7 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
                 if (protocol == 2) {
                     if (!static_next(w, s)) continue;
                 } else {
-                    s.id = batch_slot_item(tab, next++, npass, s.p);
+                    s.id = batch_slot_item(tab, next++, nent, s.p);
                 }
                 s.gp = (L == 0 ? 0 : pf[items[s.id].inst]) + s.p;
                 s.started = false;

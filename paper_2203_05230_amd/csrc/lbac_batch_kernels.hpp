@@ -18,9 +18,11 @@
 // tile grown by kBatchGrow nodes (its own rows and the rows of the items
 // around it) and writes its own tile once.
 //
-// Schedule.  The (pass, item) slots of a launch are numbered pass-major (every
-// slot of pass p before any slot of pass p + 1) and each workgroup of the
-// launch takes one slot number from a single atomic counter when it starts.
+// Schedule.  The (pass, item) slots of a launch are numbered so that every
+// slot of pass p of an instance comes before any slot of its pass p + 1 (the
+// passes of all instances interleaved in proportion to their lengths, see
+// BatchSlots) and each workgroup of the launch takes one slot number from a
+// single atomic counter when it starts.
 // Before slot (p, I) runs it waits until I and the items whose tiles overlap
 // I's read region have published pass p - 1: they wrote the rows I reads, and
 // (the relation is symmetric) they have finished reading the part of the
@@ -83,32 +85,40 @@ __device__ __forceinline__ bool batch_wait(const int32_t* done, const int32_t* d
         }
         __builtin_amdgcn_s_sleep(1);
     }
-    // make the neighbours' rows visible to this wavefront's loads
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    // the rows this slot reads are loaded after the counters were seen (the
+    // loop consumed them); the tile function reads them with device-scope
+    // loads (IoCoherent), so no cache needs invalidating.  A compiler barrier
+    // keeps the loads below this point.
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
     return true;
 }
 
-// Slot tables of a launch: order[] lists the items by decreasing number of
-// passes (so the items that have pass p are the first cum[p + 1] - cum[p]
-// entries), cum[p] is the number of the first slot of pass p, cum[npass] the
-// slot count.
+// Slot tables of a launch.  A pass of an instance is an entry (instance, p)
+// with the slots of all the instance's items; entries are ordered by the
+// fraction of its run the instance has done after the pass, (p + 1) / passes
+// (ties by instance), so every instance advances in proportion to its length
+// and all finish together, while every pass still comes after the previous
+// pass of its instance (the order stays a topological order of the
+// dependencies).  start[e] is the first slot number of entry e, start[n] the
+// slot count; the items of an instance are the contiguous ids first_item[k] ..
+// first_item[k + 1] - 1.
 struct BatchSlots {
-    const int32_t* order;
-    const int64_t* cum;
-    const int32_t* npass;  // passes of the launch (device memory: a captured graph's arguments stay valid)
+    const int32_t* entry;       // 2 per entry: instance, pass
+    const int64_t* start;       // n + 1 values
+    const int32_t* first_item;  // count + 1 values
+    const int32_t* nentries;    // n (device memory: a captured graph's arguments stay valid)
 };
 
-// Maps slot number T of a launch to its pass p (binary search of the slot
-// starts; cum has npass + 1 entries) and item.
-__host__ __device__ inline int32_t batch_slot_item(const BatchSlots& s, int64_t T, int32_t npass, int32_t& p) {
-    int32_t lo = 0, hi = npass;
+// Maps slot number T of a launch (T < start[n]) to its pass p and item.
+__host__ __device__ inline int32_t batch_slot_item(const BatchSlots& s, int64_t T, int32_t n, int32_t& p) {
+    int32_t lo = 0, hi = n;  // start[lo] <= T < start[hi]
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) / 2;
-        if (s.cum[mid] <= T) lo = mid;
+        if (s.start[mid] <= T) lo = mid;
         else hi = mid;
     }
-    p = lo;
-    return s.order[T - s.cum[lo]];
+    p = s.entry[2 * lo + 1];
+    return s.first_item[s.entry[2 * lo]] + (int32_t)(T - s.start[lo]);
 }
 
 // One workgroup per slot: a workgroup takes the next slot number from the
@@ -129,8 +139,8 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3
     constexpr int L = S == 1 ? 1 : 0;
     __shared__ TileSLds<kBatchTile, S> lds;
     __shared__ int64_t slot;
-    const int32_t npass = *slots.npass;
-    const int64_t total = slots.cum[npass];
+    const int32_t nent = *slots.nentries;
+    const int64_t total = slots.start[nent];
     if (threadIdx.x == 0) {
         const bool stop = __hip_atomic_load(&ctl->err, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) != 0;
         slot = stop ? total : (int64_t)atomicAdd((unsigned long long*)&ctl->ticket[L], 1ull);
@@ -142,7 +152,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3
                                 (uint32_t)__builtin_amdgcn_readfirstlane((int)slot));
     if (T >= total) return;
     int32_t p;
-    const int32_t id = batch_slot_item(slots, T, npass, p);
+    const int32_t id = batch_slot_item(slots, T, nent, p);
     const BatchItem& item = items[id];
     if (p > 0) {
         const bool ok = batch_wait(done, item.dep, p - 1, ctl);
@@ -153,9 +163,13 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3
     const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
     const StepArgs& a = insts[2 * item.inst + (int)(gp & 1)].a;
     const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : (int64_t)p * kBatchS));
-    stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0, lds);
-    // publish: every wavefront's stores are visible before the counter moves
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN, true>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0,
+                                                         lds);
+    // publish: every wavefront waits until its device-scope stores have
+    // completed (vmcnt counts stores on this architecture), then the counter
+    // moves; no writeback of the whole L2 is needed
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
     __syncthreads();
     if (threadIdx.x == 0) __hip_atomic_store(done + id, p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }

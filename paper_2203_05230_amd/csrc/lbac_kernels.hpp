@@ -473,6 +473,42 @@ struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
     using IoShifted<__hip_bfloat16>::IoShifted;
 };
 
+// FP32 plain storage read and written with device-scope accesses (the
+// cache-policy bit sc1, with which the compiler implements relaxed atomic
+// loads and stores at agent scope): each access is coherent across the
+// XCDs' L2 caches by itself.  The batched form, whose workgroups hand tiles
+// to each other through per-item progress counters, uses it so that a
+// producer only waits for its own stores to complete before it publishes,
+// and a consumer that has seen the counter reads current values, with no
+// writeback or invalidation of the whole L2.
+struct IoCoherent {
+    static constexpr bool kShifted = false;
+    static constexpr int kSc1 = 16;  // cache-policy operand: sc1 (device scope)
+    const char* s[9];
+    char* d[9];
+    __device__ __forceinline__ IoCoherent(const StepArgs& a, bool mirror) {
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+            const int m = mirror ? mirror_q(q) : q;
+            s[q] = static_cast<const char*>(a.src) + (size_t)m * a.plane_stride * sizeof(float);
+            d[q] = static_cast<char*>(a.dst) + (size_t)m * a.plane_stride * sizeof(float);
+        }
+    }
+    __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
+        const uint32_t b = off * 4u;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            v[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
+                                                 plane_rsrc(const_cast<char*>(s[q])), (int)b, 0, kSc1));
+    }
+    __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float /*phi*/) const {
+        const uint32_t b = on ? off * 4u : kDropOffset;
+#pragma unroll
+        for (int q = 0; q < 9; ++q)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), plane_rsrc(d[q]), (int)b, 0, kSc1);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // The step on one tile, block-wide variant.
 //
@@ -730,9 +766,12 @@ __host__ __device__ constexpr int stepS_threads() {
     return (BX + 4 * S + 63) / 64 * 64;
 }
 
-template <int MODEL, int BX, int S, int ST>
+// COH: FP32 plain storage through IoCoherent (the batched form).
+template <int MODEL, int BX, int S, int ST, bool COH = false>
 __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w, int ys, int hh, int64_t t,
                                                bool down, TileSLds<BX, S>& lds) {
+    static_assert(!COH || ST == ST_PLAIN, "coherent access is for FP32 plain storage");
+    using IoT = typename std::conditional<COH, IoCoherent, Io<float, ST>>::type;
     // Thread layout.  The C = 64 * c columns of the tile that whole wavefronts
     // own go to wavefronts 0 .. c - 1, one aligned 64-column segment each (so
     // every wavefront loads and stores whole 256-byte lines); wavefront c, the
@@ -770,7 +809,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
     // direction.  Every node helper rounds mirror-symmetrically (sums in
     // mirror-invariant order, y components that only change sign), so the
     // results equal the lattice-frame computation bit for bit.
-    const Io<float, ST> io(a, down);
+    const IoT io(a, down);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
     const int iters = hh + 5 * S - 1;
@@ -803,7 +842,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
     // shifted storage: the own column's populations 7 and 8 of stage 0's last
     // two input rows (the rings keep them only where another column pulls them)
     float o7[2] = {0.f, 0.f}, o8[2] = {0.f, 0.f};
-    constexpr bool kSh = Io<float, ST>::kShifted;
+    constexpr bool kSh = IoT::kShifted;
 #pragma unroll
     for (int k = 0; k < S; ++k) {
 #pragma unroll
