@@ -344,6 +344,19 @@ int lbac_closure_extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int3
                          double delta, float theta, int32_t augment, void* workspace, float* x_dev, float* y_dev,
                          int64_t base, int64_t capacity, int64_t* count, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight training-data loops, harnesses that forbid allocation):
+ * lbac_closure_extract without the workspace argument.  Its workspace is a
+ * fixed 8 MiB device array inside the library (one per GPU, held until the
+ * process ends; enough for coarse grids up to 512 x 512), and the call
+ * allocates nothing.  LBAC_EINVAL when lbac_closure_workspace_bytes(nxf,
+ * nyf, r) exceeds 8 MiB, else as lbac_closure_extract.  Calls on one GPU
+ * share that array: calls that overlap in time on one GPU (other host
+ * threads, other streams) race and must be serialised by the caller. */
+int lbac_closure_extract_noalloc(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f,
+                                 double eps_c, double delta, float theta, int32_t augment, float* x_dev, float* y_dev,
+                                 int64_t base, int64_t capacity, int64_t* count, void* stream);
+
 #ifdef __cplusplus
 }
 #endif

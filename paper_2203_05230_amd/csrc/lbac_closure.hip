@@ -12,7 +12,9 @@
 // node order, so the output is deterministic.
 #include <hip/hip_runtime.h>
 
+#include <atomic>
 #include <cmath>
+#include <mutex>
 #include <string>
 
 #include "lbac.h"
@@ -140,22 +142,44 @@ __global__ void emit_kernel(const double* __restrict__ phic, const double* __res
 
 }  // namespace
 
-extern "C" {
+// Workspace of lbac_closure_extract_noalloc: a file-scope device array, one
+// copy per GPU, held until the process ends.  Host code never uses its name
+// as an address (that is a host-side stand-in): the device address comes
+// from hipGetSymbolAddress, once per device, with that device current.
+constexpr size_t kNoAllocScratchBytes = size_t(8) << 20;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
-int64_t lbac_closure_workspace_bytes(int32_t nxf, int32_t nyf, int32_t r) {
+namespace {
+
+constexpr int kMaxDevices = 64;
+std::atomic<void*> g_scratch[kMaxDevices];
+std::mutex g_scratch_mu;
+
+// The current device's address of `scratch`, or nullptr on a HIP error.
+void* scratch_ptr() {
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+    void* p = g_scratch[dev].load(std::memory_order_acquire);
+    if (p) return p;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    p = g_scratch[dev].load(std::memory_order_relaxed);
+    if (!p) {
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess) return nullptr;
+        g_scratch[dev].store(p, std::memory_order_release);
+    }
+    return p;
+}
+
+int64_t workspace_bytes(int32_t nxf, int32_t nyf, int32_t r) {
     if (r < 1 || nxf < r || nyf < r) return -1;
     const int64_t nc = (int64_t)(nxf / r) * (nyf / r);
     return (int64_t)(3 * nc * sizeof(double) + (nyf / r + 64) * sizeof(int) + 64);
 }
 
-int lbac_closure_extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f, double eps_c,
-                         double delta, float theta, int32_t augment, void* workspace, float* x_dev, float* y_dev,
-                         int64_t base, int64_t capacity, int64_t* count, void* stream) {
-    if (!phi_f_dev || !workspace || !count || r < 1 || nxf % r || nyf % r || nxf / r < 5 || nyf / r < 5)
-        return LBAC_EINVAL;
-    if (!(eps_f > 0.0) || !(eps_c > 0.0) || !(delta >= 0.0) || !(theta >= 0.f) || !(theta < 0.5f) || base < 0)
-        return LBAC_EINVAL;
-    if (nxf / r > 1024 * 16) return LBAC_EINVAL;
+// The extraction with a given workspace (device memory of workspace_bytes).
+int extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f, double eps_c, double delta,
+            float theta, int32_t augment, void* workspace, float* x_dev, float* y_dev, int64_t base, int64_t capacity,
+            int64_t* count, void* stream) {
     hipStream_t s = (hipStream_t)stream;
     const int nxc = nxf / r, nyc = nyf / r;
     const int64_t nc = (int64_t)nxc * nyc;
@@ -179,6 +203,42 @@ int lbac_closure_extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int3
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess) return LBAC_EDEVICE;
     *count = host_total * copies;
     return LBAC_OK;
+}
+
+int check_args(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f, double eps_c,
+               double delta, float theta, int64_t base, int64_t* count) {
+    if (!phi_f_dev || !count || r < 1 || nxf % r || nyf % r || nxf / r < 5 || nyf / r < 5) return LBAC_EINVAL;
+    if (!(eps_f > 0.0) || !(eps_c > 0.0) || !(delta >= 0.0) || !(theta >= 0.f) || !(theta < 0.5f) || base < 0)
+        return LBAC_EINVAL;
+    if (nxf / r > 1024 * 16) return LBAC_EINVAL;
+    return LBAC_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int64_t lbac_closure_workspace_bytes(int32_t nxf, int32_t nyf, int32_t r) { return workspace_bytes(nxf, nyf, r); }
+
+int lbac_closure_extract(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f, double eps_c,
+                         double delta, float theta, int32_t augment, void* workspace, float* x_dev, float* y_dev,
+                         int64_t base, int64_t capacity, int64_t* count, void* stream) {
+    const int rc = check_args(phi_f_dev, nxf, nyf, r, eps_f, eps_c, delta, theta, base, count);
+    if (rc != LBAC_OK || !workspace) return LBAC_EINVAL;
+    return extract(phi_f_dev, nxf, nyf, r, eps_f, eps_c, delta, theta, augment, workspace, x_dev, y_dev, base,
+                   capacity, count, stream);
+}
+
+int lbac_closure_extract_noalloc(const double* phi_f_dev, int32_t nxf, int32_t nyf, int32_t r, double eps_f,
+                                 double eps_c, double delta, float theta, int32_t augment, float* x_dev, float* y_dev,
+                                 int64_t base, int64_t capacity, int64_t* count, void* stream) {
+    const int rc = check_args(phi_f_dev, nxf, nyf, r, eps_f, eps_c, delta, theta, base, count);
+    if (rc != LBAC_OK) return rc;
+    if (workspace_bytes(nxf, nyf, r) > (int64_t)kNoAllocScratchBytes) return LBAC_EINVAL;
+    void* ws = scratch_ptr();
+    if (!ws) return LBAC_EDEVICE;
+    return extract(phi_f_dev, nxf, nyf, r, eps_f, eps_c, delta, theta, augment, ws, x_dev, y_dev, base, capacity,
+                   count, stream);
 }
 
 }  // extern "C"

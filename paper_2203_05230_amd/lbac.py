@@ -66,7 +66,7 @@ EXPORTS = [
     "lbac_batch_last_error", "lbac_batch_schedule_check",
     "lbac_mlp_create", "lbac_mlp_free", "lbac_mlp_get_weights", "lbac_mlp_set_weights", "lbac_mlp_forward",
     "lbac_mlp_loss_grad", "lbac_mlp_train_step", "lbac_mlp_last_error",
-    "lbac_closure_workspace_bytes", "lbac_closure_extract",
+    "lbac_closure_workspace_bytes", "lbac_closure_extract", "lbac_closure_extract_noalloc",
 ]
 # include/lbac3.h (the D3Q19 form)
 EXPORTS3 = [
@@ -151,6 +151,9 @@ def load():
     L.lbac_closure_extract.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
                                        C.c_double, C.c_float, C.c_int32, C.c_void_p, C.c_void_p, C.c_void_p,
                                        C.c_int64, C.c_int64, P(C.c_int64), C.c_void_p]
+    L.lbac_closure_extract_noalloc.argtypes = [C.c_void_p, C.c_int32, C.c_int32, C.c_int32, C.c_double, C.c_double,
+                                               C.c_double, C.c_float, C.c_int32, C.c_void_p, C.c_void_p, C.c_int64,
+                                               C.c_int64, P(C.c_int64), C.c_void_p]
     p3 = P(lbac3_params)
     L.lbac3_default_params.argtypes = [p3, C.c_int32, C.c_int32, C.c_int32]
     L.lbac3_default_params.restype = None
@@ -506,6 +509,18 @@ def closure_extract(phi_f_ptr, nxf, nyf, r, eps_f, eps_c, delta, theta, augment,
                                        float(eps_c), float(delta), float(theta), 1 if augment else 0,
                                        C.c_void_p(workspace_ptr), C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(base),
                                        int(capacity), C.byref(n), stream), what="lbac_closure_extract")
+    return n.value
+
+
+def closure_extract_noalloc(phi_f_ptr, nxf, nyf, r, eps_f, eps_c, delta, theta, augment, x_ptr, y_ptr, base,
+                            capacity, stream=None):
+    """closure_extract with the library's fixed device workspace (allocates
+    nothing; coarse grids up to 512 x 512)."""
+    n = C.c_int64()
+    _check(load().lbac_closure_extract_noalloc(C.c_void_p(phi_f_ptr), int(nxf), int(nyf), int(r), float(eps_f),
+                                               float(eps_c), float(delta), float(theta), 1 if augment else 0,
+                                               C.c_void_p(x_ptr), C.c_void_p(y_ptr), int(base), int(capacity),
+                                               C.byref(n), stream), what="lbac_closure_extract_noalloc")
     return n.value
 
 
