@@ -65,11 +65,22 @@ typedef struct {
     double theta;      /* closure band: applied where theta < phi_clip < 1 - theta */
     int32_t mutation;  /* 0 in every real use; nonzero plants one known mistake
                           (MUT_*) so tests can show that the pins catch it */
-    double noise;      /* 0 in every real use; > 0 multiplies every post-collision
-                          population by (1 + noise xi), xi uniform in [-1, 1), to
-                          measure how the iteration amplifies rounding-sized errors */
+    double noise;      /* 0 in every real use; > 0 perturbs the post-collision
+                          populations (noise_kind) by relative errors noise xi,
+                          xi uniform in [-1, 1), to measure how the iteration
+                          amplifies rounding-sized errors */
     uint64_t noise_seed;
+    int32_t noise_kind;  /* NOISE_POPULATIONS: every f*_i times (1 + noise xi).
+                            NOISE_SHIFTED: the shifted populations g_i = f*_i - w_i phi*
+                            (i >= 1, phi* = sum_i f*_i at the node) times (1 + noise xi)
+                            and f*_0 the remainder, so the node's sum is kept: the
+                            error pattern of storing g_i in a format of unit
+                            roundoff `noise` */
+    int32_t noise_every; /* perturb after the steps s with (s + 1) % noise_every == 0
+                            and after the last step (<= 1: after every step) */
 } orc_params;
+
+enum { NOISE_POPULATIONS = 0, NOISE_SHIFTED = 1 };
 
 /* splitmix64 (Steele, Lea, Flood 2014): counter-based stream for the noise option */
 static uint64_t splitmix64(uint64_t z) {
@@ -395,7 +406,7 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
                     gx += (1.0 - CS2) * ccx[k];
                     gy += (1.0 - CS2) * ccy[k];
                 }
-                double fe[9], F[9];
+                double fe[9], F[9], post[9];
                 orc_feq(phi[k], p->mutation == MUT_FEQ_NO_U ? 0.0 : u, p->mutation == MUT_FEQ_NO_U ? 0.0 : v, fe);
                 orc_forcing(gx, gy, F);
                 if (p->mutation == MUT_DIAG_WEIGHT)
@@ -403,14 +414,31 @@ static int run_core(const orc_params* p, int ox, int oy, int lnx, int lny, const
                         fe[q] *= 2.0;
                         F[q] *= 2.0;
                     }
+                /* Eq. (9): collision */
                 for (int q = 0; q < 9; ++q) {
                     double fi = f[q * n + k];
-                    /* Eq. (9): collision, then push to x + c_q */
-                    double post = fi - (fi - fe[q]) / tau + kf * F[q];
-                    if (p->noise > 0.0)
-                        post *= 1.0 + p->noise * unit_noise(p->noise_seed, ((uint64_t)step * n + k) * 9u + (uint64_t)q);
+                    post[q] = fi - (fi - fe[q]) / tau + kf * F[q];
+                }
+                if (p->noise > 0.0 && (p->noise_every <= 1 || (step + 1) % p->noise_every == 0 || step + 1 == nsteps)) {
+                    uint64_t ctr = ((uint64_t)step * n + k) * 9u;
+                    if (p->noise_kind == NOISE_SHIFTED) {
+                        double ps = 0.0, moving = 0.0;
+                        for (int q = 0; q < 9; ++q) ps += post[q];
+                        for (int q = 1; q < 9; ++q) {
+                            double g = post[q] - W[q] * ps;
+                            post[q] = W[q] * ps + g * (1.0 + p->noise * unit_noise(p->noise_seed, ctr + (uint64_t)q));
+                            moving += post[q];
+                        }
+                        post[0] = ps - moving;
+                    } else {
+                        for (int q = 0; q < 9; ++q)
+                            post[q] *= 1.0 + p->noise * unit_noise(p->noise_seed, ctr + (uint64_t)q);
+                    }
+                }
+                /* Eq. (9): push to x + c_q */
+                for (int q = 0; q < 9; ++q) {
                     int ti = wrap(i + sdir * CX[q], lnx), tj = wrap(j + sdir * CY[q], lny);
-                    fn[q * n + (size_t)tj * lnx + ti] = post;
+                    fn[q * n + (size_t)tj * lnx + ti] = post[q];
                 }
                 pux[k] = phu;
                 puy[k] = phv;

@@ -19,6 +19,9 @@ MUTATIONS = {"drop_dt_phiu": 1, "no_force_factor": 2, "flux_sign": 3, "grad_swap
 MUTATIONS_CONVENTIONAL = {"conv_width4": 10, "conv_normal_psi": 11}
 MUTATIONS_CLOSURE = {"closure_no_cs2": 12, "closure_stencil_t": 13}
 READ_JAIN, READ_LITERAL, READ_LIANG = range(3)
+# test-only perturbations (Params.noise): every post-collision population, or
+# the shifted populations g_i = f*_i - w_i phi* with the node's sum kept
+NOISE_POPULATIONS, NOISE_SHIFTED = range(2)
 MODEL_IMPROVED, MODEL_CONVENTIONAL = range(2)
 
 
@@ -34,6 +37,7 @@ class OrcParams(C.Structure):
         ("mlp", C.POINTER(C.c_double)), ("theta", C.c_double),
         ("mutation", C.c_int32),
         ("noise", C.c_double), ("noise_seed", C.c_uint64),
+        ("noise_kind", C.c_int32), ("noise_every", C.c_int32),
     ]
 
 
@@ -88,7 +92,7 @@ class Params:
     def __init__(self, nx, ny, eps=1.0, tau=0.8, delta=1e-10, vel_kind=VEL_VORTEX, U=0.02,
                  period_T=2000.0, omega=0.0, cx=None, cy=None, ux=0.0, uy=0.0,
                  reading=READ_JAIN, model=MODEL_IMPROVED, mlp=None, theta=0.0, mutation=0, noise=0.0,
-                 noise_seed=0):
+                 noise_seed=0, noise_kind=0, noise_every=1):
         self.nx, self.ny = int(nx), int(ny)
         self.eps, self.tau, self.delta = float(eps), float(tau), float(delta)
         self.vel_kind, self.U, self.period_T = int(vel_kind), float(U), float(period_T)
@@ -101,12 +105,13 @@ class Params:
         self.theta = float(theta)
         self.mutation = int(mutation)
         self.noise, self.noise_seed = float(noise), int(noise_seed)
+        self.noise_kind, self.noise_every = int(noise_kind), int(noise_every)
 
     def c(self):
         s = OrcParams(self.nx, self.ny, self.eps, self.tau, self.delta, self.vel_kind, self.U, self.period_T,
                       self.omega, self.cx, self.cy, self.ux, self.uy, self.reading, self.model,
                       None if self.mlp is None else _dp(self.mlp), self.theta, self.mutation, self.noise,
-                      self.noise_seed)
+                      self.noise_seed, self.noise_kind, self.noise_every)
         return s
 
 
