@@ -148,17 +148,21 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
  * in flight while a row is processed; LBAC_KERNEL_BLOCK_DEEP: the same with
  * two rows in flight; LBAC_KERNEL_WAVE: every wavefront owns a 60-column
  * tile held in registers, bx / 64 wavefronts per block;
- * LBAC_KERNEL_FUSED2 and LBAC_KERNEL_FUSED3 (LBAC_F32 storage only): one
- * launch takes S = 2 or 3 steps, the populations between them kept in LDS
- * (the block layout; step k of S is computed on the tile grown by
- * 2 (S - 1 - k) columns and rows on each side), so HBM is read and written
- * once per S steps; their tiles are bx = 64, 96, 128, ..., 320 columns (any
- * multiple of 32 in that range), the block being the bx + 4S grown columns
- * rounded up to whole wavefronts; a step count that is not a multiple of S
- * ends with one-step launches (bx 256 where bx is not 64, 128 or 256), and
- * with the closure on every step is a one-step launch.  strip_h: rows each
- * tile marches (>= 1).  Results do not depend on the shape or variant
- * (bitwise).  LBAC_EINVAL for unsupported values. */
+ * LBAC_KERNEL_FUSED2 and LBAC_KERNEL_FUSED3 (FP32 collision: LBAC_F32 or a
+ * 16-bit storage): one launch takes S = 2 or 3 steps, the populations
+ * between them kept in LDS (the block layout; step k of S is computed on the
+ * tile grown by RC (S - 1 - k) columns and rows on each side, RC = 2, or 3
+ * with the closure, whose network reads a 5x5 neighbourhood), so HBM is read
+ * and written once per S steps; their tiles are bx = 64, 96, 128, ..., 320
+ * columns (any multiple of 32 in that range; with the closure 128, 160, 192
+ * or 224, another width running those launches at 224), the block being the
+ * bx + 2 RC S grown columns rounded up to whole wavefronts; a step count
+ * that is not a multiple of S ends with one-step launches (bx 256 where bx
+ * is not 64, 128 or 256).  With the closure and the conventional model every
+ * step is a one-step launch.  strip_h: rows each tile marches (>= 1).
+ * Results do not depend on the shape or variant (bitwise; the 16-bit
+ * storage forms round once per launch, so there they depend on S only).
+ * LBAC_EINVAL for unsupported values. */
 #define LBAC_KERNEL_BLOCK 0
 #define LBAC_KERNEL_WAVE 1
 #define LBAC_KERNEL_BLOCK_DEEP 2
@@ -182,11 +186,16 @@ int lbac_set_graph_chunk(lbac_ctx* h, int32_t chunk);
  * LBAC_MLP_NPARAM FP32 parameters (host, copied; layout below).  At every
  * node whose clipped phi lies in (theta, 1 - theta) the network, run in BF16
  * with FP32 accumulation (MFMA) on the 5x5 neighbourhood of phi, gives a
- * correction c that is added to the sharpening flux S n of Eq. (11).  Each
- * step then runs the block-variant step kernel (which records the band),
- * a scan that lists the band nodes and a pass that adds the correction's
- * effect on the post-collision populations at those nodes (the collision is
- * linear in G).  Needs device memory for nx * ny list entries.
+ * correction c that is added to the sharpening flux S n of Eq. (11).  The
+ * collision is linear in G, so the correction changes a band node's
+ * post-collision populations by (1 - 1/(2 tau)) w_i (c_i . c).  With
+ * LBAC_KERNEL_FUSED2 / _FUSED3 (improved model) the multi-step kernel
+ * evaluates the network inside each of its steps, on the band nodes of the
+ * rows it updates, from the phi rows it keeps in LDS.  One-step launches run
+ * the block-variant step kernel (which records the band), a scan that lists
+ * the band nodes and a pass that adds the correction at those nodes.  Both
+ * give the same results bit for bit.  Needs device memory for nx * ny list
+ * entries.
  * params == NULL switches the closure off.  LBAC_EINVAL for another
  * precision, a batch instance, theta outside [0, 0.5) or non-finite
  * parameters. */
@@ -195,8 +204,8 @@ int lbac_set_closure(lbac_ctx* h, const float* params, float theta);
 /* HBM bytes per node one launch of the step kernel moves by design: the
  * stored state read and written once.  A launch takes
  * lbac_steps_per_launch steps (2 or 3 with LBAC_KERNEL_FUSED2 or _FUSED3
- * and FP32 storage while the closure is off, else 1), so a step moves this
- * divided by that. */
+ * and FP32 collision, with the closure only for the improved model; else
+ * 1), so a step moves this divided by that. */
 int lbac_bytes_per_node(lbac_ctx* h, double* bytes);
 int lbac_steps_per_launch(lbac_ctx* h, int32_t* steps);
 

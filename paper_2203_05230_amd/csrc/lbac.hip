@@ -263,11 +263,46 @@ hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     }
 }
 
-// Steps one launch takes: S with the S-step variants (FP32 or shifted 16-bit
-// storage, closure off), else 1.
+// Whether the S-step variants can take the run: FP32 collision, and with the
+// closure on FP32 storage and the improved model.
+bool stepS_allowed(const lbac_ctx* h) {
+    if (h->p.precision == LBAC_F64) return false;
+    return !h->closure || h->p.model == LBAC_MODEL_IMPROVED;
+}
+
+// Steps one launch takes: S with the S-step variants, else 1.
 int launch_steps_of(const lbac_ctx* h) {
-    if (h->closure || h->p.precision == LBAC_F64) return 1;
+    if (!stepS_allowed(h)) return 1;
     return h->variant == LBAC_KERNEL_FUSED2 ? 2 : (h->variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
+}
+
+// Tile widths of the S-step kernels with the closure; another width set by
+// lbac_set_launch runs these launches at 224 columns (the results do not
+// depend on the tile width).
+int closure_stepS_bx(int bx) { return bx == 128 || bx == 160 || bx == 192 || bx == 224 ? bx : 224; }
+
+template <int S, int BX>
+hipError_t launch_stepS_cl_shape(StepArgs a, hipStream_t s) {
+    a.nbx = (a.nx + BX - 1) / BX;
+    const dim3 grid(a.nbx * a.nby);
+    hipLaunchKernelGGL((stepS_kernel_cl<BX, S>), grid, dim3(stepS_threads<BX, S, true>()), 0, s, a);
+    return hipGetLastError();
+}
+
+template <int S>
+hipError_t launch_stepS_cl(StepArgs a, int bx, hipStream_t s) {
+    a.nby = (a.ny + a.strip_h - 1) / a.strip_h;
+    a.n_xcd = kXcds;
+    switch (closure_stepS_bx(bx)) {
+    case 128:
+        return launch_stepS_cl_shape<S, 128>(a, s);
+    case 160:
+        return launch_stepS_cl_shape<S, 160>(a, s);
+    case 192:
+        return launch_stepS_cl_shape<S, 192>(a, s);
+    default:
+        return launch_stepS_cl_shape<S, 224>(a, s);
+    }
 }
 
 // One S-step launch with tile width BX.
@@ -318,6 +353,8 @@ hipError_t launch_stepS_st(const lbac_ctx* h, const StepArgs& a, int S) {
 // Steps k .. k + S - 1 of the current run in one launch, from pop[src] into pop[1 - src].
 hipError_t launch_stepS(const lbac_ctx* h, int src, int32_t k, int S) {
     const StepArgs a = make_args(h, src, k);
+    if (h->closure)
+        return S == 3 ? launch_stepS_cl<3>(a, h->bx, h->stream) : launch_stepS_cl<2>(a, h->bx, h->stream);
     switch (h->p.precision) {
     case LBAC_F32_F16STORE:
         return launch_stepS_st<ST_F16>(h, a, S);
@@ -786,12 +823,13 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     int best_bx = keep_bx, best_h = keep_h, best_v = keep_v;
     float best = 1e30f;
     hipError_t e = hipSuccess;
-    const int last_var = h->p.precision != LBAC_F64 && !h->closure ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
+    const int last_var = stepS_allowed(h) ? LBAC_KERNEL_FUSED3 : LBAC_KERNEL_BLOCK_DEEP;
     for (int var = LBAC_KERNEL_BLOCK; var <= last_var && e == hipSuccess; ++var)
     for (int bx : bxs) {
         const int S = var == LBAC_KERNEL_FUSED2 ? 2 : (var == LBAC_KERNEL_FUSED3 ? 3 : 1);
         if (bx > 64 && bx / 2 >= h->p.nx) continue;
         if (S == 1 ? !one_step_bx(bx) : !stepS_bx(bx)) continue;
+        if (S > 1 && h->closure && closure_stepS_bx(bx) != bx) continue;
         for (int sh : hs) {
             h->variant = var;
             h->bx = bx;

@@ -714,6 +714,227 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
     step_tile_lds<R, ST, MODEL, BX, PF>(a, bxi, syi, a.t_dev[0] + a.k, (syi & 1) != 0, lds);
 }
 
+// ---- learned closure: BF16 MFMA inference ------------------------------------
+// The network runs on the 64 samples of a wavefront, 16 at a time (N-tiles),
+// as three chained products Z^T = W H^T with gfx950's 16x16x32 BF16 MFMA
+// (features on the M side in tiles of 16, samples on the N side, FP32
+// accumulation).  A lane of group g (lanes 16g .. 16g + 15) supplies the
+// operand elements e = 0..7 of the K-slice "g" of each product, for A and B
+// alike, so the product is the same whatever order the unit sums a K-slice
+// in as long as both operands number their K entries the same way.  The
+// accumulator of one layer holds, in lane (g, n), the features
+// 16 mt + 4 g + {0..3} of M-tile mt for sample n; two M-tiles side by side
+// are the next layer's B operand, which defines that layer's K numbering, and
+// the packed weights (built by closure_pack_kernel) follow it:
+//   layer 1, one K-step of 32:      element e <-> input 8 g + e (inputs 25..31 zero);
+//   layers 2 and 3, K-step ks:      element e <-> feature 32 ks + 16 (e / 4) + 4 g + (e % 4).
+// Packed weights, BF16, each lane's eight elements of one (M-tile, K-step)
+// contiguous (16 bytes): W1 [mt 4][g 4][row 16][8], W2 [mt 4][ks 2][g 4]
+// [row 16][8], W3 [ks 2][g 4][row 16][8] (rows 2..15 zero).  Each output
+// column depends on its own sample only, so a node's correction is the same
+// whichever nodes share its wavefront.  The small tiles keep the registers
+// the network needs (about forty) low enough for it to run inside the
+// multi-step kernel's loop.
+constexpr int kClW1 = 0, kClW2 = kClW1 + 64 * 32, kClW3 = kClW2 + 64 * 64, kClWN = kClW3 + 16 * 64;
+constexpr int kClB1 = 0, kClB2 = 64, kClB3 = 128, kClBN = 160;
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef unsigned short u16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kClWaves = 4;  // wavefronts per block of the closure kernel
+
+struct ClosureLds {
+    uint16_t w[kClWN];
+    float b[kClBN];
+    uint16_t x[kClWaves][kWave * 32];  // each wavefront's stencils, one row of 32 BF16 per sample
+};
+
+__device__ __forceinline__ uint16_t bf16_bits(float f) {
+    // round to nearest even (inputs are finite)
+    uint32_t u = __builtin_bit_cast(uint32_t, f);
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+
+// tanh form of GELU, tanh(u) = 1 - 2 / (exp(2u) + 1) with the hardware exp2
+__device__ __forceinline__ float gelu_fast(float x) {
+    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
+    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * u);  // exp(2u)
+    return 0.5f * x * (2.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f));
+}
+
+// GELU of two accumulator tiles (M-tiles 2 ks and 2 ks + 1), as the next
+// layer's BF16 B operand for K-step ks
+__device__ __forceinline__ bf16x8_t gelu_operand(const f32x4_t& lo, const f32x4_t& hi) {
+    u16x8_t r;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        r[i] = bf16_bits(gelu_fast(lo[i]));
+        r[4 + i] = bf16_bits(gelu_fast(hi[i]));
+    }
+    return __builtin_bit_cast(bf16x8_t, r);
+}
+
+// Keeps the compiler from moving memory operations across this point: the
+// network runs on a rarely taken path of loops that keep most registers
+// live, and loading all its weights and biases ahead would need more
+// registers than the loop leaves.
+__device__ __forceinline__ void mlp_fence() { asm volatile("" ::: "memory"); }
+
+// All 64 lanes of the wavefront must call this together.  w, b: packed
+// weights and biases (global memory or LDS).  xfrag(nt) returns this lane's
+// layer-1 B operand for N-tile nt: elements e = 0..7 are inputs 8 g + e of
+// sample 16 nt + (lane % 16), g = lane / 16, as BF16.  Returns the
+// correction (cx, cy) of sample `lane`; only the samples whose bit is set in
+// `want` (the same on every lane) are needed, and N-tiles without one are
+// skipped (their lanes get 0).
+template <typename XF>
+__device__ __forceinline__ void closure_mlp(const uint16_t* __restrict__ w, const float* __restrict__ b, XF&& xfrag,
+                                            uint64_t want, float& cxo, float& cyo) {
+    const int l = threadIdx.x % kWave;
+    const int r = l % 16, g = l / 16;
+    const bf16x8_t* wv = reinterpret_cast<const bf16x8_t*>(w);
+    auto bias = [&](int row0) { return *reinterpret_cast<const f32x4_t*>(&b[row0 + 4 * g]); };
+    float cx = 0.f, cy = 0.f;
+#pragma unroll 1
+    for (int nt = 0; nt < 4; ++nt) {
+        if (((want >> (16 * nt)) & 0xffffull) == 0) continue;
+        mlp_fence();
+        // layer 1: Z1^T (64 hidden x 16 samples) = W1 (64 x 32) X^T (32 x 16)
+        const bf16x8_t x = xfrag(nt);
+        f32x4_t z1[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt)
+            z1[mt] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[kClW1 / 8 + (mt * 4 + g) * 16 + r], x,
+                                                             bias(kClB1 + 16 * mt), 0, 0, 0);
+        const bf16x8_t h10 = gelu_operand(z1[0], z1[1]), h11 = gelu_operand(z1[2], z1[3]);
+        mlp_fence();
+        // layer 2: Z2^T = W2 (64 x 64) H1^T (64 x 16)
+        f32x4_t z2[4];
+#pragma unroll
+        for (int mt = 0; mt < 4; ++mt) {
+            f32x4_t acc = bias(kClB2 + 16 * mt);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[kClW2 / 8 + ((mt * 2 + 0) * 4 + g) * 16 + r], h10, acc, 0,
+                                                          0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[kClW2 / 8 + ((mt * 2 + 1) * 4 + g) * 16 + r], h11, acc, 0,
+                                                          0, 0);
+            z2[mt] = acc;
+        }
+        const bf16x8_t h20 = gelu_operand(z2[0], z2[1]), h21 = gelu_operand(z2[2], z2[3]);
+        mlp_fence();
+        // layer 3: out^T (2 of 16 rows x 16 samples) = W3 (16 x 64) H2^T
+        f32x4_t o = bias(kClB3);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[kClW3 / 8 + (0 * 4 + g) * 16 + r], h20, o, 0, 0, 0);
+        o = __builtin_amdgcn_mfma_f32_16x16x32_bf16(wv[kClW3 / 8 + (1 * 4 + g) * 16 + r], h21, o, 0, 0, 0);
+        // rows 0 (c_x) and 1 (c_y) of sample 16 nt + r sit in lane r (g = 0);
+        // lane l takes sample l, i.e. N-tile l / 16, from lane l % 16
+        const float tx = __shfl(o[0], r, kWave), ty = __shfl(o[1], r, kWave);
+        if (g == nt) {
+            cx = tx;
+            cy = ty;
+        }
+    }
+    cxo = cx;
+    cyo = cy;
+}
+
+// The network's correction at a node, in the frame the node's populations
+// are held in (mirror: the y axis reversed), added to its post-collision
+// populations: Eq. (9)-(11) are linear in G, so adding c_s^2 c to G changes
+// f*_i by (1 - 1/(2 tau)) w_i (c_i . c) for i >= 1 and leaves their sum phi;
+// the rest population is re-formed as the remainder.  The pairs i,
+// opposite(i) change by exact negatives, and a mirrored node rounds exactly
+// like its mirror image.
+__device__ __forceinline__ void closure_correct(float (&f)[9], float phi, float kforce, float ccx, float ccy,
+                                                bool mirror) {
+    const float kx = kforce * ccx, ky = kforce * (mirror ? -ccy : ccy);
+    const float ax = wq<float>(1) * kx, ay = wq<float>(1) * ky;
+    const float dx5 = wq<float>(5) * kx, dy5 = wq<float>(5) * ky;
+    f[1] += ax;
+    f[3] -= ax;
+    f[2] += ay;
+    f[4] -= ay;
+    f[5] += dx5 + dy5;
+    f[7] -= dx5 + dy5;
+    f[6] += dy5 - dx5;
+    f[8] -= dy5 - dx5;
+    f[0] = phi - sum_moving(f);
+}
+
+// The network on up to 64 listed nodes whose inputs lie in rings of five phi
+// rows in LDS (the S-step kernel with the closure): entry s of `tab`
+// (s < count) names a node by its ring (high 16 bits: which of the rings,
+// `ring_stride` floats apart) and its column in the ring rows (low 16 bits);
+// ring row (base + d) % 5 holds phi of the row d rows ahead of the nodes' row
+// in the frame the rings are filled in (mirror: the lattice's y axis
+// reversed).  Lane s returns the correction (cx, cy) of node s.
+__device__ __forceinline__ float2 closure_mlp_list(const uint16_t* w, const float* b, const float* rings,
+                                                   int ring_stride, int row_len, int base, bool mirror,
+                                                   const int* tab, int count) {
+    const int lane = threadIdx.x % kWave, hf = lane / 16;
+    auto xfrag = [&](int nt) {
+        const int s = 16 * nt + lane % 16;
+        const bool on = s < count;
+        const int ent = on ? tab[s] : 0;
+        const float* ring = rings + (ent >> 16) * ring_stride;
+        const int jc = ent & 0xffff;
+        u16x8_t v;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int kk = 8 * hf + e;
+            float x = 0.f;
+            if (on && kk < 25) {
+                const int dy = kk / 5 - 2, dx = kk % 5 - 2;
+                x = ring[((base + (mirror ? -dy : dy)) % 5) * row_len + jc + dx];
+            }
+            v[e] = bf16_bits(x);
+        }
+        return __builtin_bit_cast(bf16x8_t, v);
+    };
+    const uint64_t want = count >= 64 ? ~0ull : (1ull << count) - 1ull;
+    float2 c;
+    closure_mlp(w, b, xfrag, want, c.x, c.y);
+    return c;
+}
+
+// Stages the packed closure weights into LDS (all threads of the block).
+__device__ __forceinline__ void closure_stage(const StepArgs& a, ClosureLds& L) {
+    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.cl_w);
+    uint32_t* dst = reinterpret_cast<uint32_t*>(L.w);
+    for (int i = threadIdx.x; i < kClWN / 2; i += blockDim.x) dst[i] = src[i];
+    for (int i = threadIdx.x; i < kClBN; i += blockDim.x) L.b[i] = a.cl_b[i];
+    __syncthreads();
+}
+
+// Builds the packed BF16 weights and padded biases from the FP32 parameter
+// vector W1[64][25], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
+static __global__ void closure_pack_kernel(const float* __restrict__ p, uint16_t* __restrict__ w,
+                                           float* __restrict__ b) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    const int e = t % 8, row = (t / 8) % 16, g = (t / 128) % 4;
+    // feature of element e of K-slice g in K-step ks of layers 2 and 3
+    auto feat = [&](int ks) { return 32 * ks + 16 * (e / 4) + 4 * g + (e % 4); };
+    if (t < 64 * 32) {
+        const int mt = t / 512;
+        const int k = 8 * g + e;
+        w[kClW1 + t] = k < 25 ? bf16_bits(p[(16 * mt + row) * 25 + k]) : 0;
+    }
+    if (t < 64 * 64) {
+        const int ks = (t / 512) % 2, mt = t / 1024;
+        w[kClW2 + t] = bf16_bits(p[1600 + 64 + (16 * mt + row) * 64 + feat(ks)]);
+    }
+    if (t < 16 * 64) {
+        const int ks = t / 512;
+        w[kClW3 + t] = row < 2 ? bf16_bits(p[1600 + 64 + 4096 + 64 + row * 64 + feat(ks)]) : 0;
+    }
+    if (t < 64) {
+        b[kClB1 + t] = p[1600 + t];
+        b[kClB2 + t] = p[1600 + 64 + 4096 + t];
+    }
+    if (t < 32) b[kClB3 + t] = t < 2 ? p[1600 + 64 + 4096 + 64 + 128 + t] : 0.f;
+}
+
 // ---------------------------------------------------------------------------
 // S steps per pass over HBM (S = 1, 2 or 3; FP32 collide, FP32 or shifted
 // 16-bit storage).
@@ -722,22 +943,32 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // a tile and marches the strip as the block variant does, with S stages
 // chained in one pipeline.  Stage 0 takes step t from the populations in HBM;
 // stage k takes step t + k from the post-collision populations of stage
-// k - 1, which stay in an LDS ring, and runs three rows behind it; stage
-// S - 1 stores to HBM.  Stage k works on the tile grown by 2 (S - 1 - k)
-// columns on each side (so the block loads 2 S halo columns on each side),
-// and the strip's first and last 2 S rows are loaded and computed by both
-// neighbouring strips.  Each stage does exactly the arithmetic of one step of
-// the block variant on every node, with the same helpers and summation
-// orders, so with FP32 storage S steps of this kernel equal S launches of the
-// one-step kernels bit for bit, while HBM is read and written once per S
-// steps.  With shifted 16-bit storage the populations pass through 16 bits
-// only at the launch's load and store (the intermediate steps keep them in
-// FP32 in LDS), so that form rounds to its storage precision once per launch.
+// k - 1, which stay in an LDS ring; stage S - 1 stores to HBM.  A stage
+// reaches RC = 2 columns and rows (pull and psi gradient), so stage k works
+// on the tile grown by RC (S - 1 - k) columns on each side (the block loads
+// H = RC S halo columns on each side), and the strip's first and last H rows
+// are loaded and computed by both neighbouring strips.  Each stage does
+// exactly the arithmetic of one step of the block variant on every node, with
+// the same helpers and summation orders, so with FP32 storage S steps of this
+// kernel equal S launches of the one-step kernels bit for bit, while HBM is
+// read and written once per S steps.  With shifted 16-bit storage the
+// populations pass through 16 bits only at the launch's load and store (the
+// intermediate steps keep them in FP32 in LDS), so that form rounds to its
+// storage precision once per launch.
+//
+// With the learned closure (CL; FP32 storage) a stage also evaluates the
+// network on the interface-band nodes of the row it updates and adds its
+// correction to their post-collision populations exactly as the one-step
+// path's correction pass does, so the results are again those of S one-step
+// launches bit for bit.  The network reads the 5x5 neighbourhood of phi, so
+// a stage reaches RC = 3 columns and rows, keeps its last five phi rows in
+// LDS, and updates a row UL = 2 rows behind the one it forms phi on (the
+// plain stages: UL = 1).
 //
 // Rows at iteration it (dir = +1 up the strip, -1 down it): row R enters
-// stage 0's ring; stage k forms phi and psi on R - (3k + 1) dir and updates
-// R - (3k + 2) dir.  Two LDS barriers per iteration, as in the one-step
-// kernel.
+// stage 0's ring; stage k forms phi and psi on R - (LG k + 1) dir and updates
+// R - (LG k + 1 + UL) dir, LG = UL + 2.  Two LDS barriers per iteration, as
+// in the one-step kernel.
 //
 // Rings.  A pull f_i(x, c) = f*_i(x - c_i) needs another thread's column only
 // for the six populations with c_x != 0, and each of those only from one
@@ -746,62 +977,86 @@ __global__ __launch_bounds__(block_threads<BX>()) void step_kernel_lds(StepArgs 
 // stages see) or the row ahead (the "new" pair 8, 7).  So the rings hold,
 // per pair, as many rows as the pull is late; the three populations with
 // c_x = 0 stay in the thread's registers.  Pairs are stored c_x = +1 first.  Index j <-> column
-// x0 - 2S - 1 + j; indices 0 and W - 1 are padding, so that every thread's
+// x0 - H - 1 + j; indices 0 and W - 1 are padding, so that every thread's
 // reads at j - 1 and j + 1 stay inside its row, and W - 1 also takes the
 // writes of threads past the grown tile.
-template <int BX, int S>
-struct TileSLds {
-    static constexpr int W = BX + 4 * S + 2;
-    float ro[S][3][2][W];  // input of stage k: old pair, three rows
-    float rm[S][2][2][W];  // populations 1 and 3, two rows
-    float rn[S][2][W];     // new pair, one row
-    float ps[S][3][W];     // psi of stage k on its last three rows
+template <int BX, int S, bool CL>
+struct StepSGeom {
+    static constexpr int RC = CL ? 3 : 2;      // columns and rows one stage reaches
+    static constexpr int H = RC * S;           // halo columns (and shared rows) on each side
+    static constexpr int UL = CL ? 2 : 1;      // rows from a stage's phi row back to the row it updates
+    static constexpr int LG = UL + 2;          // rows between consecutive stages
+    static constexpr int PER = 3 + 2 * UL;     // iterations between consecutive stages' first values
+    static constexpr int D = LG * (S - 1) + 1 + UL;  // rows from the loaded row back to the stored one
+    static constexpr int W = BX + 2 * H + 2;   // LDS row length
+    static constexpr int NPS = UL + 2;         // psi rows kept per stage
+    static constexpr int NP = UL + 3;          // depth of the phi(t - 1) history
 };
 
-// Threads of an S-step tile of at most BX columns: the BX + 4S columns of the
+template <int BX, int S, bool CL>
+struct TileSLdsBase {
+    static constexpr int W = StepSGeom<BX, S, CL>::W;
+    float ro[S][3][2][W];                          // input of stage k: old pair, three rows
+    float rm[S][2][2][W];                          // populations 1 and 3, two rows
+    float rn[S][2][W];                             // new pair, one row
+    float ps[S][StepSGeom<BX, S, CL>::NPS][W];     // psi of stage k on its last rows
+};
+template <int BX, int S, bool CL = false>
+struct TileSLds : TileSLdsBase<BX, S, CL> {};
+template <int BX, int S>
+struct TileSLds<BX, S, true> : TileSLdsBase<BX, S, true> {
+    float phr[S][5][TileSLdsBase<BX, S, true>::W];  // phi of stage k on its last five rows
+    int tab[(BX + 6 * S + 63) / 64][S * 64];         // per wavefront: the band nodes of an iteration
+};
+
+// Threads of an S-step tile of at most BX columns: the BX + 2H columns of the
 // grown tile rounded up to whole wavefronts (enough for the layout below at
 // every tile width up to BX).
-template <int BX, int S>
+template <int BX, int S, bool CL = false>
 __host__ __device__ constexpr int stepS_threads() {
-    return (BX + 4 * S + 63) / 64 * 64;
+    return (BX + 2 * StepSGeom<BX, S, CL>::H + 63) / 64 * 64;
 }
 
-// COH: FP32 plain storage through IoCoherent (the batched form).
-template <int MODEL, int BX, int S, int ST, bool COH = false>
+// COH: FP32 plain storage through IoCoherent (the batched form).  CL: the
+// learned closure (FP32 plain storage).
+template <int MODEL, int BX, int S, int ST, bool COH = false, bool CL = false>
 __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w, int ys, int hh, int64_t t,
-                                               bool down, TileSLds<BX, S>& lds) {
+                                               bool down, TileSLds<BX, S, CL>& lds) {
     static_assert(!COH || ST == ST_PLAIN, "coherent access is for FP32 plain storage");
+    static_assert(!CL || (ST == ST_PLAIN && !COH), "the closure runs with FP32 plain storage");
+    using G = StepSGeom<BX, S, CL>;
+    constexpr int H = G::H, UL = G::UL, LG = G::LG, PER = G::PER, D = G::D, W = G::W, NPS = G::NPS;
     using IoT = typename std::conditional<COH, IoCoherent, Io<float, ST>>::type;
     // Thread layout.  The C = 64 * c columns of the tile that whole wavefronts
     // own go to wavefronts 0 .. c - 1, one aligned 64-column segment each (so
     // every wavefront loads and stores whole 256-byte lines); wavefront c, the
-    // halo wavefront, takes the 2S left halo columns, the tile's remaining
+    // halo wavefront, takes the H left halo columns, the tile's remaining
     // w - C columns and the right halo (c is the largest count for which that
     // fits in 64 lanes, else one more, whose last columns then belong to the
     // right halo); later wavefronts (a tile narrower than BX) only take part
     // in the barriers.  Threads whose column lies past the right halo
     // duplicate its last column: they load what its owner loads, write their
     // LDS values to the padding column and store nothing.  cxo: column
-    // relative to x0 (-2S .. w + 2S - 1); act: owns tile column x0 + cxo.
+    // relative to x0 (-H .. w + H - 1); act: owns tile column x0 + cxo.
     const int l = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(l) / kWave;  // wavefront index (uniform)
     const int full = w / kWave;
-    const int C = (w - kWave * full) + 4 * S <= kWave ? kWave * full : kWave * (full + 1);
+    const int C = (w - kWave * full) + 2 * H <= kWave ? kWave * full : kWave * (full + 1);
     const int hw = C / kWave;  // the halo wavefront
     const int hl = l - C;      // lane in the halo wavefront
-    const int craw = wv < hw ? l : (hl < 2 * S ? hl - 2 * S : C + hl - 2 * S);
-    const bool dup = craw > w + 2 * S - 1;
-    const int cxo = min(craw, w + 2 * S - 1);
+    const int craw = wv < hw ? l : (hl < H ? hl - H : C + hl - H);
+    const bool dup = craw > w + H - 1;
+    const int cxo = min(craw, w + H - 1);
     const bool act = cxo >= 0 && cxo < w && !dup;
-    // Stage k forms phi/psi validly on columns -(2(S-k)-1) .. w+2(S-k)-2 and
-    // updates -(2(S-k)-2) .. w+2(S-k)-3.  Every thread runs every stage
-    // (branching on these ranges would only hold per-lane masks, since every
-    // wavefront has lanes inside them): outside them a thread forms values
-    // from rows or columns that are not valid yet, which no valid value reads
-    // (each range is the next one's reach plus one column on each side).
+    // Stage k forms phi/psi validly on the columns (and rows) up to
+    // RC (S - k) - 1 beyond the tile and updates up to RC (S - 1 - k) beyond
+    // it.  Every thread runs every stage (branching on these ranges would only
+    // hold per-lane masks, since every wavefront has lanes inside them):
+    // outside them a thread forms values from rows or columns that are not
+    // valid yet, which no valid value reads.
     const int gcol = wrap_idx(x0 + cxo, a.nx);
-    const int j = cxo + 2 * S + 1;                    // LDS column read
-    const int jw = dup ? TileSLds<BX, S>::W - 1 : j;  // LDS column written
+    const int j = cxo + H + 1;        // LDS column read
+    const int jw = dup ? W - 1 : j;   // LDS column written
     // A strip marched downward is computed in the mirrored frame y -> -y:
     // populations are read from and written to the planes of their mirror
     // images and the y velocity changes sign, so the march always runs
@@ -812,7 +1067,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
     const IoT io(a, down);
     lds_barrier();  // the LDS may still be read by a previous tile of this block
 
-    const int iters = hh + 5 * S - 1;
+    const int iters = hh + H + D;
     if (wv > hw) {
         // no column in this wavefront: the loop's two barriers per iteration only
         for (int it = 0; it < iters; ++it) {
@@ -831,14 +1086,16 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
     for (int k = 0; k < S; ++k) kcs[k] = NodeConst<float>(a, t + k);
     // pulled populations and phi of stage k, ping-pong by iteration parity:
     // the pull of iteration it fills half it & 1, the update of iteration
-    // it + 1 reads it
+    // it + UL reads it (with UL = 2 through fh, which keeps the pull of two
+    // iterations ago before the half is refilled)
     float fp[S][2][9], ph[S][2], ob[9];
+    float fh[CL ? S : 1][9];
     float phl = 0.f;  // phi of the last stage's updated node (the shifted store's phi*)
     // Histories, index = age in iterations (0: this iteration).  P[k]: the sum
     // of stage k's input populations at the own node (phi(t + k - 1) as the
     // one-step kernel forms it); z0, zo, zn: the own column's c_x = 0 inputs
     // of stage k (population 0, the old-row one, the new-row one).
-    float P[S][4], z0[S][4], zo[S][4], zn[S][4];
+    float P[S][G::NP], z0[S][4], zo[S][4], zn[S][4];
     // shifted storage: the own column's populations 7 and 8 of stage 0's last
     // two input rows (the rings keep them only where another column pulls them)
     float o7[2] = {0.f, 0.f}, o8[2] = {0.f, 0.f};
@@ -852,16 +1109,22 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
             for (int q = 0; q < 9; ++q) fp[k][b][q] = 0.f;
         }
 #pragma unroll
-        for (int d = 0; d < 4; ++d) P[k][d] = z0[k][d] = zo[k][d] = zn[k][d] = 0.f;
+        for (int d = 0; d < G::NP; ++d) P[k][d] = 0.f;
+#pragma unroll
+        for (int d = 0; d < 4; ++d) z0[k][d] = zo[k][d] = zn[k][d] = 0.f;
     }
+#pragma unroll
+    for (int k = 0; k < (CL ? S : 1); ++k)
+#pragma unroll
+        for (int q = 0; q < 9; ++q) fh[k][q] = 0.f;
 #pragma unroll
     for (int q = 0; q < 9; ++q) ob[q] = 0.f;
 
     const int dir = down ? -1 : 1;
-    auto raw_row = [&](int it) { return down ? ys + hh + 2 * S - 1 - it : ys - 2 * S + it; };
+    auto raw_row = [&](int it) { return down ? ys + hh + H - 1 - it : ys - H + it; };
     // lattice row loaded at iteration it (iterations past the last input row
     // repeat it; what they form is not used)
-    auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, hh + 4 * S - 1)), a.ny); };
+    auto row_of = [&](int it) { return (uint32_t)wrap_idx(raw_row(min(it, hh + 2 * H - 1)), a.ny); };
     // a stage's input into its ring and histories (v: populations at the own column)
     auto put = [&](int k, int s3, int s2, const float(&v)[9]) __attribute__((always_inline)) {
         // phi at t + k - 1: the sum of the stage's input values (phi* itself
@@ -885,6 +1148,7 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
         constexpr int B = decltype(parity)::value;  // it & 1
         const int Rr = raw_row(it);
         const int s3 = it % 3, s2 = B;
+        const int sps = CL ? it % NPS : s3;  // psi slot of this iteration's phi row
         // ---- row R into stage 0's ring
         put(0, s3, s2, nv);
         io.load(row_of(it + 2) * (uint32_t)a.pitch + (uint32_t)gcol, nv);
@@ -897,7 +1161,11 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const int lag = k == 0 ? 0 : 1;
-            if (it >= 5 * k + 2) {
+            if constexpr (CL) {
+#pragma unroll
+                for (int q = 0; q < 9; ++q) fh[k][q] = fp[k][B][q];
+            }
+            if (it >= PER * k + 2) {
                 const int so = (it + 1 + 2 * lag) % 3;  // old pair: it - 2 - lag
                 const int sm = B ^ 1 ^ lag;             // populations 1, 3: it - 1 - lag
                 float(&f)[9] = fp[k][B];
@@ -930,42 +1198,125 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
                     s = sum9(f);
                 }
                 ph[k][B] = s;
-                lds.ps[k][s3][jw] = normal_source<float, MODEL>(s, kcs[k]);
+                lds.ps[k][sps][jw] = normal_source<float, MODEL>(s, kcs[k]);
+                if constexpr (CL) lds.phr[k][it % 5][jw] = s;
             }
         }
         lds_barrier();
 
-        // psi rows around an updated row (centre slot it + 2; the newest row,
-        // slot it, is one step ahead of it: +y in the stages' frame)
-        const int c0 = (it + 2) % 3;
-        const int cm = (it + 1) % 3;
-        const int cp = it % 3;
-        // ---- updates: stage k on row R - (3k + 2) dir at t + k; the last stage into HBM
-        const bool st = act && it >= 5 * S - 1;
-        const int yl = min(max(Rr - (3 * S - 1) * dir, 0), a.ny - 1);
+        // psi rows around an updated row: the centre row is UL rows behind this
+        // iteration's phi row, and the row ahead of it (+y in the stages'
+        // frame) one row nearer
+        const int c0 = (it + NPS - UL) % NPS;
+        const int cm = (it + NPS - UL - 1) % NPS;
+        const int cp = (it + (NPS - UL + 1) % NPS) % NPS;
+        // ---- updates: stage k on row R - (LG k + 1 + UL) dir at t + k; the last stage into HBM
+        const bool st = act && it >= PER * (S - 1) + 2 + 2 * UL;
+        const int yl = min(max(Rr - D * dir, 0), a.ny - 1);
+        uint64_t bms[S];  // closure: band nodes of stage k's updated row (one bit per lane)
+#pragma unroll
+        for (int k = 0; k < S; ++k) bms[k] = 0;
 #pragma unroll
         for (int k = 0; k < S; ++k) {
             const bool last = k == S - 1;
-            if (it >= 5 * k + 4) {
+            if (it >= PER * k + 2 + 2 * UL) {
                 const NodeConst<float>& kc = kcs[k];
-                const int y = last ? yl : wrap_idx(Rr - (3 * k + 2) * dir, a.ny);
-                const float(&ps)[3][TileSLds<BX, S>::W] = lds.ps[k];
+                const int y = last ? yl : wrap_idx(Rr - (LG * k + 1 + UL) * dir, a.ny);
+                const float(&ps)[NPS][W] = lds.ps[k];
                 float gx, gy, Gx, Gy;
                 iso_gradient(ps[c0][j + 1], ps[c0][j - 1], ps[cp][j], ps[cm][j], ps[cp][j + 1], ps[cp][j - 1],
                              ps[cm][j + 1], ps[cm][j - 1], gx, gy);
-                const float phi = ph[k][B ^ 1];
+                float phi;
+                if constexpr (CL) phi = lds.phr[k][(it + 3) % 5][j];  // phi row it - 2
+                else phi = ph[k][B ^ 1];
                 const float uxr = Ax * row_factor(a.vtabf, 2 * a.nx + y);
                 const float uyr = Bx * row_factor(a.vtabf, 2 * a.nx + a.ny + y);
-                const float phio = P[k][k == 0 ? 2 : 3];
+                const float phio = P[k][(k == 0 ? 1 : 2) + UL];
                 flux_bracket<float, MODEL>(gx, gy, phi, kc.first ? phi : phio, kc.s_now * uxr, kc.s_now * uyr,
                                            kc.s_old * uxr, kc.s_old * uyr, kc, Gx, Gy);
-                collide(fp[k][B ^ 1], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
+                if constexpr (CL) {
+                    collide(fh[k], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
+                    // interface-band nodes among those stage k must update (the
+                    // condition of the one-step path's band mask); their
+                    // correction is added after the last stage (below)
+                    const int reach = G::RC * (S - 1 - k);
+                    const int rel = it - H - (LG * k + 1 + UL);  // row relative to the strip, march frame
+                    const bool need = !dup && cxo >= -reach && cxo < w + reach && rel >= -reach && rel < hh + reach;
+                    const float pc = clip01(phi);
+                    bms[k] = __ballot(need && pc > a.cl_theta && pc < 1.0f - a.cl_theta);
+                } else {
+                    collide(fp[k][B ^ 1], phi, kc.s_now * uxr, kc.s_now * uyr, Gx, Gy, kc, ob);
+                }
                 if (!last) put(k + 1, s3, s2, ob);
                 else phl = phi;
             }
         }
+        if constexpr (CL) {
+            // The network on every stage's band nodes of this wavefront, packed
+            // into one list (stage by stage, lanes in order), from stage k's
+            // phi ring (rows it - 4 .. it; the updated row is it - 2), and its
+            // correction added to the node's post-collision populations: for
+            // the last stage in ob before the store, for an earlier one where
+            // put() left them (the next stage's rings and own-column
+            // histories), which nothing reads before the next iteration.
+            const int lane = l % kWave;
+            const uint64_t below = (1ull << lane) - 1ull;
+            int slot[S], count = 0;
+#pragma unroll
+            for (int k = 0; k < S; ++k) {
+                slot[k] = count + __popcll(bms[k] & below);
+                count += __popcll(bms[k]);
+            }
+            if (count) {
+                int* tab = lds.tab[wv];
+#pragma unroll
+                for (int k = 0; k < S; ++k)
+                    if ((bms[k] >> lane) & 1ull) tab[slot[k]] = (k << 16) | j;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+                for (int first = 0; first < count; first += kWave) {
+                    const float2 c = closure_mlp_list(a.cl_w, a.cl_b, &lds.phr[0][0][0], 5 * W, W, it + 3, down,
+                                                      tab + first, count - first);
+#pragma unroll
+                    for (int k = 0; k < S; ++k) {
+                        const int src = slot[k] - first;
+                        const float cx = __shfl(c.x, src & (kWave - 1), kWave);
+                        const float cy = __shfl(c.y, src & (kWave - 1), kWave);
+                        if (!((bms[k] >> lane) & 1ull) || src < 0 || src >= kWave) continue;
+                        const float phi = lds.phr[k][(it + 3) % 5][j];
+                        if (k == S - 1) {
+                            closure_correct(ob, phi, kcs[k].kforce, cx, cy, down);
+                        } else {
+                            const int n = k == S - 1 ? 0 : k + 1;  // (k + 1 without the out-of-range index)
+                            float f[9];
+                            f[1] = lds.rm[n][s2][0][jw];
+                            f[3] = lds.rm[n][s2][1][jw];
+                            f[5] = lds.ro[n][s3][0][jw];
+                            f[6] = lds.ro[n][s3][1][jw];
+                            f[8] = lds.rn[n][0][jw];
+                            f[7] = lds.rn[n][1][jw];
+                            f[2] = zo[n][0];
+                            f[4] = zn[n][0];
+                            closure_correct(f, phi, kcs[k].kforce, cx, cy, down);
+                            lds.rm[n][s2][0][jw] = f[1];
+                            lds.rm[n][s2][1][jw] = f[3];
+                            lds.ro[n][s3][0][jw] = f[5];
+                            lds.ro[n][s3][1][jw] = f[6];
+                            lds.rn[n][0][jw] = f[8];
+                            lds.rn[n][1][jw] = f[7];
+                            z0[n][0] = f[0];
+                            zo[n][0] = f[2];
+                            zn[n][0] = f[4];
+                            P[n][0] = sum9(f);
+                        }
+                    }
+                }
+                __builtin_amdgcn_wave_barrier();  // the list is rewritten next iteration
+            }
+        }
         // non-temporal: a stored row is not read again in this launch, while
-        // the 4S rows each strip shares with its neighbours are (1.5% faster
+        // the 2H rows each strip shares with its neighbours are (1.5% faster
         // at 8192^2 than plain stores)
         io.store_nt(st, (uint32_t)yl * (uint32_t)a.pitch + (uint32_t)(x0 + cxo), ob, phl);
         // ---- age the histories by one iteration
@@ -974,8 +1325,9 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
 #pragma unroll
         for (int k = 0; k < S; ++k) {
 #pragma unroll
+            for (int d = G::NP - 1; d > 0; --d) P[k][d] = P[k][d - 1];
+#pragma unroll
             for (int d = 3; d > 0; --d) {
-                P[k][d] = P[k][d - 1];
                 z0[k][d] = z0[k][d - 1];
                 zo[k][d] = zo[k][d - 1];
                 zn[k][d] = zn[k][d - 1];
@@ -1002,6 +1354,20 @@ __global__ __launch_bounds__((stepS_threads<BX, S>())) void stepS_kernel_lds(Ste
     const int x0 = bxi * BX, ys = syi * a.strip_h;
     stepS_tile_lds<MODEL, BX, S, ST>(a, x0, min(BX, a.nx - x0), ys, min(a.strip_h, a.ny - ys), a.t_dev[0] + a.k,
                                      (syi & 1) != 0, lds);
+}
+
+// The S-step kernel with the learned closure (FP32 storage, improved model).
+template <int BX, int S>
+__global__ __launch_bounds__((stepS_threads<BX, S, true>())) __attribute__((amdgpu_waves_per_eu(2, 2))) void
+stepS_kernel_cl(StepArgs a) {
+    __shared__ TileSLds<BX, S, true> lds;
+    const int ntile = a.nbx * a.nby;
+    const int tile = xcd_tile(blockIdx.x, ntile, a.n_xcd);
+    const int bxi = tile % a.nbx, syi = tile / a.nbx;
+    const int x0 = bxi * BX, ys = syi * a.strip_h;
+    stepS_tile_lds<MODEL_IMPROVED, BX, S, ST_PLAIN, false, true>(a, x0, min(BX, a.nx - x0), ys,
+                                                                 min(a.strip_h, a.ny - ys), a.t_dev[0] + a.k,
+                                                                 (syi & 1) != 0, lds);
 }
 
 // ---------------------------------------------------------------------------
@@ -1048,154 +1414,6 @@ __device__ __forceinline__ R pulled(const R (&r0)[9], const R (&r1)[9], const R 
     constexpr int d = DIR * cy(Q);
     const R v = d == -1 ? r0[Q] : (d == 0 ? r1[Q] : r2[Q]);
     return from_lane<cx(Q)>(v);
-}
-
-// ---- learned closure: BF16 MFMA inference ------------------------------------
-// Packed weights (built on the device by closure_pack_kernel): W1 as 64 rows of
-// 32 (inputs 25..31 zero), W2 64 x 64, W3 as 32 rows of 64 (rows 2..31 zero),
-// all BF16, row-major.  The network runs on the 64 samples of a wavefront as
-// three chained products Z^T = W H^T with the 32x32x8 BF16 MFMA (features on
-// the M side, samples on the N side): the FP32 accumulator tile of one layer
-// holds, per lane, exactly the K-fragment the next layer's B operand needs,
-// so only the input stencils pass through LDS.
-constexpr int kClW1 = 0, kClW2 = kClW1 + 64 * 32, kClW3 = kClW2 + 64 * 64, kClWN = kClW3 + 32 * 64;
-constexpr int kClB1 = 0, kClB2 = 64, kClB3 = 128, kClBN = 160;
-
-typedef short bf16x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x16_t __attribute__((ext_vector_type(16)));
-
-constexpr int kClWaves = 4;  // wavefronts per block of the closure kernel
-
-struct ClosureLds {
-    uint16_t w[kClWN];
-    float b[kClBN];
-    uint16_t x[kClWaves][kWave * 32];  // each wavefront's stencils, one row of 32 BF16 per sample
-};
-
-__device__ __forceinline__ uint16_t bf16_bits(float f) {
-    // round to nearest even (inputs are finite)
-    uint32_t u = __builtin_bit_cast(uint32_t, f);
-    u += 0x7fffu + ((u >> 16) & 1u);
-    return (uint16_t)(u >> 16);
-}
-
-// tanh form of GELU, tanh(u) = 1 - 2 / (exp(2u) + 1) with the hardware exp2
-__device__ __forceinline__ float gelu_fast(float x) {
-    const float u = 0.7978845608028654f * (x + 0.044715f * x * x * x);
-    const float e = __builtin_amdgcn_exp2f(2.8853900817779268f * u);  // exp(2u)
-    return 0.5f * x * (2.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f));
-}
-
-// All 64 lanes must call this together.  xin: this lane's 25 inputs;
-// returns this lane's correction (cx, cy).
-__device__ __forceinline__ void closure_mlp(ClosureLds& L, const float (&xin)[25], float& cxo, float& cyo) {
-    const int l = threadIdx.x % kWave;
-    const int lr = l % 32, lk = 4 * (l / 32);
-    uint16_t* xs = L.x[(threadIdx.x / kWave) % kClWaves];
-#pragma unroll
-    for (int k = 0; k < 32; k += 2) {
-        const uint32_t lo = k < 25 ? bf16_bits(xin[k]) : 0u;
-        const uint32_t hi = k + 1 < 25 ? bf16_bits(xin[k + 1]) : 0u;
-        *reinterpret_cast<uint32_t*>(&xs[l * 32 + k]) = lo | (hi << 16);
-    }
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
-
-    bf16x4_t h1[2][2][4], h2[2][2][4];
-    // layer 1: Z1^T (64 hidden x 64 samples) = W1 (64 x 32) X^T (32 x 64)
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            f32x16_t acc;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB1 + 32 * mt + 8 * (v / 4) + lk + (v % 4)];
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const bf16x4_t A = *reinterpret_cast<const bf16x4_t*>(&L.w[kClW1 + (32 * mt + lr) * 32 + 8 * ks + lk]);
-                const bf16x4_t B = *reinterpret_cast<const bf16x4_t*>(&xs[(32 * nt + lr) * 32 + 8 * ks + lk]);
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, B, acc, 0, 0, 0);
-            }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h1[mt][nt][ks][t] = (short)bf16_bits(gelu_fast(acc[4 * ks + t]));
-        }
-    // layer 2: Z2^T = W2 (64 x 64) H1^T (64 x 64)
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt)
-#pragma unroll
-        for (int nt = 0; nt < 2; ++nt) {
-            f32x16_t acc;
-#pragma unroll
-            for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB2 + 32 * mt + 8 * (v / 4) + lk + (v % 4)];
-#pragma unroll
-            for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-                for (int ks = 0; ks < 4; ++ks) {
-                    const bf16x4_t A =
-                        *reinterpret_cast<const bf16x4_t*>(&L.w[kClW2 + (32 * mt + lr) * 64 + 32 * kt + 8 * ks + lk]);
-                    acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, h1[kt][nt][ks], acc, 0, 0, 0);
-                }
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks)
-#pragma unroll
-                for (int t = 0; t < 4; ++t) h2[mt][nt][ks][t] = (short)bf16_bits(gelu_fast(acc[4 * ks + t]));
-        }
-    // layer 3: out^T (2 of 32 rows x 64 samples) = W3 (32 x 64) H2^T
-    float o[2][2];
-#pragma unroll
-    for (int nt = 0; nt < 2; ++nt) {
-        f32x16_t acc;
-#pragma unroll
-        for (int v = 0; v < 16; ++v) acc[v] = L.b[kClB3 + 8 * (v / 4) + lk + (v % 4)];
-#pragma unroll
-        for (int kt = 0; kt < 2; ++kt)
-#pragma unroll
-            for (int ks = 0; ks < 4; ++ks) {
-                const bf16x4_t A = *reinterpret_cast<const bf16x4_t*>(&L.w[kClW3 + lr * 64 + 32 * kt + 8 * ks + lk]);
-                acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(A, h2[kt][nt][ks], acc, 0, 0, 0);
-            }
-        o[nt][0] = acc[0];  // row 0 (c_x) of sample 32 nt + lr, valid on lanes 0..31
-        o[nt][1] = acc[1];  // row 1 (c_y)
-    }
-    // sample l lives in tile l / 32 at lane l % 32
-    const float t0 = __shfl(o[1][0], (l + 32) & 63, kWave);
-    const float t1 = __shfl(o[1][1], (l + 32) & 63, kWave);
-    cxo = l < 32 ? o[0][0] : t0;
-    cyo = l < 32 ? o[0][1] : t1;
-    __builtin_amdgcn_wave_barrier();  // the staging rows are reused by the next call
-}
-
-// Stages the packed closure weights into LDS (all threads of the block).
-__device__ __forceinline__ void closure_stage(const StepArgs& a, ClosureLds& L) {
-    const uint32_t* src = reinterpret_cast<const uint32_t*>(a.cl_w);
-    uint32_t* dst = reinterpret_cast<uint32_t*>(L.w);
-    for (int i = threadIdx.x; i < kClWN / 2; i += blockDim.x) dst[i] = src[i];
-    for (int i = threadIdx.x; i < kClBN; i += blockDim.x) L.b[i] = a.cl_b[i];
-    __syncthreads();
-}
-
-// Builds the packed BF16 weights and padded biases from the FP32 parameter
-// vector W1[64][25], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].
-static __global__ void closure_pack_kernel(const float* __restrict__ p, uint16_t* __restrict__ w,
-                                           float* __restrict__ b) {
-    const int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < 64 * 32) {
-        const int r = i / 32, k = i % 32;
-        w[kClW1 + i] = k < 25 ? bf16_bits(p[r * 25 + k]) : 0;
-    }
-    if (i < 64 * 64) w[kClW2 + i] = bf16_bits(p[1600 + 64 + i]);
-    if (i < 32 * 64) {
-        const int r = i / 64, k = i % 64;
-        w[kClW3 + i] = r < 2 ? bf16_bits(p[1600 + 64 + 4096 + 64 + r * 64 + k]) : 0;
-    }
-    if (i < 64) {
-        b[kClB1 + i] = p[1600 + i];
-        b[kClB2 + i] = p[1600 + 64 + 4096 + i];
-    }
-    if (i < 32) b[kClB3 + i] = i < 2 ? p[1600 + 64 + 4096 + 64 + 128 + i] : 0.f;
 }
 
 // ---- the wavefront step ----------------------------------------------------
@@ -1420,27 +1638,31 @@ static __global__ __launch_bounds__(kClWaves * kWave) void closure_apply_kernel(
                                 wrap_idx(zx - cx(q), a.nx)];
                 xin[(dy + 2) * 5 + (dx + 2)] = sum9(fz);
             }
+        // the inputs as BF16 rows of 32 (25..31 zero) in this wavefront's staging area
+        uint16_t* xs = cl.x[(threadIdx.x / kWave) % kClWaves];
+#pragma unroll
+        for (int k = 0; k < 32; k += 2) {
+            const uint32_t lo = k < 25 ? bf16_bits(xin[k]) : 0u;
+            const uint32_t hi = k + 1 < 25 ? bf16_bits(xin[k + 1]) : 0u;
+            *reinterpret_cast<uint32_t*>(&xs[l * 32 + k]) = lo | (hi << 16);
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+        auto xfrag = [&](int nt) {
+            return *reinterpret_cast<const bf16x8_t*>(&xs[(16 * nt + l % 16) * 32 + 8 * (l / 16)]);
+        };
         float ccx, ccy;
-        closure_mlp(cl, xin, ccx, ccy);
+        closure_mlp(cl.w, cl.b, xfrag, ~0ull, ccx, ccy);
+        __builtin_amdgcn_wave_barrier();  // the staging rows are rewritten by the next group
         if (on) {
             const float phi = xin[12];
             const int64_t off = (int64_t)y * a.pitch + x;
-            const float kx = kforce * ccx, ky = kforce * ccy;
             float f[9];
 #pragma unroll
             for (int q = 1; q < 9; ++q) f[q] = dst[q * a.plane_stride + off];
-            // w_i (c_i . (1 - 1/(2 tau)) c): the pairs i, opposite(i) change by exact negatives
-            const float ax = wq<float>(1) * kx, ay = wq<float>(1) * ky;
-            const float dx5 = wq<float>(5) * kx, dy5 = wq<float>(5) * ky;
-            f[1] += ax;
-            f[3] -= ax;
-            f[2] += ay;
-            f[4] -= ay;
-            f[5] += dx5 + dy5;
-            f[7] -= dx5 + dy5;
-            f[6] += dy5 - dx5;
-            f[8] -= dy5 - dx5;
-            dst[off] = phi - sum_moving(f);
+            closure_correct(f, phi, kforce, ccx, ccy, false);
+            dst[off] = f[0];
 #pragma unroll
             for (int q = 1; q < 9; ++q) dst[q * a.plane_stride + off] = f[q];
         }

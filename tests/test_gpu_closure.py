@@ -53,17 +53,22 @@ def test_zero_output_layer_is_the_plain_step(gpu_lib):
     assert np.array_equal(a.phi(), b.phi())
 
 
-@pytest.mark.parametrize("eps", [1.0, 0.5])
-def test_closure_matches_oracle(gpu_lib, eps):
+@pytest.mark.parametrize("eps,launch", [(1.0, None), (0.5, None), (1.0, (224, 16, 4)), (0.5, (160, 24, 4)),
+                                        (1.0, (128, 40, 3))])
+def test_closure_matches_oracle(gpu_lib, eps, launch):
     """The GPU rounds the network's inputs and hidden activations to BF16; the
     oracle evaluates the same BF16-rounded weights in FP64.  The difference
-    must stay within 5% of what the closure changes."""
-    say("case: closure vs oracle, eps", eps)
+    must stay within 5% of what the closure changes.  Default launch (one-step
+    kernels and the correction pass) and the two- and three-step kernels with
+    the network inside."""
+    say("case: closure vs oracle, eps", eps, "launch", launch)
     n, steps, theta = 96, 120, 0.02
     case = W.single_vortex_case(n, eps=eps, U=0.04, period_T=400.0)
     phi0 = W.circle(n, eps)
     w = closure_params(5, 0.02)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+    if launch:
+        sim.set_launch(*launch)
     sim.set_closure(w, theta=theta)
     sim.step(steps)
     got = sim.phi()
@@ -76,11 +81,14 @@ def test_closure_matches_oracle(gpu_lib, eps):
     assert np.linalg.norm(got - ref_cl) <= 0.05 * effect
 
 
-def test_closure_keeps_mass(gpu_lib):
-    say("case: closure mass")
+@pytest.mark.parametrize("launch", [None, (224, 40, 4)])
+def test_closure_keeps_mass(gpu_lib, launch):
+    say("case: closure mass, launch", launch)
     n = 128
     case = W.single_vortex_case(n, eps=0.5, U=0.02, period_T=1024.0)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, W.circle(n, 0.5))
+    if launch:
+        sim.set_launch(*launch)
     sim.set_closure(closure_params(7, 0.05), theta=0.02)
     m0 = sim.mass()
     sim.step(300)
@@ -129,19 +137,25 @@ def test_extraction_matches_oracle(gpu_lib):
     assert np.allclose(Ya[:, 1], np.stack([-Yg[:, 1], Yg[:, 0]], 1))
 
 
-def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib):
+@pytest.mark.parametrize("nx,ny", [(200, 200), (150, 97)])
+def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib, nx, ny):
     """The band list is built with atomics (its order varies), but every listed
-    node is corrected independently, so launch shapes, variants and graph
-    replay give identical results."""
-    say("case: closure launch shapes and graph replay")
-    n = 200
-    case = W.single_vortex_case(n, eps=1.0, U=0.04, period_T=400.0)
-    phi0 = W.circle(n, 1.0)
+    node is corrected independently, so launch shapes and graph replay give
+    identical results; the two- and three-step kernels, which run the network
+    inside their stages (marching odd strips in the mirrored frame), equal
+    the one-step kernels with the correction pass bit for bit (40 steps: 13
+    three-step launches and one single step, or 20 two-step launches)."""
+    say("case: closure launch shapes and graph replay", nx, ny)
+    case = W.single_vortex_case(nx, eps=1.0, U=0.04, period_T=400.0)
+    case["ny"] = ny
+    phi0 = W.circle(nx, 1.0, ny=ny)
     w = closure_params(5, 0.05)
     base = None
-    # (the two-step variant runs one-step launches while the closure is on)
+    # (tile widths other than 128, 160, 192 and 224 run the closure's
+    # multi-step launches at 224 columns)
     for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8), ((128, 16, 3), 0),
-                          ((256, 32, 3), 6), ((64, 16, 4), 0)):
+                          ((256, 32, 3), 6), ((64, 16, 4), 0), ((224, 40, 4), 0), ((160, 9, 4), 0), ((192, 13, 4), 6),
+                          ((224, 8, 3), 0), ((128, 200, 4), 0)):
         sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
         sim.set_launch(*launch)
         if graph:

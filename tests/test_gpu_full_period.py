@@ -1,0 +1,95 @@
+"""Full-length and full-size runs through the C ABI against the FP64 oracle.
+
+* The paper's own set-up over its full period T = 6 L/U0 = 30 000 steps
+  (Sec. 3) in FP64, against the oracle's phi(T) (tests/golden/
+  make_preset_oracle.py), bounded by twice the oracle's response to one ulp of
+  phi0 at the saturated nodes.
+* The 8192^2 benchmark grid in the benchmark's launch (224-column tiles,
+  strips of 40 rows, three steps per launch), FP32 and both 16-bit forms:
+  sampled windows against the oracle's padded-window run.
+"""
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import lib as O
+from paper_2203_05230_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+BENCH_LAUNCH = (224, 40, 4)  # bx, strip rows, LBAC_KERNEL_FUSED3
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def rel_l2(a, b):
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+@pytest.mark.parametrize("eps_paper", [3.0, 1.5])
+def test_paper_preset_full_period_fp64_against_oracle(gpu_lib, eps_paper):
+    z = np.load(os.path.join(GOLDEN, "preset_oracle_eps_paper%g.npz" % eps_paper))
+    c = W.paper_vortex_case(eps_paper)
+    steps = int(c["steps"])
+    assert int(z["steps"]) == steps == 30000
+    say("case: paper preset eps_paper", eps_paper, "FP64,", steps, "steps")
+    phi0 = W.initial_field(c)
+    ref = z["phi"]
+    sim = gpu_lib.Simulation({**c, "precision": "f64"}, phi0)
+    sim.set_graph_chunk(1000)
+    m0 = sim.mass()
+    sim.step(steps)
+    phi = sim.phi()
+    mass = sim.mass()
+    sim.close()
+    m = np.abs(ref) > 1e-8
+    err = rel_l2(phi[m], ref[m])
+    say("  rel L2 on resolved nodes %.3e; oracle response to one ulp of the bulk %.3e; mass drift %.1e" %
+        (err, float(z["ulp_response"]), abs(mass - m0) / m0))
+    # over the full period the response saturates: the one-ulp change and any
+    # other rounding difference in the saturated bulk move phi(T) by the same
+    # amount, so the bound is twice that response
+    assert err <= 2.0 * float(z["ulp_response"])
+    # FP64 conservation: a few roundings per node and step at most
+    assert abs(mass - m0) / m0 <= 4 * steps * 2.0**-52
+    assert abs(mass - float(z["massT"])) / float(z["massT"]) <= 4 * steps * 2.0**-52
+
+
+# Each three-step launch rounds the stored shifted populations (|g_i| below
+# about 0.01 on these fields) to the format's unit roundoff u once; phi at a
+# node is the sum of nine of them, so a launch moves it by at most 9 * 0.01 * u,
+# and 16 steps are six launches (five of three steps, one of one step).
+@pytest.mark.parametrize("prec,bound", [("f32", 2e-6), ("f32_f16store", 2e-6 + 6 * 9 * 0.01 * 2.0**-11),
+                                        ("f32_bf16store", 2e-6 + 6 * 9 * 0.01 * 2.0**-8)])
+def test_full_size_8192_benchmark_launch_sampled(gpu_lib, prec, bound):
+    n, steps = 8192, 16
+    say("case: 8192x8192", prec, steps, "steps, launch", BENCH_LAUNCH, "sampled windows")
+    case = W.single_vortex_case(n, eps=1.0, period_T=4096.0)
+    phi0 = W.circle(n, 1.0)
+    sim = gpu_lib.Simulation({**case, "precision": prec}, phi0)
+    sim.set_launch(*BENCH_LAUNCH)
+    assert sim.steps_per_launch() == 3
+    m0 = sim.mass()
+    sim.step(steps)
+    m1 = sim.mass()
+    phi = sim.phi()
+    sim.close()
+    assert abs(m1 - m0) / m0 <= 1e-6
+    p = O.Params(n, n, eps=1.0, tau=0.8, delta=1e-10, vel_kind=O.VEL_VORTEX, U=0.02, period_T=4096.0)
+    # the interface (circle of radius 1228.8 at (4096, 6144)) at several angles,
+    # the bulk, the periodic corners and an edge
+    wins = [(4096 - 8, 6144 + 1229 - 8), (4096 + 1229 - 8, 6144 - 8), (4096 - 1229 - 8, 6144 - 8),
+            (4096 + 869 - 8, 6144 - 869 - 8), (2900, 6144 - 8), (0, 0), (8192 - 8, 8192 - 8), (100, 4000)]
+    worst = 0.0
+    for x0, y0 in wins:
+        ref = O.run_window(p, phi0, x0, y0, 16, 16, steps)
+        got = phi[np.ix_((y0 + np.arange(16)) % n, (x0 + np.arange(16)) % n)]
+        worst = max(worst, float(np.max(np.abs(got - ref))))
+    say("  worst |dphi| over the windows %.3e (bound %.3e)" % (worst, bound))
+    assert worst <= bound

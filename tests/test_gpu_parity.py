@@ -334,7 +334,7 @@ def test_full_size_8192_fp32_sampled(gpu_lib):
     case = W.single_vortex_case(n, eps=1.0, period_T=4096.0)
     phi0 = W.circle(n, 1.0)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
-    sim.autotune(12)  # the same selection the benchmark makes
+    sim.autotune(12)  # the selection an autotuned run makes (the benchmark's launch: test_gpu_full_period)
     say("  launch", sim.get_launch())
     m0 = sim.mass()
     sim.step(steps)
