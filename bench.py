@@ -303,6 +303,39 @@ def closure_leg(lbac, torch, case, phi0, steps, theta=0.02, launch=None):
                                    mlups=round(n / (ms1 * 1e-3) / 1e6, 1)))
 
 
+def train_leg(lbac, torch, steps, batch=4096):
+    """One Adam step of the closure network's training (forward, backward,
+    gradient and update kernels) on a seeded synthetic batch of `batch`
+    stencils (inputs uniform in [0, 1], targets normal with deviation 0.05),
+    the batch size of the closure's training: time per step from HIP events
+    over `steps` steps after 5 untimed ones."""
+    from paper_2203_05230_amd import closure as CL
+
+    rng = np.random.default_rng(1)
+    X = torch.from_numpy(rng.uniform(0.0, 1.0, (batch, 25)).astype(np.float32)).cuda()
+    Y = torch.from_numpy(rng.normal(0.0, 0.05, (batch, 2)).astype(np.float32)).cuda()
+    stream = torch.cuda.Stream()
+    torch.cuda.set_stream(stream)
+    net = lbac.Mlp(CL.init_weights(3), stream=stream.cuda_stream)
+    for _ in range(5):
+        net.train_step(X.data_ptr(), Y.data_ptr(), batch, 1e-3)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(steps):
+        net.train_step(X.data_ptr(), Y.data_ptr(), batch, 1e-3)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    us = ev0.elapsed_time(ev1) / steps * 1e3
+    loss = net.train_step(X.data_ptr(), Y.data_ptr(), batch, 1e-3, want_loss=True)
+    torch.cuda.set_stream(torch.cuda.default_stream())
+    # FP32 matrix work of one step: forward 2 (25 * 64 + 64 * 64 + 64 * 2)
+    # per sample, backward about twice that
+    flop = 3 * 2 * (25 * 64 + 64 * 64 + 64 * 2) * batch
+    return dict(batch=batch, steps=steps, us_per_step=round(us, 2), samples_per_s=round(batch / (us * 1e-6), 1),
+                fp32_tflops=round(flop / (us * 1e-6) / 1e12, 3), loss=loss)
+
+
 def c2_leg(lbac, torch, W, n, steps):
     """The 1024^2 single vortex (R = 0.15 n at (0.5 n, 0.75 n), tau 0.8, U
     0.02, period = `steps`) at eps 0.5 and 1 with FP32, FP16 and BF16 shifted
@@ -496,6 +529,7 @@ def main():
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-strip", type=int, default=0, help="strip height of the batched leg (default: autotune)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
+    ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the closure-training leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
     ap.add_argument("--c1-steps", type=int, default=2000, help="steps (= period) of the 64^2 FP64 run (0: skip)")
     ap.add_argument("--c2-steps", type=int, default=16384,
@@ -607,6 +641,10 @@ def main():
         print("bench: closure", file=sys.stderr, flush=True)
         closure = closure_leg(lbac, torch, case, phi0, args.closure_steps)
         closure["vs_plain_mlups"] = round(closure["mlups"] / mlups, 4)
+    training = None
+    if args.train_steps > 0:
+        print("bench: closure training", file=sys.stderr, flush=True)
+        training = train_leg(lbac, torch, args.train_steps)
     d3 = None
     c1 = None
     if args.c1_steps > 0:
@@ -665,6 +703,7 @@ def main():
         "forms": forms,
         "batched": batched,
         "closure": closure,
+        "closure_training": training,
         "c1_64": c1,
         "c2_1024": c2,
         "d3q19": d3,

@@ -308,7 +308,10 @@ const char* lbac_last_error(lbac_ctx* h);
  * outer, dx = -2..2 inner) to a correction (cx, cy) of the sharpening flux
  * S n of Eq. (11).  Parameters: LBAC_MLP_NPARAM FP32 values laid out as
  * W1[64][25], b1[64], W2[64][64], b2[64], W3[2][64], b3[2].  Training runs
- * on the GPU in FP32 (hand-written forward, backward, Adam kernels); loss
+ * on the GPU in FP32 (hand-written kernels on the FP32 matrix cores: one
+ * wavefront per 16 samples for the forward and backward passes and its share
+ * of the gradient, then a fixed-order sum of the shares and the Adam update,
+ * so a training run is reproducible); loss
  * L = (1/B) sum_samples sum_outputs (out - y)^2.  Sample arrays are device
  * memory owned by the caller: x_dev is batch*25 floats, y_dev and out_dev
  * batch*2 floats, row-major. */
