@@ -169,6 +169,40 @@ def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib, nx, ny):
         assert np.array_equal(phi, base), (launch, graph)
 
 
+def test_closure_full_size_benchmark_launch(gpu_lib):
+    """The benchmark grid (8192^2, eps 1) with the closure, 12 steps: the
+    three-step kernel with the network inside, in the benchmark's launch,
+    equals the one-step path bit for bit, and 16x16 windows on the interface
+    (top, right, diagonal) agree with the oracle's padded-window run with the
+    same BF16-rounded weights to within 5% of what the closure changes there."""
+    n, steps, theta = 8192, 12, 0.02
+    say("case: closure at 8192^2, %d steps" % steps)
+    case = W.single_vortex_case(n, eps=1.0, period_T=4096.0)
+    phi0 = W.circle(n, 1.0)
+    w = closure_params(5, 0.05)
+    phis = []
+    for launch in ((224, 40, 4), (256, 40, 2)):
+        sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
+        sim.set_launch(*launch)
+        sim.set_closure(w, theta=theta)
+        sim.step(steps)
+        phis.append(sim.phi())
+        sim.close()
+    assert np.array_equal(phis[0], phis[1])
+    p_cl = oparams(n, 1.0, 0.02, 4096.0, mlp=bf16_round(w), theta=theta)
+    p_plain = oparams(n, 1.0, 0.02, 4096.0)
+    got, ref, plain = [], [], []
+    for x0, y0 in ((4096 - 8, 6144 + 1229 - 8), (4096 + 1229 - 8, 6144 - 8), (4096 + 869 - 8, 6144 + 869 - 8)):
+        got.append(phis[0][y0:y0 + 16, x0:x0 + 16])
+        ref.append(O.run_window(p_cl, phi0, x0, y0, 16, 16, steps))
+        plain.append(O.run_window(p_plain, phi0, x0, y0, 16, 16, steps))
+    got, ref, plain = np.array(got), np.array(ref), np.array(plain)
+    effect = np.linalg.norm(ref - plain)
+    say("  closure effect %.3e, GPU vs oracle %.3e" % (effect, np.linalg.norm(got - ref)))
+    assert effect > 1e-3
+    assert np.linalg.norm(got - ref) <= 0.05 * effect
+
+
 def test_closure_rejected_for_batch_instances(gpu_lib):
     say("case: closure on a batch instance")
     case = W.single_vortex_case(64, eps=1.0)
