@@ -244,7 +244,10 @@ typedef struct lbac_batch lbac_batch;
 /* params[k], phi0[k] (host, ny*nx doubles): instance k, k < count.  The stream
  * of params[0] (or a private one) is used for the whole batch; allocators are
  * honoured per instance.  Errors as lbac_init, plus LBAC_EINVAL for a
- * precision other than LBAC_F32 or a model other than LBAC_MODEL_IMPROVED. */
+ * precision other than LBAC_F32, a model other than LBAC_MODEL_IMPROVED, or
+ * an instance whose nine population planes take 2^31 bytes or more (about
+ * 7700 x 7700 nodes; such a lattice fills the device by itself and belongs
+ * to lbac_step). */
 int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_t count, lbac_batch** out);
 int lbac_batch_free(lbac_batch* b);
 
@@ -292,7 +295,9 @@ const char* lbac_batch_last_error(lbac_batch* b);
  * check detects what goes wrong with them).
  * *verdict: 0 = every slot ran and every slot read only tiles holding the
  * previous pass while no running slot wrote them; 1 = deadlock (no workgroup
- * could act before the end); 2 = a read or write hazard.  *slots_run (may be
+ * could act before the end); 2 = a read or write hazard; 3 = the kernel's
+ * slot lookup maps a slot to another (pass, item) than the slot table
+ * defines.  *slots_run (may be
  * NULL) gets the number of slots run.  LBAC_EINVAL for bad sizes. */
 int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_t* nsteps, int32_t count,
                               int32_t strip_h, int32_t workers, int32_t protocol, uint64_t seed, int32_t* verdict,

@@ -121,6 +121,7 @@ struct Slots {
     std::vector<int32_t> entry;       // 2 per entry: instance, pass
     std::vector<int64_t> start;       // entries + 1
     std::vector<int32_t> first_item;  // instances + 1
+    std::vector<int32_t> coarse;      // (slots >> kBatchCoarseBits) + 2
 };
 
 void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, Slots& sl) {
@@ -151,6 +152,17 @@ void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& pa
         else
             heap.pop_back();
     }
+    // coarse index: the entry holding slot c << kBatchCoarseBits
+    const int32_t n = (int32_t)(sl.entry.size() / 2);
+    const int64_t total = sl.start.back();
+    sl.coarse.assign((size_t)((total >> kBatchCoarseBits) + 2), n - 1);
+    int32_t e = 0;
+    for (size_t c = 0; c < sl.coarse.size(); ++c) {
+        const int64_t T = (int64_t)c << kBatchCoarseBits;
+        if (T >= total) break;
+        while (sl.start[e + 1] <= T) ++e;
+        sl.coarse[c] = e;
+    }
 }
 
 }  // namespace
@@ -175,6 +187,7 @@ struct lbac_batch {
     BatchItem* d_items = nullptr;
     int32_t* d_entry[2] = {nullptr, nullptr};
     int64_t* d_start[2] = {nullptr, nullptr};
+    int32_t* d_coarse[2] = {nullptr, nullptr};
     int32_t* d_first = nullptr;   // first item of each instance
     int32_t* d_done = nullptr;
     BatchCtl* d_ctl = nullptr;
@@ -184,6 +197,7 @@ struct lbac_batch {
     int32_t* h_nent = nullptr;    // pinned
     int cap_items = 0;
     int64_t cap_ent[2] = {0, 0};
+    int64_t cap_coarse[2] = {0, 0};
     hipGraphExec_t gexec = nullptr;
     int64_t g_slots[2] = {-1, -1};  // grids the captured graph was made for
     std::string err;
@@ -218,9 +232,12 @@ void free_tables(lbac_batch* b) {
     for (int L = 0; L < 2; ++L) {
         (void)hipFree(b->d_entry[L]);
         (void)hipFree(b->d_start[L]);
+        (void)hipFree(b->d_coarse[L]);
         b->d_entry[L] = nullptr;
         b->d_start[L] = nullptr;
+        b->d_coarse[L] = nullptr;
         b->cap_ent[L] = 0;
+        b->cap_coarse[L] = 0;
     }
 }
 
@@ -244,10 +261,10 @@ void release(lbac_batch* b) {
     if (b->own_stream && b->stream) (void)hipStreamDestroy(b->stream);
 }
 
-// Device tables large enough for the items and for the entries of each
-// launch; a reallocation invalidates the captured graph (its kernel
-// arguments).
-int ensure_tables(lbac_batch* b, const int64_t nent[2]) {
+// Device tables large enough for the items and for the entries and coarse
+// index of each launch; a reallocation invalidates the captured graph (its
+// kernel arguments).
+int ensure_tables(lbac_batch* b, const int64_t nent[2], const int64_t ncoarse[2]) {
     if (b->cap_items < b->nitems) {
         drop_graph(b);
         (void)hipFree(b->d_items);
@@ -273,6 +290,16 @@ int ensure_tables(lbac_batch* b, const int64_t nent[2]) {
             BHIP(b, hipMalloc(&b->d_start[L], sizeof(int64_t) * c));
             b->cap_ent[L] = c;
         }
+    for (int L = 0; L < 2; ++L)
+        if (b->cap_coarse[L] < ncoarse[L]) {
+            drop_graph(b);
+            (void)hipFree(b->d_coarse[L]);
+            b->d_coarse[L] = nullptr;
+            b->cap_coarse[L] = 0;
+            const int64_t c = std::max<int64_t>(ncoarse[L], 64);
+            BHIP(b, hipMalloc(&b->d_coarse[L], sizeof(int32_t) * c));
+            b->cap_coarse[L] = c;
+        }
     return LBAC_OK;
 }
 
@@ -294,7 +321,7 @@ int capture(lbac_batch* b) {
     auto launch_slots = [&](int L) {
         for (int64_t left = b->nslots[L]; left > 0 && e == hipSuccess;) {
             const int64_t g = std::min<int64_t>(left, kBatchMaxGrid);
-            const BatchSlots sl{b->d_entry[L], b->d_start[L], b->d_first, b->d_nent + L};
+            const BatchSlots sl{b->d_entry[L], b->d_start[L], b->d_first, b->d_nent + L, b->d_coarse[L]};
             if (L == 0)
                 hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
                                    b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
@@ -359,14 +386,15 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
     Slots sl[2];
     build_slots(b->items, pf, sl[0]);
     build_slots(b->items, pr, sl[1]);
-    int64_t nent[2];
+    int64_t nent[2], ncoarse[2];
     for (int L = 0; L < 2; ++L) {
         nent[L] = (int64_t)sl[L].entry.size() / 2;
+        ncoarse[L] = (int64_t)sl[L].coarse.size();
         b->nslots[L] = sl[L].start.back();
         if (nent[L] > INT32_MAX || b->nslots[L] > 64 * kBatchMaxGrid)
             return bfail(b, LBAC_EINVAL, "too many slots");
     }
-    int rc = ensure_tables(b, nent);
+    int rc = ensure_tables(b, nent, ncoarse);
     if (rc != LBAC_OK) return rc;
     std::vector<BatchItem> di(b->nitems);
     for (int i = 0; i < b->nitems; ++i) {
@@ -408,6 +436,8 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
             BHIP(b, hipMemcpyAsync(b->d_entry[L], sl[L].entry.data(), sizeof(int32_t) * sl[L].entry.size(),
                                    hipMemcpyHostToDevice, b->stream));
         BHIP(b, hipMemcpyAsync(b->d_start[L], sl[L].start.data(), sizeof(int64_t) * sl[L].start.size(),
+                               hipMemcpyHostToDevice, b->stream));
+        BHIP(b, hipMemcpyAsync(b->d_coarse[L], sl[L].coarse.data(), sizeof(int32_t) * sl[L].coarse.size(),
                                hipMemcpyHostToDevice, b->stream));
     }
     rc = capture(b);
@@ -451,6 +481,9 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
     for (int k = 0; k < count; ++k) {
         if (params[k].precision != LBAC_F32 || params[k].model != LBAC_MODEL_IMPROVED) return LBAC_EINVAL;
         if (!phi0[k]) return LBAC_EINVAL;
+        // nine FP32 planes of at least nx * ny values each must stay below
+        // 2^31 bytes (checked exactly, padding included, once allocated)
+        if ((int64_t)params[k].nx * params[k].ny * 9 * (int64_t)sizeof(float) >= (int64_t)0x7FFFFFFF) return LBAC_EINVAL;
     }
     lbac_batch* b = new (std::nothrow) lbac_batch();
     if (!b) return LBAC_ENOMEM;
@@ -475,6 +508,9 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         if (rc != LBAC_OK) return bail(rc);
         c->in_batch = true;
         b->inst[k] = c;
+        // the batch kernel addresses the nine planes of a buffer through one
+        // buffer resource with 32-bit offsets below 2^31
+        if (c->plane_stride * 9 * (int64_t)sizeof(float) >= (int64_t)0x7FFFFFFF) return bail(LBAC_EINVAL);
     }
     int per_cu = 0, cus = 0, khz = 0;
     // the default grid: as many workgroups as the device keeps resident (the
@@ -599,6 +635,7 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
     std::vector<int64_t> ver[2] = {std::vector<int64_t>(n, -1), std::vector<int64_t>(n, -3)};
     std::mt19937_64 rng(seed);
     *verdict = 0;
+    if (slots_run) *slots_run = 0;
     int64_t ran = 0;
     struct Slot {
         int32_t p, id;
@@ -611,7 +648,18 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
         build_slots(items, passes, sl);
         const int32_t nent = (int32_t)(sl.entry.size() / 2);
         const int64_t total = sl.start.back();
-        const BatchSlots tab{sl.entry.data(), sl.start.data(), sl.first_item.data(), &nent};
+        const BatchSlots tab{sl.entry.data(), sl.start.data(), sl.first_item.data(), &nent, sl.coarse.data()};
+        // the kernel's slot lookup (coarse index, then a search) against the
+        // entry list walked slot by slot
+        for (int64_t T = 0, e = 0; T < total && protocol != 2; ++T) {
+            while (sl.start[e + 1] <= T) ++e;
+            int32_t p = -1;
+            const int32_t id = batch_slot_item(tab, T, nent, p);
+            if (p != sl.entry[2 * e + 1] || id != sl.first_item[sl.entry[2 * e]] + (int32_t)(T - sl.start[e])) {
+                *verdict = 3;
+                return LBAC_OK;
+            }
+        }
         int32_t npass = 0;
         for (int64_t v : passes) npass = std::max<int32_t>(npass, (int32_t)v);
         // protocol 2: fixed item lists of 2 * workers workgroups (items dealt

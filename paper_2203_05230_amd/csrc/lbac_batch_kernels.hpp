@@ -101,17 +101,24 @@ __device__ __forceinline__ bool batch_wait(const int32_t* done, const int32_t* d
 // pass of its instance (the order stays a topological order of the
 // dependencies).  start[e] is the first slot number of entry e, start[n] the
 // slot count; the items of an instance are the contiguous ids first_item[k] ..
-// first_item[k + 1] - 1.
+// first_item[k + 1] - 1.  coarse[c] is the entry that holds slot c * 2^B
+// (B = kBatchCoarseBits; n - 1 where that slot does not exist), so the entry
+// of a slot is found among the few entries between two coarse values instead
+// of by a search over all of them, a chain of dependent loads as long as
+// log2 n that every workgroup runs before its wait.
+constexpr int kBatchCoarseBits = 6;
 struct BatchSlots {
     const int32_t* entry;       // 2 per entry: instance, pass
     const int64_t* start;       // n + 1 values
     const int32_t* first_item;  // count + 1 values
     const int32_t* nentries;    // n (device memory: a captured graph's arguments stay valid)
+    const int32_t* coarse;      // (start[n] >> kBatchCoarseBits) + 2 values
 };
 
 // Maps slot number T of a launch (T < start[n]) to its pass p and item.
 __host__ __device__ inline int32_t batch_slot_item(const BatchSlots& s, int64_t T, int32_t n, int32_t& p) {
-    int32_t lo = 0, hi = n;  // start[lo] <= T < start[hi]
+    const int64_t c = T >> kBatchCoarseBits;
+    int32_t lo = s.coarse[c], hi = s.coarse[c + 1] + 1;  // start[lo] <= T < start[hi]
     while (hi - lo > 1) {
         const int32_t mid = (lo + hi) / 2;
         if (s.start[mid] <= T) lo = mid;

@@ -1,6 +1,7 @@
 // Device code of the lbac library: the fused collide-and-stream step of the
 // accurate interface-capturing LB scheme (H. Liang, arXiv:2203.05230,
-// Sec. 2.2, Eq. (9)-(13)) and the small kernels around it (initialisation,
+// Sec. 2.2, Eq. (9)-(13)), its multi-step form, the learned closure's
+// network inference, and the small kernels around them (initialisation,
 // phi, reductions).
 //
 // Storage.  The state between steps is the post-collision population
@@ -10,7 +11,8 @@
 // planes hold g_i = f*_i - w_i phi* for i = 1..8 in 16 bits plus phi* in FP32,
 // with g_0 = -(g_1 + .. + g_8), so the nine populations always sum to phi*.
 //
-// Step kernel dataflow (one launch per step).  A block owns a strip of bx
+// One-step kernel dataflow (the multi-step kernel further below chains two
+// or three such steps through LDS).  A block owns a strip of bx
 // columns and strip_h rows and marches up it one row per iteration.  At
 // iteration `it` it loads lattice row r of every plane (own columns plus a
 // two-column halo) into a three-row LDS ring, forms phi (Eq. (12)) and psi
@@ -481,31 +483,37 @@ struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
 // producer only waits for its own stores to complete before it publishes,
 // and a consumer that has seen the counter reads current values, with no
 // writeback or invalidation of the whole L2.
+//
+// One buffer resource per population buffer, with the plane of population q
+// selected by the scalar offset m(q) * plane bytes (m(q): q or its mirror
+// image): eight scalar registers for the two buffers instead of four per
+// plane and buffer, which had made the tile function spill scalar registers
+// into vector lanes (a tenth more vector instructions per row).  Requires
+// the nine planes of a buffer to span less than 2^31 bytes, so that every
+// in-range offset, the scalar offset included, stays below the resource's
+// range and the dropped stores' offset above it; the batch's set-up rejects
+// larger instances.
 struct IoCoherent {
     static constexpr bool kShifted = false;
     static constexpr int kSc1 = 16;  // cache-policy operand: sc1 (device scope)
-    const char* s[9];
-    char* d[9];
-    __device__ __forceinline__ IoCoherent(const StepArgs& a, bool mirror) {
+    __amdgpu_buffer_rsrc_t sr, dr;
+    uint32_t pb[9];  // byte offset of the plane read and written for population q
+    __device__ __forceinline__ IoCoherent(const StepArgs& a, bool mirror)
+        : sr(plane_rsrc(const_cast<void*>(a.src))), dr(plane_rsrc(a.dst)) {
+        const uint32_t ps = (uint32_t)a.plane_stride * 4u;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) {
-            const int m = mirror ? mirror_q(q) : q;
-            s[q] = static_cast<const char*>(a.src) + (size_t)m * a.plane_stride * sizeof(float);
-            d[q] = static_cast<char*>(a.dst) + (size_t)m * a.plane_stride * sizeof(float);
-        }
+        for (int q = 0; q < 9; ++q) pb[q] = (uint32_t)(mirror ? mirror_q(q) : q) * ps;
     }
     __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
         const uint32_t b = off * 4u;
 #pragma unroll
         for (int q = 0; q < 9; ++q)
-            v[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(
-                                                 plane_rsrc(const_cast<char*>(s[q])), (int)b, 0, kSc1));
+            v[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sr, (int)b, (int)pb[q], kSc1));
     }
     __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float /*phi*/) const {
         const uint32_t b = on ? off * 4u : kDropOffset;
 #pragma unroll
-        for (int q = 0; q < 9; ++q)
-            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), plane_rsrc(d[q]), (int)b, 0, kSc1);
+        for (int q = 0; q < 9; ++q) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), dr, (int)b, (int)pb[q], kSc1);
     }
 };
 

@@ -90,6 +90,21 @@ def test_bad_sizes_rejected():
         assert L.lbac_init(C.byref(p), phi0.ctypes.data_as(C.POINTER(C.c_double)), C.byref(h)) == lbac.LBAC_EINVAL
 
 
+def test_batch_rejects_instances_beyond_its_addressing():
+    """The batch kernel reaches the nine planes of an instance through one
+    buffer resource with offsets below 2^31 bytes: a larger instance is
+    refused before anything is allocated."""
+    L = lbac.load()
+    ps = (lbac.lbac_params * 2)(lbac.make_params(128, 128, precision="f32"),
+                                lbac.make_params(7800, 7800, precision="f32"))
+    phi0 = np.zeros(16)
+    ptr = phi0.ctypes.data_as(C.POINTER(C.c_double))
+    ptrs = (C.POINTER(C.c_double) * 2)(ptr, ptr)
+    h = C.c_void_p()
+    assert L.lbac_batch_init(ps, ptrs, 2, C.byref(h)) == lbac.LBAC_EINVAL
+    assert not h.value
+
+
 def test_null_arguments_rejected():
     L = lbac.load()
     p = lbac.make_params(16, 16)
