@@ -228,14 +228,17 @@ void* lbac_stream(lbac_ctx* h);
  * column tile of at most 224 columns, strip of rows) items.  An item takes
  * three steps per pass (the populations between them kept in LDS, as with
  * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes).  The
- * (pass, item) slots are numbered pass by pass; the launch has one workgroup
- * per slot and each takes the next slot number from an atomic counter when
- * it starts, then waits, through per-item progress counters, for the
- * previous pass of its own item and of the items its read region overlaps
- * (no grid-wide barrier), so instances retire independently.  Every slot
- * waited for has a smaller number and belongs to a workgroup that has
- * started, so the schedule progresses whatever number of workgroups the
- * device keeps resident.  Every instance uses FP32
+ * instances are dealt to eight classes of about equal work (one per XCD, so
+ * neighbouring tiles share that XCD's L2), and the (pass, item) slots of a
+ * class are numbered pass by pass; the launch has one workgroup per slot and
+ * each takes the next slot number of its class (blockIdx mod 8; once that
+ * class is used up, of another) from the class's atomic counter when it
+ * starts, then waits, through per-item progress counters, for the previous
+ * pass of its own item and of the items its read region overlaps (no
+ * grid-wide barrier), so instances retire independently.  Every slot waited
+ * for is of the same class, has a smaller number and belongs to a workgroup
+ * that has started, so the schedule progresses whatever number of
+ * workgroups the device keeps resident.  Every instance uses FP32
  * collide and storage and the improved model; results are bitwise those of
  * lbac_step on the same instance.  A wait that exceeds the time-out makes
  * every workgroup exit and the run return LBAC_EDEVICE. */
@@ -288,8 +291,9 @@ const char* lbac_batch_last_error(lbac_batch* b);
  * instances of nx[k] x ny[k] nodes advanced by nsteps[k] steps with strips of
  * strip_h rows, and runs a slot protocol on the CPU with `workers`
  * workgroups running at once and their actions interleaved at random (seed).
- * protocol 0: the library's (pass-major slot numbers from one counter, waits
- * for the previous pass of the dependencies); 1: the same without the waits;
+ * protocol 0: the library's (pass-major slot numbers from per-class
+ * counters, waits for the previous pass of the dependencies); 1: the same
+ * without the waits;
  * 2: fixed item lists of 2 * workers workgroups, each walked pass by pass, of
  * which only `workers` run at once (the two others exist to show that the
  * check detects what goes wrong with them).

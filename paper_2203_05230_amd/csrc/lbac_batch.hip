@@ -3,9 +3,9 @@
 // in lbac_batch_kernels.hpp for the slot schedule and its dependency rule).
 //
 // Host side: the work list of (instance, column tile, strip) items with their
-// dependency lists, the pass-major slot tables of the two launches, graph
-// capture of reset -> full passes -> reset -> one-step passes -> time
-// advance, and an autotuner over the strip height and the workgroup count.
+// dependency lists, the classes and pass-major slot tables of the two
+// launches, graph capture of reset -> full passes -> reset -> one-step passes
+// -> time advance, and an autotuner over the strip height.
 // It also exports a host-only check of the schedule (lbac_batch_schedule_check)
 // that runs the kernel's slot protocol on the CPU with a bounded number of
 // concurrently running workgroups.
@@ -29,8 +29,8 @@ namespace {
 
 // Rows per strip at least (a shorter last strip of an instance is allowed).
 constexpr int kBatchMinStrip = kBatchGrow + 2;
-// Workgroups of one batch launch at most: (2^32 - 1) work-items.
-constexpr int64_t kBatchMaxGrid = 0xFFFFFFFFll / kBatchThreads;
+// Slots of one batch launch at most (bounds the host tables).
+constexpr int64_t kBatchMaxSlots = int64_t(1) << 36;
 
 struct Geometry {
     int nx, ny;
@@ -112,19 +112,41 @@ bool build_items(const std::vector<Geometry>& geo, int strip_h, std::vector<Item
     return true;
 }
 
-// Slot tables of a launch (see BatchSlots): the entries (instance, pass) in
-// the order of the fraction of its run the instance has done after the pass,
-// (p + 1) / passes[k], ties by instance (a merge of the instances' pass
-// sequences; the fractions are compared exactly in integers), the first slot
-// of each entry, and the first item of each instance.
+// Classes of the instances (see batch_kernel): instances dealt largest work
+// first (node-updates of the run, ties by index) to the class with the least
+// work so far (ties: the lowest class).
+std::vector<int> assign_classes(const std::vector<Geometry>& geo, const int64_t* nsteps) {
+    const int count = (int)geo.size();
+    std::vector<int> order(count), cls(count, 0);
+    std::vector<double> work(count);
+    for (int k = 0; k < count; ++k) work[k] = (double)geo[k].nx * geo[k].ny * (double)nsteps[k];
+    std::iota(order.begin(), order.end(), 0);
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work[a] > work[b]; });
+    double load[kBatchClasses] = {};
+    for (int k : order) {
+        const int c = (int)(std::min_element(load, load + kBatchClasses) - load);
+        cls[k] = c;
+        load[c] += work[k];
+    }
+    return cls;
+}
+
+// Slot tables of a launch (see BatchSlots): per class, in class order, the
+// entries (instance, pass) of the class's instances in the order of the
+// fraction of its run the instance has done after the pass, (p + 1) /
+// passes[k], ties by instance (a merge of the instances' pass sequences; the
+// fractions are compared exactly in integers); the first slot of each entry
+// and of each class, and the first item of each instance.
 struct Slots {
     std::vector<int32_t> entry;       // 2 per entry: instance, pass
     std::vector<int64_t> start;       // entries + 1
     std::vector<int32_t> first_item;  // instances + 1
     std::vector<int32_t> coarse;      // (slots >> kBatchCoarseBits) + 2
+    std::vector<int64_t> cls;         // kBatchClasses + 1
 };
 
-void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, Slots& sl) {
+void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& passes, const std::vector<int>& cls_of,
+                 Slots& sl) {
     const int count = (int)passes.size();
     sl.first_item.assign(count + 1, 0);
     for (const ItemH& it : items) sl.first_item[it.inst + 1] += 1;
@@ -135,23 +157,28 @@ void build_slots(const std::vector<ItemH>& items, const std::vector<int64_t>& pa
         const __int128 fa = (__int128)(next[a] + 1) * passes[b], fb = (__int128)(next[b] + 1) * passes[a];
         return fa != fb ? fa > fb : a > b;
     };
-    std::vector<int> heap;
-    for (int k = 0; k < count; ++k)
-        if (passes[k] > 0 && sl.first_item[k + 1] > sl.first_item[k]) heap.push_back(k);
-    std::make_heap(heap.begin(), heap.end(), later);
     sl.entry.clear();
     sl.start.assign(1, 0);
-    while (!heap.empty()) {
-        std::pop_heap(heap.begin(), heap.end(), later);
-        const int k = heap.back();
-        sl.entry.push_back(k);
-        sl.entry.push_back((int32_t)next[k]);
-        sl.start.push_back(sl.start.back() + (sl.first_item[k + 1] - sl.first_item[k]));
-        if (++next[k] < passes[k])
-            std::push_heap(heap.begin(), heap.end(), later);
-        else
-            heap.pop_back();
+    sl.cls.assign(kBatchClasses + 1, 0);
+    for (int c = 0; c < kBatchClasses; ++c) {
+        sl.cls[c] = sl.start.back();
+        std::vector<int> heap;
+        for (int k = 0; k < count; ++k)
+            if (cls_of[k] == c && passes[k] > 0 && sl.first_item[k + 1] > sl.first_item[k]) heap.push_back(k);
+        std::make_heap(heap.begin(), heap.end(), later);
+        while (!heap.empty()) {
+            std::pop_heap(heap.begin(), heap.end(), later);
+            const int k = heap.back();
+            sl.entry.push_back(k);
+            sl.entry.push_back((int32_t)next[k]);
+            sl.start.push_back(sl.start.back() + (sl.first_item[k + 1] - sl.first_item[k]));
+            if (++next[k] < passes[k])
+                std::push_heap(heap.begin(), heap.end(), later);
+            else
+                heap.pop_back();
+        }
     }
+    sl.cls[kBatchClasses] = sl.start.back();
     // coarse index: the entry holding slot c << kBatchCoarseBits
     const int32_t n = (int32_t)(sl.entry.size() / 2);
     const int64_t total = sl.start.back();
@@ -173,7 +200,7 @@ struct lbac_batch {
     bool own_stream = false;
     std::vector<lbac_ctx*> inst;
     int strip_h = 40;   // >= kBatchMinStrip
-    int max_wgs = 0;    // workgroups the device keeps resident at once (information only)
+    int max_wgs = 0;    // workgroups the device keeps resident at once: the grid of a launch
     double ticks_per_s = 1e8;
     double timeout_s = 20.0;
     int test_stall = 0;
@@ -182,12 +209,15 @@ struct lbac_batch {
     int items_h = -1;  // strip height the item list was built for
     std::vector<ItemH> items;
     int nitems = 0;
-    int64_t nslots[2] = {0, 0};  // slots (workgroups) of the two launches of the current run
+    int64_t nslots[2] = {0, 0};  // slots of the two launches of the current run
     BatchInst* d_inst = nullptr;
     BatchItem* d_items = nullptr;
     int32_t* d_entry[2] = {nullptr, nullptr};
     int64_t* d_start[2] = {nullptr, nullptr};
     int32_t* d_coarse[2] = {nullptr, nullptr};
+    int64_t* d_cls = nullptr;     // first slot of each class, per launch (2 x (kBatchClasses + 1))
+    BatchDev* d_dev = nullptr;    // the batch launches' argument block
+    BatchDev* h_dev = nullptr;    // pinned
     int32_t* d_first = nullptr;   // first item of each instance
     int32_t* d_done = nullptr;
     BatchCtl* d_ctl = nullptr;
@@ -248,6 +278,9 @@ void release(lbac_batch* b) {
     (void)hipFree(b->d_ctl);
     (void)hipFree(b->d_nent);
     (void)hipFree(b->d_first);
+    (void)hipFree(b->d_cls);
+    (void)hipFree(b->d_dev);
+    if (b->h_dev) (void)hipHostFree(b->h_dev);
     if (b->h_ctl) (void)hipHostFree(b->h_ctl);
     if (b->h_inst) (void)hipHostFree(b->h_inst);
     if (b->h_nent) (void)hipHostFree(b->h_nent);
@@ -303,10 +336,15 @@ int ensure_tables(lbac_batch* b, const int64_t nent[2], const int64_t ncoarse[2]
     return LBAC_OK;
 }
 
-// The run as one graph; its two batch launches have one workgroup per slot,
-// so the graph is captured again when the slot counts change.
+// Workgroups of a batch launch: as many as the device keeps resident, fewer
+// if the launch has fewer slots (each workgroup takes slots until none is
+// left; a grid beyond the resident count would only add workgroups that
+// start when the slots are gone).
+int64_t batch_grid(const lbac_batch* b, int L) { return std::min<int64_t>(b->nslots[L], b->max_wgs); }
+
+// The run as one graph; it is captured again when a launch's grid changes.
 int capture(lbac_batch* b) {
-    if (b->gexec && b->g_slots[0] == b->nslots[0] && b->g_slots[1] == b->nslots[1]) return LBAC_OK;
+    if (b->gexec && b->g_slots[0] == batch_grid(b, 0) && b->g_slots[1] == batch_grid(b, 1)) return LBAC_OK;
     drop_graph(b);
     BHIP(b, hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
     const int count = (int)b->inst.size();
@@ -315,22 +353,16 @@ int capture(lbac_batch* b) {
     hipLaunchKernelGGL(batch_reset_kernel, dim3((nreset + 255) / 256), dim3(256), 0, b->stream, b->d_done, nreset,
                        b->d_ctl, 0, 1);
     hipError_t e = hipGetLastError();
-    // one workgroup per slot; a dispatch holds at most 2^32 - 1 work-items,
-    // so a launch with more slots is split into consecutive launches, all
-    // taking slot numbers from the same counter
     auto launch_slots = [&](int L) {
-        for (int64_t left = b->nslots[L]; left > 0 && e == hipSuccess;) {
-            const int64_t g = std::min<int64_t>(left, kBatchMaxGrid);
-            const BatchSlots sl{b->d_entry[L], b->d_start[L], b->d_first, b->d_nent + L, b->d_coarse[L]};
-            if (L == 0)
-                hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
-                                   b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
-            else
-                hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3((unsigned)g), dim3(kBatchThreads), 0,
-                                   b->stream, b->d_inst, b->d_items, sl, b->d_done, b->d_ctl);
-            e = hipGetLastError();
-            left -= g;
-        }
+        const int64_t g = batch_grid(b, L);
+        if (g <= 0 || e != hipSuccess) return;
+        if (L == 0)
+            hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
+                               b->stream, b->d_dev);
+        else
+            hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3((unsigned)g), dim3(kBatchThreads), 0,
+                               b->stream, b->d_dev);
+        e = hipGetLastError();
     };
     launch_slots(0);
     if (e == hipSuccess) {
@@ -353,8 +385,8 @@ int capture(lbac_batch* b) {
     e = hipGraphInstantiate(&b->gexec, g, nullptr, nullptr, 0);
     (void)hipGraphDestroy(g);
     if (e != hipSuccess) return bfail(b, LBAC_EDEVICE, std::string("batch graph instantiate: ") + hipGetErrorString(e));
-    b->g_slots[0] = b->nslots[0];
-    b->g_slots[1] = b->nslots[1];
+    b->g_slots[0] = batch_grid(b, 0);
+    b->g_slots[1] = batch_grid(b, 1);
     return LBAC_OK;
 }
 
@@ -383,15 +415,18 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
         pf[k] = nsteps[k] / kBatchS;
         pr[k] = nsteps[k] % kBatchS;
     }
+    std::vector<Geometry> geo(count);
+    for (int k = 0; k < count; ++k) geo[k] = {b->inst[k]->p.nx, b->inst[k]->p.ny};
+    const std::vector<int> cls_of = assign_classes(geo, nsteps);
     Slots sl[2];
-    build_slots(b->items, pf, sl[0]);
-    build_slots(b->items, pr, sl[1]);
+    build_slots(b->items, pf, cls_of, sl[0]);
+    build_slots(b->items, pr, cls_of, sl[1]);
     int64_t nent[2], ncoarse[2];
     for (int L = 0; L < 2; ++L) {
         nent[L] = (int64_t)sl[L].entry.size() / 2;
         ncoarse[L] = (int64_t)sl[L].coarse.size();
         b->nslots[L] = sl[L].start.back();
-        if (nent[L] > INT32_MAX || b->nslots[L] > 64 * kBatchMaxGrid)
+        if (nent[L] > INT32_MAX || b->nslots[L] > kBatchMaxSlots)
             return bfail(b, LBAC_EINVAL, "too many slots");
     }
     int rc = ensure_tables(b, nent, ncoarse);
@@ -418,13 +453,21 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
         b->h_inst[2 * k + 1].a = o;
         b->h_inst[2 * k].nsteps = b->h_inst[2 * k + 1].nsteps = nsteps[k];
     }
-    b->h_ctl->ticket[0] = b->h_ctl->ticket[1] = 0;
+    std::memset(b->h_ctl->ticket, 0, sizeof(b->h_ctl->ticket));
     b->h_ctl->timeout_ticks = (int64_t)(b->timeout_s * b->ticks_per_s);
     b->h_ctl->dry = dry ? 1 : 0;
     b->h_ctl->err = 0;
     b->h_ctl->test_stall = b->test_stall;
     b->h_nent[0] = (int32_t)nent[0];
     b->h_nent[1] = (int32_t)nent[1];
+    b->h_dev->insts = b->d_inst;
+    b->h_dev->items = b->d_items;
+    for (int L = 0; L < 2; ++L)
+        b->h_dev->slots[L] = BatchSlots{b->d_entry[L],  b->d_start[L], b->d_first, b->d_nent + L, b->d_coarse[L],
+                                        b->d_cls + L * (kBatchClasses + 1)};
+    b->h_dev->done = b->d_done;
+    b->h_dev->ctl = b->d_ctl;
+    BHIP(b, hipMemcpyAsync(b->d_dev, b->h_dev, sizeof(BatchDev), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_inst, b->h_inst, sizeof(BatchInst) * 2 * count, hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_ctl, b->h_ctl, sizeof(BatchCtl), hipMemcpyHostToDevice, b->stream));
     BHIP(b, hipMemcpyAsync(b->d_nent, b->h_nent, 2 * sizeof(int32_t), hipMemcpyHostToDevice, b->stream));
@@ -439,6 +482,8 @@ int run(lbac_batch* b, const int64_t* nsteps, bool dry, float* ms_out) {
                                hipMemcpyHostToDevice, b->stream));
         BHIP(b, hipMemcpyAsync(b->d_coarse[L], sl[L].coarse.data(), sizeof(int32_t) * sl[L].coarse.size(),
                                hipMemcpyHostToDevice, b->stream));
+        BHIP(b, hipMemcpyAsync(b->d_cls + L * (kBatchClasses + 1), sl[L].cls.data(),
+                               sizeof(int64_t) * (kBatchClasses + 1), hipMemcpyHostToDevice, b->stream));
     }
     rc = capture(b);
     if (rc != LBAC_OK) return rc;
@@ -526,6 +571,9 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
     if (hipMalloc(&b->d_inst, sizeof(BatchInst) * 2 * count) != hipSuccess ||
         hipMalloc(&b->d_ctl, sizeof(BatchCtl)) != hipSuccess || hipMalloc(&b->d_nent, 64) != hipSuccess ||
         hipMalloc(&b->d_first, sizeof(int32_t) * (count + 1)) != hipSuccess ||
+        hipMalloc(&b->d_cls, sizeof(int64_t) * 2 * (kBatchClasses + 1)) != hipSuccess ||
+        hipMalloc(&b->d_dev, sizeof(BatchDev)) != hipSuccess ||
+        hipHostMalloc((void**)&b->h_dev, sizeof(BatchDev), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_ctl, sizeof(BatchCtl), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_nent, 2 * sizeof(int32_t), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc((void**)&b->h_inst, sizeof(BatchInst) * 2 * count, hipHostMallocDefault) != hipSuccess)
@@ -629,6 +677,7 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
     std::vector<ItemH> items;
     if (!build_items(geo, strip_h, items)) return LBAC_EINVAL;
     const int n = (int)items.size();
+    const std::vector<int> cls_of = assign_classes(geo, nsteps);
     // The state, per buffer and item tile: the pass (run-wide index) that last
     // wrote it; the initial state is in buffer 0 (pass -1), buffer 1 holds
     // nothing valid.  Pass gp reads buffer gp & 1 and writes the other one.
@@ -645,17 +694,28 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
     for (int L = 0; L < 2 && *verdict == 0; ++L) {
         const std::vector<int64_t>& passes = L == 0 ? pf : pr;
         Slots sl;
-        build_slots(items, passes, sl);
+        build_slots(items, passes, cls_of, sl);
         const int32_t nent = (int32_t)(sl.entry.size() / 2);
         const int64_t total = sl.start.back();
-        const BatchSlots tab{sl.entry.data(), sl.start.data(), sl.first_item.data(), &nent, sl.coarse.data()};
+        const BatchSlots tab{sl.entry.data(), sl.start.data(), sl.first_item.data(), &nent, sl.coarse.data(),
+                             sl.cls.data()};
+        // every instance's entries lie in its class's block of slots
+        for (int64_t e = 0; e < nent; ++e) {
+            const int c = cls_of[sl.entry[2 * e]];
+            if (sl.start[e] < sl.cls[c] || sl.start[e + 1] > sl.cls[c + 1]) {
+                *verdict = 3;
+                return LBAC_OK;
+            }
+        }
         // the kernel's slot lookup (coarse index, then a search) against the
         // entry list walked slot by slot
         for (int64_t T = 0, e = 0; T < total && protocol != 2; ++T) {
             while (sl.start[e + 1] <= T) ++e;
             int32_t p = -1;
             const int32_t id = batch_slot_item(tab, T, nent, p);
-            if (p != sl.entry[2 * e + 1] || id != sl.first_item[sl.entry[2 * e]] + (int32_t)(T - sl.start[e])) {
+            const int k = sl.entry[2 * e], pe = sl.entry[2 * e + 1];
+            const int want = sl.first_item[k] + (int)(T - sl.start[e]);
+            if (p != pe || id != want || items[want].inst != k) {
                 *verdict = 3;
                 return LBAC_OK;
             }
@@ -688,7 +748,8 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
         std::vector<int> wl(workers, -1), wpos(workers, 0);
         std::vector<int32_t> wpass(workers, 0);
         int next_list = 0;
-        int64_t next = 0, finished = 0;
+        int64_t finished = 0, taken = 0;
+        std::vector<int64_t> tk(kBatchClasses, 0);  // the classes' counters
         // the next (pass, item) of worker w under protocol 2, or false at the
         // end of its list (the worker then takes the next list, if any)
         auto static_next = [&](int w, Slot& s) -> bool {
@@ -714,7 +775,8 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
             }
         };
         // Each worker is a resident workgroup running the kernel's loop: take
-        // the next slot, wait until every dependency has published p - 1, work
+        // a slot (the next of its class, else of another class, as the kernel
+        // does), wait until every dependency has published p - 1, work
         // (reading its read region and writing its tile anywhere in that
         // interval), publish.  The interleaving of the workers' actions is
         // random; a state in which no worker can act before every slot has
@@ -725,7 +787,7 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
             std::vector<int> can;
             for (int w = 0; w < workers; ++w) {
                 if (!busy[w]) {
-                    if (protocol == 2 ? (wl[w] >= 0 || next_list < lists) : next < total) can.push_back(w);
+                    if (protocol == 2 ? (wl[w] >= 0 || next_list < lists) : taken < total) can.push_back(w);
                 } else if (slot[w].started) {
                     can.push_back(w);
                 } else {
@@ -745,7 +807,11 @@ int lbac_batch_schedule_check(const int32_t* nx, const int32_t* ny, const int64_
                 if (protocol == 2) {
                     if (!static_next(w, s)) continue;
                 } else {
-                    s.id = batch_slot_item(tab, next++, nent, s.p);
+                    // worker w is workgroup w of the grid: class w mod kBatchClasses
+                    const int64_t T = batch_take(sl.cls.data(), w % kBatchClasses,
+                                                 [&](int c, int64_t nn) { return tk[c] < nn ? tk[c]++ : nn; });
+                    s.id = batch_slot_item(tab, T, nent, s.p);
+                    ++taken;
                 }
                 s.gp = (L == 0 ? 0 : pf[items[s.id].inst]) + s.p;
                 s.started = false;

@@ -498,11 +498,21 @@ struct IoCoherent {
     static constexpr int kSc1 = 16;  // cache-policy operand: sc1 (device scope)
     __amdgpu_buffer_rsrc_t sr, dr;
     uint32_t pb[9];  // byte offset of the plane read and written for population q
+    // the bases and the stride pass through readfirstlane: they are uniform,
+    // and saying so keeps the resources and offsets in scalar registers where
+    // the compiler cannot prove it (it would wrap every access in a loop over
+    // the distinct values)
+    __device__ __forceinline__ static void* uniform_ptr(const void* p) {
+        const uint64_t v = (uint64_t)p;
+        return (void*)(((uint64_t)(uint32_t)__builtin_amdgcn_readfirstlane((int)(v >> 32)) << 32) |
+                       (uint32_t)__builtin_amdgcn_readfirstlane((int)v));
+    }
     __device__ __forceinline__ IoCoherent(const StepArgs& a, bool mirror)
-        : sr(plane_rsrc(const_cast<void*>(a.src))), dr(plane_rsrc(a.dst)) {
-        const uint32_t ps = (uint32_t)a.plane_stride * 4u;
+        : sr(plane_rsrc(uniform_ptr(a.src))), dr(plane_rsrc(uniform_ptr(a.dst))) {
+        const uint32_t ps = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.plane_stride) * 4u;
+        const bool m = __builtin_amdgcn_readfirstlane((int)mirror) != 0;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) pb[q] = (uint32_t)(mirror ? mirror_q(q) : q) * ps;
+        for (int q = 0; q < 9; ++q) pb[q] = (uint32_t)(m ? mirror_q(q) : q) * ps;
     }
     __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
         const uint32_t b = off * 4u;
