@@ -230,15 +230,16 @@ void* lbac_stream(lbac_ctx* h);
  * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes).  The
  * instances are dealt to eight classes of about equal work (one per XCD, so
  * neighbouring tiles share that XCD's L2), and the (pass, item) slots of a
- * class are numbered pass by pass; the launch has one workgroup per slot and
- * each takes the next slot number of its class (blockIdx mod 8; once that
- * class is used up, of another) from the class's atomic counter when it
- * starts, then waits, through per-item progress counters, for the previous
- * pass of its own item and of the items its read region overlaps (no
- * grid-wide barrier), so instances retire independently.  Every slot waited
- * for is of the same class, has a smaller number and belongs to a workgroup
- * that has started, so the schedule progresses whatever number of
- * workgroups the device keeps resident.  Every instance uses FP32
+ * class are numbered pass by pass; the launch has as many workgroups as the
+ * device keeps resident, and each repeatedly takes the next slot number of
+ * its class (blockIdx mod 8; once that class is used up, of another) from
+ * the class's atomic counter, waits, through per-item progress counters, for
+ * the previous pass of its own item and of the items its read region
+ * overlaps (no grid-wide barrier), runs the pass and publishes, so instances
+ * retire independently.  Every slot waited for is of the same class, has a
+ * smaller number and is finished or held by a running workgroup, so the
+ * schedule progresses whatever number of workgroups the device keeps
+ * resident.  Every instance uses FP32
  * collide and storage and the improved model; results are bitwise those of
  * lbac_step on the same instance.  A wait that exceeds the time-out makes
  * every workgroup exit and the run return LBAC_EDEVICE. */

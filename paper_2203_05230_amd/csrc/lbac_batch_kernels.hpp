@@ -161,13 +161,13 @@ __host__ __device__ inline int32_t batch_slot_item(const BatchSlots& s, int64_t 
 // holds it until it is done, so every smaller number of a class belongs to a
 // slot that is finished or held by a running workgroup, however many
 // workgroups of the grid the device keeps resident (the grid, about the
-// resident count, only sets how many run at once).  Looping instead of one
-// workgroup per slot saves the dispatch of a workgroup and the kernel
-// prologue per slot, which had kept a tenth of the device's workgroup slots
-// empty.  S = kBatchS: the full passes; S = 1: the remaining one-step passes
-// (launch L = 1).  Both use the tile function of the multi-step kernel, so
-// one block shape serves both and the results are those of the
-// single-instance kernels.  Three waves per SIMD, no scratch.
+// resident count, only sets how many run at once; a workgroup keeps its
+// XCD, and so its class, for all its slots).  S = kBatchS: the full passes;
+// S = 1: the remaining one-step passes (launch L = 1).  Both use the tile
+// function of the multi-step kernel, so one block shape serves both and the
+// results are those of the single-instance kernels.  Three waves per SIMD;
+// the few registers spilled (36 bytes per lane) are per-slot values, outside
+// the row loop.
 // Everything a batch launch reads, in device memory behind one pointer: the
 // workgroup loop reads it again per slot, so that the tile function has the
 // scalar registers to itself instead of sharing them with a dozen pointers
