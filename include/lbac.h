@@ -268,9 +268,11 @@ int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
 int lbac_batch_count(lbac_batch* b, int32_t* count);
 
-/* Strip height (rows per item, >= 8; the default is 40).  get_shape also
- * gives the number of batch workgroups the device keeps resident at once
- * (information only: the schedule does not depend on it). */
+/* Strip height (>= 8; the default is 40): an instance ny rows high is cut
+ * into the nearest whole number of strips to ny / strip_h (at least one, at
+ * most ny / 8) of balanced heights.  get_shape also gives the number of
+ * batch workgroups the device keeps resident at once (the grid of a batch
+ * launch; the schedule's progress does not depend on it). */
 int lbac_batch_set_shape(lbac_batch* b, int32_t strip_h);
 int lbac_batch_get_shape(lbac_batch* b, int32_t* strip_h, int32_t* resident_workgroups);
 

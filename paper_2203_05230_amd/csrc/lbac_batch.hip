@@ -13,6 +13,7 @@
 
 #include <algorithm>
 #include <climits>
+#include <cmath>
 #include <cstring>
 #include <numeric>
 #include <random>
@@ -27,7 +28,7 @@ using namespace lbac_host;
 
 namespace {
 
-// Rows per strip at least (a shorter last strip of an instance is allowed).
+// Rows per strip at least (an instance with fewer rows is one strip).
 constexpr int kBatchMinStrip = kBatchGrow + 2;
 // Slots of one batch launch at most (bounds the host tables).
 constexpr int64_t kBatchMaxSlots = int64_t(1) << 36;
@@ -78,12 +79,18 @@ bool build_items(const std::vector<Geometry>& geo, int strip_h, std::vector<Item
     for (int k = 0; k < (int)geo.size(); ++k) {
         const int nx = geo[k].nx, ny = geo[k].ny;
         const std::vector<std::pair<int, int>> ct = column_tiles(nx);
-        const int sh = std::max(1, std::min(strip_h, ny));
-        const int nby = (ny + sh - 1) / sh, nbx = (int)ct.size();
+        // the nearest whole number of strips to ny / strip_h (at least one,
+        // at most ny / kBatchMinStrip), of balanced heights: strip j covers
+        // rows [j ny / nby, (j + 1) ny / nby); each strip costs its rows plus
+        // the pipeline's fill, so a ragged last strip is avoided
+        const int nby = std::max(1, std::min((int)std::lround((double)ny / strip_h), ny / kBatchMinStrip));
+        const int nbx = (int)ct.size();
+        auto strip_y0 = [&](int j) { return (int)((int64_t)j * ny / nby); };
         std::vector<int> tile_of_col(nx), strip_of_row(ny);
         for (int i = 0; i < nbx; ++i)
             for (int c = ct[i].first; c < ct[i].first + ct[i].second; ++c) tile_of_col[c] = i;
-        for (int r = 0; r < ny; ++r) strip_of_row[r] = r / sh;
+        for (int j = 0; j < nby; ++j)
+            for (int r = strip_y0(j); r < strip_y0(j + 1); ++r) strip_of_row[r] = j;
         const int base = (int)items.size();
         for (int j = 0; j < nby; ++j)
             for (int i = 0; i < nbx; ++i) {
@@ -91,8 +98,8 @@ bool build_items(const std::vector<Geometry>& geo, int strip_h, std::vector<Item
                 it.inst = k;
                 it.x0 = ct[i].first;
                 it.w = ct[i].second;
-                it.ys = j * sh;
-                it.hh = std::min(sh, ny - j * sh);
+                it.ys = strip_y0(j);
+                it.hh = strip_y0(j + 1) - strip_y0(j);
                 it.down = j & 1;
                 std::vector<int> tx, ty;
                 for (int c = it.x0 - G; c <= it.x0 + it.w - 1 + G; ++c) tx.push_back(tile_of_col[((c % nx) + nx) % nx]);

@@ -25,8 +25,9 @@ def test_benchmark_list_without_deadlock_at_any_residency(workers):
     shapes = [(c["nx"], c["ny"]) for c in cases]
     verdict, ran = lbac.batch_schedule_check(shapes, [48] * 256, 40, workers, seed=workers)
     assert verdict == 0, verdict
-    items_min = sum(-(-nx // 224) * -(-ny // 40) for nx, ny in shapes)
-    items_max = sum(-(-nx // 32) * -(-ny // 40) for nx, ny in shapes)
+    strips = [max(1, min(int(ny / 40 + 0.5), ny // 8)) for _, ny in shapes]  # nearest count, balanced heights
+    items_min = sum(-(-nx // 224) * s for (nx, _), s in zip(shapes, strips))
+    items_max = sum(-(-nx // 32) * s for (nx, _), s in zip(shapes, strips))
     assert items_min * 16 <= ran <= items_max * 16 and ran % 16 == 0
 
 
