@@ -122,6 +122,33 @@ def test_batch_seeded_list_subset(gpu_lib):
     b.close()
 
 
+def test_batch_benchmark_list_at_full_lengths(gpu_lib):
+    """The benchmark's batched workload as timed: the 256 seeded instances
+    (sides 128..512) over their whole runs (vortex 8 N, slotted disk 64 N
+    steps; 1 024 to 32 768 steps), strips of 80 rows.  Every instance reaches
+    its step count with its mass kept; the two longest runs, the two shortest
+    and four between are bitwise equal to the same instances advanced alone."""
+    say("case: benchmark batch list, 256 instances, full lengths")
+    cases = W.batch_cases(count=256, seed=0)
+    phis = [W.initial_field(c) for c in cases]
+    steps = [c["steps"] for c in cases]
+    b = gpu_lib.Batch(cases, phis)
+    b.set_shape(80)
+    b.run(steps)
+    for k, (c, p0) in enumerate(zip(cases, phis)):
+        inst = b.instance(k)
+        assert inst.time() == steps[k], k
+        m0 = float(p0.astype(np.float64).sum())
+        assert abs(inst.mass() - m0) / m0 < 5e-5, k  # FP32 rounding over up to 32 768 steps
+    order = sorted(range(256), key=lambda k: (steps[k] * cases[k]["nx"] * cases[k]["ny"], k))
+    probe = order[:2] + order[-2:] + order[64:256:48]
+    got = {k: b.instance(k).phi() for k in probe}
+    b.close()
+    for k in probe:
+        say("  probe", k, cases[k]["nx"], steps[k])
+        assert np.array_equal(got[k], single(gpu_lib, cases[k], phis[k], steps[k])), k
+
+
 def oracle_params(c):
     if c["vel"] == "rotation":
         return O.Params(c["nx"], c["ny"], eps=c["eps"], tau=c["tau"], delta=c["delta"], vel_kind=O.VEL_ROTATION,
