@@ -163,7 +163,7 @@ def run_form(lbac, torch, case, phi0, precision, steps, warmup, launch=None, aut
     return out
 
 
-def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512):
+def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512, precision="f32"):
     """The batched form on the seeded instance list (sides 128..512, eps in
     {0.5, 1, 2}, tau in [0.6, 1]; half single vortex over one period of 8 N
     steps, half slotted disk over one revolution of 64 N steps), every
@@ -173,14 +173,16 @@ def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512):
     against the same instance advanced alone, and, for context, the rate of
     the list advanced one instance after another through lbac_step (three
     steps per launch, HIP-graph replay) over the first `seq_cap` steps of
-    each instance.  strip_h: rows per item, else autotuned (dry runs)."""
+    each instance.  strip_h: rows per item, else autotuned (dry runs).
+    precision: the batch's storage; with 16-bit storage the sequential
+    context rate is skipped (seq_cap 0)."""
     cases = W.batch_cases(count=count, seed=seed)
     phis = [W.initial_field(c) for c in cases]
     steps = [c["steps"] for c in cases]
     updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, steps)))
     stream = torch.cuda.Stream()
     torch.cuda.set_stream(stream)
-    b = lbac.Batch(cases, phis, stream=stream.cuda_stream)
+    b = lbac.Batch(cases, phis, stream=stream.cuda_stream, precision=precision)
     if strip_h:
         b.set_shape(strip_h)
     else:
@@ -206,7 +208,7 @@ def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512):
     b.close()
 
     def alone(k, n):
-        sim = lbac.Simulation({**cases[k], "precision": "f32"}, phis[k], stream=stream.cuda_stream)
+        sim = lbac.Simulation({**cases[k], "precision": precision}, phis[k], stream=stream.cuda_stream)
         sim.set_launch(224, 40, 4)
         sim.set_graph_chunk(96)
         sim.step(n)
@@ -217,36 +219,39 @@ def batch_leg(lbac, torch, W, count, seed, strip_h=None, seq_cap=512):
         sim = alone(k, steps[k])
         same = same and bool(np.array_equal(got[k], sim.phi()))
         sim.close()
-    # sequential context rate: the first seq_cap steps of every instance, one after another
-    sims = [alone(k, 0) for k in range(count)]
-    for sim in sims:
-        sim.step(96)  # captures the graph outside the timed region
-    torch.cuda.synchronize()
-    seq_steps = [max(0, min(k, seq_cap) - 96) for k in steps]
-    seq_updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, seq_steps)))
-    ev0.record(stream)
-    for sim, k in zip(sims, seq_steps):
-        sim.step(k)
-    ev1.record(stream)
-    torch.cuda.synchronize()
-    ms_seq = ev0.elapsed_time(ev1)
-    for sim in sims:
-        sim.close()
-    torch.cuda.set_stream(torch.cuda.default_stream())
     mlups = updates / (ms_batch * 1e-3) / 1e6
-    seq_mlups = seq_updates / (ms_seq * 1e-3) / 1e6
+    seq = None
+    if seq_cap > 0:
+        # sequential context rate: the first seq_cap steps of every instance, one after another
+        sims = [alone(k, 0) for k in range(count)]
+        for sim in sims:
+            sim.step(96)  # captures the graph outside the timed region
+        torch.cuda.synchronize()
+        seq_steps = [max(0, min(k, seq_cap) - 96) for k in steps]
+        seq_updates = float(sum(c["nx"] * c["ny"] * k for c, k in zip(cases, seq_steps)))
+        ev0.record(stream)
+        for sim, k in zip(sims, seq_steps):
+            sim.step(k)
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        ms_seq = ev0.elapsed_time(ev1)
+        for sim in sims:
+            sim.close()
+        seq = dict(mlups=round(seq_updates / (ms_seq * 1e-3) / 1e6, 1), ms=round(ms_seq, 2),
+                   steps_per_instance_cap=seq_cap, launch=[224, 40, 4], graph_chunk=96)
+    torch.cuda.set_stream(torch.cuda.default_stream())
     e2a = np.array(e2)
     by_kind = {kind: dict(instances=int(sum(1 for x in kinds if x == kind)),
                           e2_median=float(np.median(e2a[[x == kind for x in kinds]])),
                           e2_max=float(np.max(e2a[[x == kind for x in kinds]])))
                for kind in ("vortex", "slotted disk")}
-    return dict(instances=count, seed=seed, node_updates=updates, steps_min=min(steps), steps_max=max(steps),
-                mlups=round(mlups, 1), ms=round(ms_batch, 2), strip_h=shape[0], resident_workgroups=shape[1],
-                e2_at_T=by_kind, e2_per_instance=[float("%.4e" % v) for v in e2],
-                bitwise_equal_probe=same, probed=probe,
-                sequential=dict(mlups=round(seq_mlups, 1), ms=round(ms_seq, 2), steps_per_instance_cap=seq_cap,
-                                launch=[224, 40, 4], graph_chunk=96),
-                speedup_vs_sequential=round(mlups / seq_mlups, 3))
+    out = dict(instances=count, seed=seed, precision=precision, node_updates=updates, steps_min=min(steps),
+               steps_max=max(steps), mlups=round(mlups, 1), ms=round(ms_batch, 2), strip_h=shape[0],
+               resident_workgroups=shape[1], e2_at_T=by_kind, e2_per_instance=[float("%.4e" % v) for v in e2],
+               bitwise_equal_probe=same, probed=probe)
+    if seq is not None:
+        out.update(sequential=seq, speedup_vs_sequential=round(mlups / seq["mlups"], 3))
+    return out
 
 
 CLOSURE_LAUNCHES = ((224, 40, 4), (192, 40, 4), (160, 40, 4), (224, 80, 4), (224, 40, 3))
@@ -636,6 +641,16 @@ def main():
     if args.batch > 0:
         print("bench: batched form, %d instances" % args.batch, file=sys.stderr, flush=True)
         batched = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None)
+        # the same list with shifted FP16 storage (the precision form inside the batched one)
+        print("bench: batched form, FP16 shifted storage", file=sys.stderr, flush=True)
+        b16 = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None, seq_cap=0,
+                        precision="f32_f16store")
+        e2_32 = np.array(batched["e2_per_instance"])
+        e2_16 = np.array(b16["e2_per_instance"])
+        batched["f32_f16store"] = dict(mlups=b16["mlups"], ms=b16["ms"], strip_h=b16["strip_h"],
+                                       bitwise_equal_probe=b16["bitwise_equal_probe"], e2_at_T=b16["e2_at_T"],
+                                       e2_ratio_vs_f32_median=float(np.median(e2_16 / e2_32)),
+                                       e2_ratio_vs_f32_max=float(np.max(e2_16 / e2_32)))
     closure = None
     if args.closure_steps > 0:
         print("bench: closure", file=sys.stderr, flush=True)

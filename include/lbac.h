@@ -239,19 +239,22 @@ void* lbac_stream(lbac_ctx* h);
  * retire independently.  Every slot waited for is of the same class, has a
  * smaller number and is finished or held by a running workgroup, so the
  * schedule progresses whatever number of workgroups the device keeps
- * resident.  Every instance uses FP32
- * collide and storage and the improved model; results are bitwise those of
- * lbac_step on the same instance.  A wait that exceeds the time-out makes
- * every workgroup exit and the run return LBAC_EDEVICE. */
+ * resident.  Every instance uses FP32 collide, FP32 or shifted 16-bit
+ * storage and the improved model; results are bitwise those of lbac_step on
+ * the same instance.  A wait that exceeds the time-out makes every workgroup
+ * exit and the run return LBAC_EDEVICE. */
 typedef struct lbac_batch lbac_batch;
 
 /* params[k], phi0[k] (host, ny*nx doubles): instance k, k < count.  The stream
  * of params[0] (or a private one) is used for the whole batch; allocators are
- * honoured per instance.  Errors as lbac_init, plus LBAC_EINVAL for a
- * precision other than LBAC_F32, a model other than LBAC_MODEL_IMPROVED, or
- * an instance whose nine population planes take 2^31 bytes or more (about
- * 7700 x 7700 nodes; such a lattice fills the device by itself and belongs
- * to lbac_step). */
+ * honoured per instance.  Every instance has the same precision: LBAC_F32,
+ * or the shifted 16-bit storage LBAC_F32_F16STORE / LBAC_F32_BF16STORE (FP32
+ * collide, the populations kept in FP32 between the three steps of a pass
+ * and rounded to 16 bits once per pass, as lbac_step does).  Errors as
+ * lbac_init, plus LBAC_EINVAL for another precision or mixed precisions, a
+ * model other than LBAC_MODEL_IMPROVED, or an instance whose population
+ * planes take 2^31 bytes or more (FP32: about 7700 x 7700 nodes; such a
+ * lattice fills the device by itself and belongs to lbac_step). */
 int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_t count, lbac_batch** out);
 int lbac_batch_free(lbac_batch* b);
 

@@ -208,6 +208,7 @@ struct lbac_batch {
     std::vector<lbac_ctx*> inst;
     int strip_h = 40;   // >= kBatchMinStrip
     int max_wgs = 0;    // workgroups the device keeps resident at once: the grid of a launch
+    int st = ST_PLAIN;  // storage of every instance
     double ticks_per_s = 1e8;
     double timeout_s = 20.0;
     int test_stall = 0;
@@ -343,6 +344,25 @@ int ensure_tables(lbac_batch* b, const int64_t nent[2], const int64_t ncoarse[2]
     return LBAC_OK;
 }
 
+// The batch kernel of storage st for launch L (L = 0: full passes; 1: one-step passes).
+template <int ST>
+void launch_batch_st(int L, dim3 grid, hipStream_t stream, const BatchDev* dev) {
+    if (L == 0)
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS, ST>), grid, dim3(kBatchThreads), 0, stream, dev);
+    else
+        hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1, ST>), grid, dim3(kBatchThreads), 0, stream, dev);
+}
+void launch_batch(int st, int L, dim3 grid, hipStream_t stream, const BatchDev* dev) {
+    if (st == ST_F16) launch_batch_st<ST_F16>(L, grid, stream, dev);
+    else if (st == ST_BF16) launch_batch_st<ST_BF16>(L, grid, stream, dev);
+    else launch_batch_st<ST_PLAIN>(L, grid, stream, dev);
+}
+const void* batch_kernel_of(int st) {
+    if (st == ST_F16) return (const void*)batch_kernel<MODEL_IMPROVED, kBatchS, ST_F16>;
+    if (st == ST_BF16) return (const void*)batch_kernel<MODEL_IMPROVED, kBatchS, ST_BF16>;
+    return (const void*)batch_kernel<MODEL_IMPROVED, kBatchS, ST_PLAIN>;
+}
+
 // Workgroups of a batch launch: as many as the device keeps resident, fewer
 // if the launch has fewer slots (each workgroup takes slots until none is
 // left; a grid beyond the resident count would only add workgroups that
@@ -363,12 +383,7 @@ int capture(lbac_batch* b) {
     auto launch_slots = [&](int L) {
         const int64_t g = batch_grid(b, L);
         if (g <= 0 || e != hipSuccess) return;
-        if (L == 0)
-            hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, kBatchS>), dim3((unsigned)g), dim3(kBatchThreads), 0,
-                               b->stream, b->d_dev);
-        else
-            hipLaunchKernelGGL((batch_kernel<MODEL_IMPROVED, 1>), dim3((unsigned)g), dim3(kBatchThreads), 0,
-                               b->stream, b->d_dev);
+        launch_batch(b->st, L, dim3((unsigned)g), b->stream, b->d_dev);
         e = hipGetLastError();
     };
     launch_slots(0);
@@ -530,8 +545,10 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
     if (!out) return LBAC_EINVAL;
     *out = nullptr;
     if (!params || !phi0 || count < 1) return LBAC_EINVAL;
+    const int prec = params[0].precision;
+    if (prec != LBAC_F32 && prec != LBAC_F32_F16STORE && prec != LBAC_F32_BF16STORE) return LBAC_EINVAL;
     for (int k = 0; k < count; ++k) {
-        if (params[k].precision != LBAC_F32 || params[k].model != LBAC_MODEL_IMPROVED) return LBAC_EINVAL;
+        if (params[k].precision != prec || params[k].model != LBAC_MODEL_IMPROVED) return LBAC_EINVAL;
         if (!phi0[k]) return LBAC_EINVAL;
         // nine FP32 planes of at least nx * ny values each must stay below
         // 2^31 bytes (checked exactly, padding included, once allocated)
@@ -560,16 +577,16 @@ int lbac_batch_init(const lbac_params* params, const double* const* phi0, int32_
         if (rc != LBAC_OK) return bail(rc);
         c->in_batch = true;
         b->inst[k] = c;
-        // the batch kernel addresses the nine planes of a buffer through one
+        // the batch kernel addresses the planes of a buffer through one
         // buffer resource with 32-bit offsets below 2^31
-        if (c->plane_stride * 9 * (int64_t)sizeof(float) >= (int64_t)0x7FFFFFFF) return bail(LBAC_EINVAL);
+        if (c->plane_stride * c->nplanes * (int64_t)c->elem_bytes >= (int64_t)0x7FFFFFFF) return bail(LBAC_EINVAL);
     }
+    b->st = b->inst[0]->storage;
     int per_cu = 0, cus = 0, khz = 0;
     // the default grid: as many workgroups as the device keeps resident (the
     // schedule itself does not depend on residency); the multi-step launch
     // has the lower occupancy and sets it for both
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel<MODEL_IMPROVED, kBatchS>, kBatchThreads, 0) !=
-            hipSuccess ||
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, batch_kernel_of(b->st), kBatchThreads, 0) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, b->device) != hipSuccess)
         return bail(LBAC_EDEVICE);
     if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, b->device) == hipSuccess && khz > 0)

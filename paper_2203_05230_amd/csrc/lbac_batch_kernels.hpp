@@ -180,7 +180,9 @@ struct BatchDev {
     BatchCtl* ctl;
 };
 
-template <int MODEL, int S>
+// ST: the storage of every instance of the batch (FP32, or shifted FP16 or
+// BF16 with the populations in FP32 between the steps of a pass).
+template <int MODEL, int S, int ST>
 __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3))) void batch_kernel(
     const BatchDev* dv) {
     static_assert(stepS_threads<kBatchTile, S>() == kBatchThreads, "one block size serves both launches");
@@ -234,8 +236,7 @@ __global__ __launch_bounds__(kBatchThreads) __attribute__((amdgpu_waves_per_eu(3
         const int64_t gp = S == 1 ? nfull + p : p;  // pass index within the run
         const StepArgs a = insts[2 * inst + (int)(gp & 1)].a;
         const int64_t t = a.t_dev[0] + (dry ? 0 : (S == 1 ? nfull * kBatchS + p : (int64_t)p * kBatchS));
-        stepS_tile_lds<MODEL, kBatchTile, S, ST_PLAIN, true>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0,
-                                                             lds);
+        stepS_tile_lds<MODEL, kBatchTile, S, ST, true>(a, item.x0, item.w, item.ys, item.hh, t, item.down != 0, lds);
         // publish: every wavefront waits until its device-scope stores have
         // completed (vmcnt counts stores on this architecture), then the
         // counter moves; no writeback of the whole L2 is needed

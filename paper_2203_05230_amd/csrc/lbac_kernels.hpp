@@ -527,6 +527,51 @@ struct IoCoherent {
     }
 };
 
+// Shifted 16-bit storage (g_i planes and the FP32 phi* plane, as IoShifted)
+// read and written with device-scope accesses, for the batched form: one
+// buffer resource for the g planes of a buffer (the plane chosen by the
+// scalar offset, as IoCoherent) and one for its phi* plane.  Requires the
+// eight g planes to span less than 2^31 bytes.
+template <typename H>
+struct IoCoherentShifted {
+    static constexpr bool kShifted = true;
+    static constexpr int kSc1 = IoCoherent::kSc1;
+    __amdgpu_buffer_rsrc_t sg, dg, sp, dp;
+    uint32_t pb[9];  // byte offset of the g plane read and written for population q (q >= 1)
+    __device__ __forceinline__ IoCoherentShifted(const StepArgs& a, bool mirror)
+        : sg(plane_rsrc(IoCoherent::uniform_ptr(a.src))),
+          dg(plane_rsrc(IoCoherent::uniform_ptr(a.dst))),
+          sp(plane_rsrc(IoCoherent::uniform_ptr(a.src_phi))),
+          dp(plane_rsrc(IoCoherent::uniform_ptr(a.dst_phi))) {
+        const uint32_t ps = (uint32_t)__builtin_amdgcn_readfirstlane((int)a.plane_stride) * (uint32_t)sizeof(H);
+        const bool m = __builtin_amdgcn_readfirstlane((int)mirror) != 0;
+        pb[0] = 0;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) pb[q] = (uint32_t)((m ? mirror_q(q) : q) - 1) * ps;
+    }
+    // v[0] = phi*, v[i] = w_i phi* + g_i
+    __device__ __forceinline__ void load(uint32_t off, float (&v)[9]) const {
+        const float ph =
+            __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sp, (int)(off * 4u), 0, kSc1));
+        v[0] = ph;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) {
+            const unsigned short g = __builtin_amdgcn_raw_buffer_load_b16(sg, (int)(off * 2u), (int)pb[q], kSc1);
+            v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(__builtin_bit_cast(H, g)));
+        }
+    }
+    // stores g_i = v_i - w_i phi and phi* = phi when `on`
+    __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float phi) const {
+        const uint32_t b2 = on ? off * 2u : kDropOffset, b4 = on ? off * 4u : kDropOffset;
+#pragma unroll
+        for (int q = 1; q < 9; ++q)
+            __builtin_amdgcn_raw_buffer_store_b16(
+                __builtin_bit_cast(unsigned short, f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]))), dg, (int)b2,
+                (int)pb[q], kSc1);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(phi), dp, (int)b4, 0, kSc1);
+    }
+};
+
 // ---------------------------------------------------------------------------
 // The step on one tile, block-wide variant.
 //
@@ -1035,16 +1080,19 @@ __host__ __device__ constexpr int stepS_threads() {
     return (BX + 2 * StepSGeom<BX, S, CL>::H + 63) / 64 * 64;
 }
 
-// COH: FP32 plain storage through IoCoherent (the batched form).  CL: the
+// COH: storage read and written with device-scope accesses (IoCoherent,
+// IoCoherentShifted: the batched form).  CL: the
 // learned closure (FP32 plain storage).
 template <int MODEL, int BX, int S, int ST, bool COH = false, bool CL = false>
 __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w, int ys, int hh, int64_t t,
                                                bool down, TileSLds<BX, S, CL>& lds) {
-    static_assert(!COH || ST == ST_PLAIN, "coherent access is for FP32 plain storage");
     static_assert(!CL || (ST == ST_PLAIN && !COH), "the closure runs with FP32 plain storage");
     using G = StepSGeom<BX, S, CL>;
     constexpr int H = G::H, UL = G::UL, LG = G::LG, PER = G::PER, D = G::D, W = G::W, NPS = G::NPS;
-    using IoT = typename std::conditional<COH, IoCoherent, Io<float, ST>>::type;
+    using IoCoh = typename std::conditional<
+        ST == ST_PLAIN, IoCoherent,
+        IoCoherentShifted<typename std::conditional<ST == ST_F16, __half, __hip_bfloat16>::type>>::type;
+    using IoT = typename std::conditional<COH, IoCoh, Io<float, ST>>::type;
     // Thread layout.  The C = 64 * c columns of the tile that whole wavefronts
     // own go to wavefronts 0 .. c - 1, one aligned 64-column segment each (so
     // every wavefront loads and stores whole 256-byte lines); wavefront c, the

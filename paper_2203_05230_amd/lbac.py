@@ -363,14 +363,16 @@ class _Borrowed(Simulation):
 
 
 class Batch:
-    """Independent instances advanced together by one persistent launch."""
+    """Independent instances advanced together by one persistent launch.
+    precision: the storage of every instance ("f32", "f32_f16store" or
+    "f32_bf16store"; FP32 collide in all three)."""
 
-    def __init__(self, cases, phi0s, stream=None):
+    def __init__(self, cases, phi0s, stream=None, precision="f32"):
         L = load()
         n = len(cases)
         params = (lbac_params * n)()
         for k, c in enumerate(cases):
-            params[k] = make_params(**{**c, "precision": "f32", "stream": stream if k == 0 else None})
+            params[k] = make_params(**{**c, "precision": precision, "stream": stream if k == 0 else None})
         self._phi = [np.ascontiguousarray(p, dtype=np.float64).reshape(c["ny"], c["nx"]) for c, p in zip(cases, phi0s)]
         ptrs = (C.POINTER(C.c_double) * n)(*[_dp(a) for a in self._phi])
         h = C.c_void_p()

@@ -105,6 +105,20 @@ def test_batch_rejects_instances_beyond_its_addressing():
     assert not h.value
 
 
+@pytest.mark.parametrize("precs", [("f64", "f64"), ("f32", "f32_f16store"), ("f32_bf16store", "f32_f16store")])
+def test_batch_rejects_fp64_and_mixed_precisions(precs):
+    """Every instance of a batch has one precision, FP32 or shifted 16-bit
+    storage (one kernel serves the launch); refused before anything is
+    allocated."""
+    L = lbac.load()
+    ps = (lbac.lbac_params * 2)(*[lbac.make_params(64, 64, precision=p) for p in precs])
+    phi0 = np.zeros(16)
+    ptr = phi0.ctypes.data_as(C.POINTER(C.c_double))
+    h = C.c_void_p()
+    assert L.lbac_batch_init(ps, (C.POINTER(C.c_double) * 2)(ptr, ptr), 2, C.byref(h)) == lbac.LBAC_EINVAL
+    assert not h.value
+
+
 def test_null_arguments_rejected():
     L = lbac.load()
     p = lbac.make_params(16, 16)

@@ -39,8 +39,8 @@ def mixed_cases():
     return cases, phis, steps
 
 
-def single(lb, case, phi0, n):
-    sim = lb.Simulation({**case, "precision": "f32"}, phi0)
+def single(lb, case, phi0, n, precision="f32"):
+    sim = lb.Simulation({**case, "precision": precision}, phi0)
     sim.step(n)
     out = sim.phi()
     sim.close()
@@ -56,6 +56,32 @@ def test_batch_bitwise_equals_single_instances(gpu_lib):
         inst = b.instance(k)
         assert inst.time() == n
         assert np.array_equal(inst.phi(), single(gpu_lib, c, p, n)), k
+    b.close()
+
+
+@pytest.mark.parametrize("precision", ["f32_f16store", "f32_bf16store"])
+def test_batch_16bit_storage_bitwise_equals_single_instances(gpu_lib, precision):
+    """Shifted 16-bit storage in the batch (FP32 between the steps of a pass,
+    rounded once per pass): bitwise the single-instance form, over two runs
+    (the second continues from the first's state) and two strip heights."""
+    say("case: batch of 6 mixed instances,", precision)
+    cases, phis, steps = mixed_cases()
+    b = gpu_lib.Batch(cases, phis, precision=precision)
+    b.run(steps)
+    b.set_shape(24)
+    b.run(steps)
+    for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
+        inst = b.instance(k)
+        assert inst.time() == 2 * n
+        # 16-bit storage rounds once per launch, so the single run takes the
+        # three-step launches and the same two calls (n // 3 three-step
+        # launches, then n mod 3 one-step ones, each time)
+        sim = gpu_lib.Simulation({**c, "precision": precision}, p)
+        sim.set_launch(224, 40, 4)
+        sim.step(n)
+        sim.step(n)
+        assert np.array_equal(inst.phi(), sim.phi()), k
+        sim.close()
     b.close()
 
 
