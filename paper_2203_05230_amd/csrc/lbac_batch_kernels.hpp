@@ -11,7 +11,8 @@
 // Batched form: many independent lattices advanced by ONE persistent launch.
 //
 // Work is split into items = (instance, tile of at most kBatchTile columns,
-// strip of rows).  A run is two persistent launches: the first takes the full
+// strip of rows; one storage, FP32 or shifted 16-bit, for every instance).
+// A run is two persistent launches: the first takes the full
 // passes of kBatchS steps each (the multi-step tile function, the populations
 // between the steps in LDS), the second the remaining nsteps mod kBatchS steps
 // as one-step passes of the same tile function.  A pass of an item reads its
@@ -36,9 +37,9 @@
 // running workgroup that stays resident until it is done (a slot is taken
 // only by a running workgroup): the lowest unfinished slot of a class can
 // always proceed, whatever number of workgroups the device keeps resident and
-// whichever class a workgroup takes from, and the schedule cannot deadlock.  Every wait is also bounded in
-// wall-clock time and sets an error flag that makes all later workgroups exit
-// at once.
+// whichever class a workgroup takes from, and the schedule cannot deadlock.
+// Every wait is also bounded in wall-clock time and sets an error flag that
+// makes all later workgroups exit at once.
 namespace lbac {
 
 constexpr int kBatchTile = 224;          // widest item tile (columns)
