@@ -533,6 +533,7 @@ def main():
     ap.add_argument("--cpu-single-core", default="", help=argparse.SUPPRESS)
     ap.add_argument("--batch", type=int, default=256, help="instances in the batched leg (0: skip)")
     ap.add_argument("--batch-strip", type=int, default=0, help="strip height of the batched leg (default: autotune)")
+    ap.add_argument("--batch-f16", type=int, default=1, help="also time the batched list with FP16 storage (0: skip)")
     ap.add_argument("--closure-steps", type=int, default=256, help="steps of the closure leg (0: skip)")
     ap.add_argument("--train-steps", type=int, default=200, help="Adam steps of the closure-training leg (0: skip)")
     ap.add_argument("--grid3d", type=int, default=256, help="side of the D3Q19 leg (0: skip)")
@@ -641,16 +642,17 @@ def main():
     if args.batch > 0:
         print("bench: batched form, %d instances" % args.batch, file=sys.stderr, flush=True)
         batched = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None)
-        # the same list with shifted FP16 storage (the precision form inside the batched one)
-        print("bench: batched form, FP16 shifted storage", file=sys.stderr, flush=True)
-        b16 = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None, seq_cap=0,
-                        precision="f32_f16store")
-        e2_32 = np.array(batched["e2_per_instance"])
-        e2_16 = np.array(b16["e2_per_instance"])
-        batched["f32_f16store"] = dict(mlups=b16["mlups"], ms=b16["ms"], strip_h=b16["strip_h"],
-                                       bitwise_equal_probe=b16["bitwise_equal_probe"], e2_at_T=b16["e2_at_T"],
-                                       e2_ratio_vs_f32_median=float(np.median(e2_16 / e2_32)),
-                                       e2_ratio_vs_f32_max=float(np.max(e2_16 / e2_32)))
+        if args.batch_f16:
+            # the same list with shifted FP16 storage (the precision form inside the batched one)
+            print("bench: batched form, FP16 shifted storage", file=sys.stderr, flush=True)
+            b16 = batch_leg(lbac, torch, W, args.batch, 0, strip_h=args.batch_strip or None, seq_cap=0,
+                            precision="f32_f16store")
+            e2_32 = np.array(batched["e2_per_instance"])
+            e2_16 = np.array(b16["e2_per_instance"])
+            batched["f32_f16store"] = dict(mlups=b16["mlups"], ms=b16["ms"], strip_h=b16["strip_h"],
+                                           bitwise_equal_probe=b16["bitwise_equal_probe"], e2_at_T=b16["e2_at_T"],
+                                           e2_ratio_vs_f32_median=float(np.median(e2_16 / e2_32)),
+                                           e2_ratio_vs_f32_max=float(np.max(e2_16 / e2_32)))
     closure = None
     if args.closure_steps > 0:
         print("bench: closure", file=sys.stderr, flush=True)
