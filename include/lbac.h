@@ -271,6 +271,17 @@ int lbac_batch_run(lbac_batch* b, const int64_t* nsteps);
 int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx);
 int lbac_batch_count(lbac_batch* b, int32_t* count);
 
+/* phi of instance k (Eq. (12), the pulled sum): out is ny*nx host doubles of
+ * that instance, caller-owned, as lbac_phi on lbac_batch_instance(b, k).
+ * Synchronises.  LBAC_EINVAL for k out of range; LBAC_ESTATE after a run
+ * that timed out. */
+int lbac_batch_phi(lbac_batch* b, int32_t k, double* out);
+
+/* The mass of every instance (the sum of phi over its lattice, as
+ * lbac_mass): per_instance is count host doubles, caller-owned.
+ * Synchronises.  Errors as lbac_mass for the first instance that fails. */
+int lbac_batch_mass(lbac_batch* b, double* per_instance);
+
 /* Strip height (>= 8; the default is 40): an instance ny rows high is cut
  * into the nearest whole number of strips to ny / strip_h (at least one, at
  * most ny / 8) of balanced heights.  get_shape also gives the number of

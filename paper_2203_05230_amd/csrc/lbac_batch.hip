@@ -627,6 +627,20 @@ int lbac_batch_instance(lbac_batch* b, int32_t k, lbac_ctx** ctx) {
     return LBAC_OK;
 }
 
+int lbac_batch_phi(lbac_batch* b, int32_t k, double* out) {
+    if (!b || !out || k < 0 || k >= (int)b->inst.size()) return LBAC_EINVAL;
+    return lbac_phi(b->inst[k], out);
+}
+
+int lbac_batch_mass(lbac_batch* b, double* per_instance) {
+    if (!b || !per_instance) return LBAC_EINVAL;
+    for (size_t k = 0; k < b->inst.size(); ++k) {
+        const int rc = lbac_mass(b->inst[k], per_instance + k);
+        if (rc != LBAC_OK) return rc;
+    }
+    return LBAC_OK;
+}
+
 int lbac_batch_count(lbac_batch* b, int32_t* count) {
     if (!b || !count) return LBAC_EINVAL;
     *count = (int32_t)b->inst.size();

@@ -62,6 +62,7 @@ EXPORTS = [
     "lbac_copy_ceiling", "lbac_set_closure",
     "lbac_stream", "lbac_strerror", "lbac_last_error",
     "lbac_batch_init", "lbac_batch_free", "lbac_batch_run", "lbac_batch_instance", "lbac_batch_count",
+    "lbac_batch_phi", "lbac_batch_mass",
     "lbac_batch_set_shape", "lbac_batch_get_shape", "lbac_batch_autotune", "lbac_batch_set_timeout",
     "lbac_batch_last_error", "lbac_batch_schedule_check",
     "lbac_mlp_create", "lbac_mlp_free", "lbac_mlp_get_weights", "lbac_mlp_set_weights", "lbac_mlp_forward",
@@ -128,6 +129,8 @@ def load():
     L.lbac_batch_run.argtypes = [C.c_void_p, P(C.c_int64)]
     L.lbac_batch_instance.argtypes = [C.c_void_p, C.c_int32, ctx_pp]
     L.lbac_batch_count.argtypes = [C.c_void_p, P(C.c_int32)]
+    L.lbac_batch_phi.argtypes = [C.c_void_p, C.c_int32, P(C.c_double)]
+    L.lbac_batch_mass.argtypes = [C.c_void_p, P(C.c_double)]
     L.lbac_batch_set_shape.argtypes = [C.c_void_p, C.c_int32]
     L.lbac_batch_get_shape.argtypes = [C.c_void_p, P(C.c_int32), P(C.c_int32)]
     L.lbac_batch_autotune.argtypes = [C.c_void_p, P(C.c_int64), dp]
@@ -405,6 +408,19 @@ class Batch:
         self._err(load().lbac_batch_instance(self.h, int(k), C.byref(c)))
         nx, ny = self.shapes[k]
         return _Borrowed(c, nx, ny)
+
+    def phi(self, k):
+        """phi of instance k (ny x nx, FP64) through lbac_batch_phi."""
+        nx, ny = self.shapes[k]
+        out = np.empty((ny, nx), dtype=np.float64)
+        self._err(load().lbac_batch_phi(self.h, int(k), _dp(out)))
+        return out
+
+    def masses(self):
+        """The mass of every instance through lbac_batch_mass."""
+        out = np.empty(self.count, dtype=np.float64)
+        self._err(load().lbac_batch_mass(self.h, _dp(out)))
+        return out
 
     def set_shape(self, strip_h):
         self._err(load().lbac_batch_set_shape(self.h, int(strip_h)))

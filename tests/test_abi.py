@@ -119,6 +119,13 @@ def test_batch_rejects_fp64_and_mixed_precisions(precs):
     assert not h.value
 
 
+def test_batch_queries_reject_null_handles():
+    L = lbac.load()
+    out = np.zeros(4)
+    assert L.lbac_batch_phi(None, 0, out.ctypes.data_as(C.POINTER(C.c_double))) == lbac.LBAC_EINVAL
+    assert L.lbac_batch_mass(None, out.ctypes.data_as(C.POINTER(C.c_double))) == lbac.LBAC_EINVAL
+
+
 def test_null_arguments_rejected():
     L = lbac.load()
     p = lbac.make_params(16, 16)

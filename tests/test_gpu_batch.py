@@ -52,10 +52,14 @@ def test_batch_bitwise_equals_single_instances(gpu_lib):
     cases, phis, steps = mixed_cases()
     b = gpu_lib.Batch(cases, phis)
     b.run(steps)
+    masses = b.masses()
     for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
         inst = b.instance(k)
         assert inst.time() == n
-        assert np.array_equal(inst.phi(), single(gpu_lib, c, p, n)), k
+        ref = single(gpu_lib, c, p, n)
+        assert np.array_equal(inst.phi(), ref), k
+        assert np.array_equal(b.phi(k), ref), k  # lbac_batch_phi
+        assert masses[k] == inst.mass(), k       # lbac_batch_mass
     b.close()
 
 
