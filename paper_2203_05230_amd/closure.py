@@ -191,7 +191,7 @@ def main(argv=None):
     ap.add_argument("--theta", type=float, default=0.02)
     ap.add_argument("--eps", type=float, default=0.5)
     ap.add_argument("--seed", type=int, default=1)
-    ap.add_argument("--out", default="gpurun_out/closure")
+    ap.add_argument("--out", default="closure_out")
     a = ap.parse_args(argv)
     torch.cuda.set_device(0)
     lbac.load()

@@ -43,7 +43,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description="the paper's single-vortex experiment with this scheme")
     ap.add_argument("--eps", default="1,1.5,2,2.5,3,4", help="interface widths in the paper's convention")
     ap.add_argument("--precision", default="f64")
-    ap.add_argument("--out", default="gpurun_out/paper_preset")
+    ap.add_argument("--out", default="paper_preset_out")
     a = ap.parse_args(argv)
     lbac.load()
     os.makedirs(a.out, exist_ok=True)
