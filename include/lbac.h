@@ -154,9 +154,9 @@ int lbac_set_state(lbac_ctx* h, const void* buf, size_t bytes);
  * tile grown by RC (S - 1 - k) columns and rows on each side, RC = 2, or 3
  * with the closure, whose network reads a 5x5 neighbourhood), so HBM is read
  * and written once per S steps; their tiles are bx = 64, 96, 128, ..., 320
- * columns (any multiple of 32 in that range; with the closure 128, 160, 192
- * or 224, another width running those launches at 224), the block being the
- * bx + 2 RC S grown columns rounded up to whole wavefronts; a step count
+ * columns (any multiple of 32 in that range, and 240; with the closure 128,
+ * 160, 192 or 224, another width running those launches at 224), the block
+ * being the bx + 2 RC S grown columns rounded up to whole wavefronts; a step count
  * that is not a multiple of S ends with one-step launches (bx 256 where bx
  * is not 64, 128 or 256).  With the closure and the conventional model every
  * step is a one-step launch.  strip_h: rows each tile marches (>= 1).
@@ -225,7 +225,7 @@ void* lbac_stream(lbac_ctx* h);
  * Many independent lattices (instances) of uneven sizes and parameters
  * advanced together by ONE kernel launch (plus one for the last nsteps mod 3
  * steps), replayed from a captured HIP graph.  Work is split into (instance,
- * column tile of at most 224 columns, strip of rows) items.  An item takes
+ * column tile of at most 240 columns, strip of rows) items.  An item takes
  * three steps per pass (the populations between them kept in LDS, as with
  * LBAC_KERNEL_FUSED3; the last nsteps mod 3 steps are one-step passes).  The
  * instances are dealt to eight classes of about equal work (one per XCD, so

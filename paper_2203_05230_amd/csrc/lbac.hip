@@ -224,8 +224,10 @@ hipError_t launch_step_m(const lbac_ctx* h, const StepArgs& a, int variant, int 
 bool one_step_bx(int bx) { return bx == 64 || bx == 128 || bx == 256; }
 
 // Tile widths of the S-step kernels: multiples of 32 columns from 64 to 320,
-// so every tile row starts on a 128-byte line.
-bool stepS_bx(int bx) { return bx >= 64 && bx <= 320 && bx % 32 == 0; }
+// and 240 (the widest tile whose grown columns, bx + 4S at S = 3, fill four
+// wavefronts; its odd tiles start half a line in, and their head columns go to
+// the halo wavefront).
+bool stepS_bx(int bx) { return (bx >= 64 && bx <= 320 && bx % 32 == 0) || bx == 240; }
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
     StepArgs a = make_args(h, src, k);
@@ -331,6 +333,8 @@ hipError_t launch_stepS_m(StepArgs a, int bx, hipStream_t s) {
         return launch_stepS_shape<MODEL, S, ST, 192>(a, s);
     case 224:
         return launch_stepS_shape<MODEL, S, ST, 224>(a, s);
+    case 240:
+        return launch_stepS_shape<MODEL, S, ST, 240>(a, s);
     case 288:
         return launch_stepS_shape<MODEL, S, ST, 288>(a, s);
     case 320:
@@ -783,7 +787,7 @@ int lbac_set_launch(lbac_ctx* h, int32_t variant, int32_t bx, int32_t strip_h) {
     const int S = variant == LBAC_KERNEL_FUSED2 ? 2 : (variant == LBAC_KERNEL_FUSED3 ? 3 : 1);
     if (!(S == 1 ? one_step_bx(bx) : stepS_bx(bx)))
         return fail(h, LBAC_EINVAL, "bx must be 64, 128 or 256 (with the multi-step variants any multiple of 32 from "
-                                    "64 to 320)");
+                                    "64 to 320, or 240)");
     if (strip_h < 1) return fail(h, LBAC_EINVAL, "strip_h must be >= 1");
     h->variant = variant;
     h->bx = bx;
@@ -804,7 +808,7 @@ int lbac_autotune(lbac_ctx* h, int32_t steps, double* us_per_step) {
     if (!h || steps < 1) return LBAC_EINVAL;
     if (h->failed) return fail(h, LBAC_ESTATE, "the batch run of this instance timed out; its state is undefined");
     DeviceGuard g(h->device);
-    const int bxs[9] = {64, 96, 128, 160, 192, 224, 256, 288, 320};
+    const int bxs[10] = {64, 96, 128, 160, 192, 224, 240, 256, 288, 320};
     // strip heights: multiples of 8 up to 256 and powers of two up to 512 (the
     // count of tiles against the workgroups resident at once decides how full
     // the last round of tiles is, so heights between the powers of two can

@@ -42,7 +42,7 @@
 // makes all later workgroups exit at once.
 namespace lbac {
 
-constexpr int kBatchTile = 224;          // widest item tile (columns)
+constexpr int kBatchTile = 240;          // widest item tile (columns)
 constexpr int kBatchS = 3;               // steps per full pass
 constexpr int kBatchGrow = 2 * kBatchS;  // read region: the tile grown by this many nodes
 constexpr int kBatchThreads = stepS_threads<kBatchTile, kBatchS>();

@@ -1093,24 +1093,30 @@ __device__ __forceinline__ void stepS_tile_lds(const StepArgs& a, int x0, int w,
         ST == ST_PLAIN, IoCoherent,
         IoCoherentShifted<typename std::conditional<ST == ST_F16, __half, __hip_bfloat16>::type>>::type;
     using IoT = typename std::conditional<COH, IoCoh, Io<float, ST>>::type;
-    // Thread layout.  The C = 64 * c columns of the tile that whole wavefronts
-    // own go to wavefronts 0 .. c - 1, one aligned 64-column segment each (so
-    // every wavefront loads and stores whole 256-byte lines); wavefront c, the
-    // halo wavefront, takes the H left halo columns, the tile's remaining
-    // w - C columns and the right halo (c is the largest count for which that
-    // fits in 64 lanes, else one more, whose last columns then belong to the
-    // right halo); later wavefronts (a tile narrower than BX) only take part
-    // in the barriers.  Threads whose column lies past the right halo
+    // Thread layout.  The tile's first hd columns (its head: the columns up to
+    // the first 128-byte line boundary of the storage, when x0 is not on one
+    // and the layout below still fits; else hd = 0) and the C = 64 * c
+    // columns after them that whole wavefronts own go to wavefronts 0 .. c - 1
+    // in segments of 64 columns, each starting on a line (so every wavefront
+    // loads and stores whole lines); wavefront c, the halo wavefront, takes the
+    // H left halo columns, the head, the tile's remaining w - hd - C columns
+    // and the right halo (c is the largest count for which that fits in 64
+    // lanes, else one more, whose last columns then belong to the right halo);
+    // later wavefronts (a tile narrower than BX) only take part in the
+    // barriers.  Threads whose column lies past the right halo
     // duplicate its last column: they load what its owner loads, write their
     // LDS values to the padding column and store nothing.  cxo: column
     // relative to x0 (-H .. w + H - 1); act: owns tile column x0 + cxo.
     const int l = threadIdx.x;
     const int wv = __builtin_amdgcn_readfirstlane(l) / kWave;  // wavefront index (uniform)
-    const int full = w / kWave;
+    constexpr int LC = ST == ST_PLAIN ? 32 : 64;  // columns per 128-byte line of the storage
+    const int xa = (LC - x0 % LC) % LC;
+    const int hd = xa <= w && (w - kWave * ((w - xa) / kWave)) + 2 * H <= kWave ? xa : 0;
+    const int full = (w - hd) / kWave;
     const int C = (w - kWave * full) + 2 * H <= kWave ? kWave * full : kWave * (full + 1);
     const int hw = C / kWave;  // the halo wavefront
     const int hl = l - C;      // lane in the halo wavefront
-    const int craw = wv < hw ? l : (hl < H ? hl - H : C + hl - H);
+    const int craw = wv < hw ? hd + l : (hl < H + hd ? hl - H : C + hl - H);
     const bool dup = craw > w + H - 1;
     const int cxo = min(craw, w + H - 1);
     const bool act = cxo >= 0 && cxo < w && !dup;

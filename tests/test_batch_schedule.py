@@ -26,8 +26,8 @@ def test_benchmark_list_without_deadlock_at_any_residency(workers):
     verdict, ran = lbac.batch_schedule_check(shapes, [48] * 256, 40, workers, seed=workers)
     assert verdict == 0, verdict
     strips = [max(1, min(int(ny / 40 + 0.5), ny // 8)) for _, ny in shapes]  # nearest count, balanced heights
-    items_min = sum(-(-nx // 224) * s for (nx, _), s in zip(shapes, strips))
-    items_max = sum(-(-nx // 32) * s for (nx, _), s in zip(shapes, strips))
+    items_min = sum(-(-nx // 240) * s for (nx, _), s in zip(shapes, strips))
+    items_max = sum(-(-nx // 16) * s for (nx, _), s in zip(shapes, strips))
     assert items_min * 16 <= ran <= items_max * 16 and ran % 16 == 0
 
 
@@ -38,7 +38,7 @@ def test_uneven_lengths_ragged_grids_and_remainder_passes(seed):
     heights and residencies."""
     rng = np.random.default_rng(seed)
     shapes = [(int(a), int(b)) for a, b in zip(rng.integers(3, 300, 12), rng.integers(3, 300, 12))]
-    shapes += [(1, 64), (64, 1), (5, 3), (224, 224), (225, 41)]
+    shapes += [(1, 64), (64, 1), (5, 3), (224, 224), (225, 41), (240, 33), (496, 40), (512, 24)]
     nsteps = [int(v) for v in rng.integers(0, 40, len(shapes))]
     for strip_h in (8, 13, 40):
         for workers in (1, 3, 40):

@@ -47,7 +47,8 @@ def test_bitwise_equal_to_one_step_kernels(gpu_lib, model, variant):
     base = run(gpu_lib, case, phi0, 13, (256, 64, 0)).phi()
     fw = full_widths(variant)
     for bx, strip in ((256, 64), (64, 5), (128, 320), (256, 1), (64, 17), (128, 2), (256, 3), (192, 40), (320, 7),
-                      (192, 1), (320, 320), (fw[1], 9), (fw[2], 64), (fw[3], 1), (fw[2], 320), (fw[2], 2), (fw[0], 11)):
+                      (192, 1), (320, 320), (fw[1], 9), (fw[2], 64), (fw[3], 1), (fw[2], 320), (fw[2], 2), (fw[0], 11),
+                      (240, 9), (240, 320)):
         phi = run(gpu_lib, case, phi0, 13, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -62,7 +63,7 @@ def test_ragged_and_degenerate_grids(gpu_lib, nx, ny, variant):
     base = run(gpu_lib, case, phi0, 11, (64, 7, 0)).phi()
     fw = full_widths(variant)
     for bx, strip in ((64, 7), (128, 4), (256, 1), (64, 64), (256, 2), (192, 3), (320, 5), (fw[2], 4), (fw[1], 13),
-                      (fw[3], 2), (fw[0], 6)):
+                      (fw[3], 2), (fw[0], 6), (240, 5)):
         phi = run(gpu_lib, case, phi0, 11, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip, variant)
 
@@ -158,7 +159,7 @@ def test_shifted_storage_bitwise_over_launch_shapes(gpu_lib, prec, variant):
     case = W.single_vortex_case(320, U=0.05, period_T=100.0)
     phi0 = W.circle(320, 1.0)
     base = run16(gpu_lib, prec, case, phi0, 12, (224, 40, variant)).phi()
-    for bx, strip in ((256, 64), (64, 5), (128, 320), (96, 1), (160, 9), (320, 7), (192, 3)):
+    for bx, strip in ((256, 64), (64, 5), (128, 320), (96, 1), (160, 9), (320, 7), (192, 3), (240, 11), (240, 1)):
         phi = run16(gpu_lib, prec, case, phi0, 12, (bx, strip, variant)).phi()
         assert np.array_equal(phi, base), (bx, strip)
 
@@ -207,7 +208,7 @@ def test_shifted_storage_reflection_symmetry(gpu_lib, prec):
 
 
 def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
-    """Tiles of 96, 160, 192, 224, 288 and 320 columns exist for the
+    """Tiles of 96, 160, 192, 224, 240, 288 and 320 columns exist for the
     multi-step kernels only; the one-step launches such a
     context makes (a remainder, or with the closure on) use 256-column tiles,
     bit for bit the same."""
@@ -215,7 +216,7 @@ def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
     phi0 = W.circle(200, 1.0)
     sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
     for variant in (0, 1, 2):
-        for bx in [192, 320] + full_widths(FUSED3):
+        for bx in [192, 240, 320] + full_widths(FUSED3):
             with pytest.raises(gpu_lib.LbacError):
                 sim.set_launch(bx, 16, variant)
     for variant in VARIANTS:
@@ -225,7 +226,7 @@ def test_tile_widths_of_the_multi_step_kernels_only(gpu_lib):
     sim.close()
     base = run(gpu_lib, case, phi0, 7, (256, 16, 0)).phi()
     for variant in VARIANTS:
-        for bx in [192, 320] + full_widths(variant):
+        for bx in [192, 240, 320] + full_widths(variant):
             assert np.array_equal(run(gpu_lib, case, phi0, 7, (bx, 16, variant)).phi(), base), (bx, variant)
 
 
