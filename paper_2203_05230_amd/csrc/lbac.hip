@@ -225,8 +225,8 @@ bool one_step_bx(int bx) { return bx == 64 || bx == 128 || bx == 256; }
 
 // Tile widths of the S-step kernels: multiples of 32 columns from 64 to 320,
 // and 240 (the widest tile whose grown columns, bx + 4S at S = 3, fill four
-// wavefronts; its odd tiles start half a line in, and their head columns go to
-// the halo wavefront).
+// wavefronts; tiles that start off a 128-byte line of the storage, every
+// other one in FP32, give their head columns to the halo wavefront).
 bool stepS_bx(int bx) { return (bx >= 64 && bx <= 320 && bx % 32 == 0) || bx == 240; }
 
 hipError_t launch_step(const lbac_ctx* h, int src, int32_t k) {
