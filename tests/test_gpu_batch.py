@@ -89,6 +89,37 @@ def test_batch_16bit_storage_bitwise_equals_single_instances(gpu_lib, precision)
     b.close()
 
 
+@pytest.mark.parametrize("precision", ["f32", "f32_f16store", "f32_bf16store"])
+def test_batch_tiles_off_the_lines_bitwise(gpu_lib, precision):
+    """Instances cut into 240-column tiles whose second tile starts off a
+    128-byte line of the storage (x0 = 240: 960 bytes in FP32, 480 in 16-bit),
+    so the tile function hands the head columns to its halo wavefront, and
+    ragged last tiles of 20 to 160 columns; a 960-column instance also has
+    16-bit tiles that start half a line and a quarter of a line in: bitwise
+    the single runs."""
+    say("case: batch tiles off the lines,", precision)
+    shapes = [(500, 40, 10), (272, 33, 7), (400, 24, 12), (336, 50, 5), (960, 20, 5)]
+    cases, phis, steps = [], [], []
+    for i, (nx, ny, n) in enumerate(shapes):
+        rng = np.random.default_rng(40 + i)
+        phi = W.circle(max(nx, ny), 1.0, R_frac=0.3, yc_frac=0.5)[:ny, :nx] * 0.9 + 0.05 * rng.random((ny, nx))
+        if i % 2:
+            c = dict(nx=nx, ny=ny, eps=1.0, tau=0.8, delta=1e-10, vel="uniform", ux=0.03, uy=-0.021)
+        else:
+            c = dict(nx=nx, ny=ny, eps=1.0, tau=0.7, delta=1e-10, vel="vortex", U=0.03, period_T=100.0)
+        cases.append(c), phis.append(np.ascontiguousarray(phi)), steps.append(n)
+    b = gpu_lib.Batch(cases, phis, precision=precision)
+    b.set_shape(16)
+    b.run(steps)
+    for k, (c, p, n) in enumerate(zip(cases, phis, steps)):
+        sim = gpu_lib.Simulation({**c, "precision": precision}, p)
+        sim.set_launch(224, 40, 4)
+        sim.step(n)
+        assert np.array_equal(b.instance(k).phi(), sim.phi()), (k, precision)
+        sim.close()
+    b.close()
+
+
 @pytest.mark.parametrize("strip_h", [8, 9, 32, 64, 128])
 def test_batch_shapes_and_continuation(gpu_lib, strip_h):
     say("case: batch strip height", strip_h)
