@@ -44,13 +44,13 @@ struct ItemH {
 };
 
 // Column tiles of an instance nx columns wide: widths that are multiples of 16
-// columns (every tile starts on a 64-byte boundary in FP32 storage, 32 bytes in
-// 16-bit storage; the tile function gives the columns before the first
-// 128-byte line to its halo wavefront), at most
-// kBatchTile, the last one ragged; chosen to minimise the wavefronts that run
-// per row (ceil((w + 4S) / 64) per tile), then the number of tiles, the
-// widest tiles first (a 512-column instance: 240 + 240 + 32, nine wavefronts
-// per row against ten with multiples of 32).
+// columns (every tile starts on a 64-byte boundary in FP32 storage, 32 bytes
+// in 16-bit storage; the tile function gives the columns before the first
+// 128-byte line to its halo wavefront), at most kBatchTile, the last one
+// ragged; chosen to minimise the wavefronts that run per row
+// (ceil((w + 4S) / 64) per tile), then the number of tiles, the widest tiles
+// first (a 512-column instance: 240 + 240 + 32, nine wavefronts per row
+// against ten with multiples of 32).
 std::vector<std::pair<int, int>> column_tiles(int nx) {
     constexpr int U = 16;
     const int n = (nx + U - 1) / U;
