@@ -671,7 +671,7 @@ int lbac_batch_autotune(lbac_batch* b, const int64_t* nsteps, double* ms) {
     const int count = (int)b->inst.size();
     std::vector<int64_t> ns(nsteps, nsteps + count);
     const int keep_h = b->strip_h;
-    const int hs[10] = {16, 24, 32, 40, 48, 64, 80, 96, 128, 192};
+    const int hs[13] = {16, 24, 32, 40, 48, 56, 64, 72, 80, 88, 96, 128, 192};
     float best = 1e30f;
     int best_h = keep_h;
     for (int h : hs) {
