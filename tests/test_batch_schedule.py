@@ -59,6 +59,17 @@ def test_full_length_schedule_of_a_reduced_list():
     assert max(nsteps) > 3 * min(nsteps)
 
 
+@pytest.mark.parametrize("nx,tiles", [(512, 3), (500, 3), (480, 2), (384, 2), (256, 2), (241, 2), (240, 1),
+                                       (192, 1), (32, 1), (1000, 5)])
+def test_column_tiles_of_an_instance(nx, tiles):
+    """Column tiles of at most 240 columns in multiples of 16, chosen for the
+    fewest wavefronts per row, then the fewest tiles: 480 columns take two
+    tiles (three with 224-column tiles), 512 three (240 + 240 + 32).  One
+    strip and 48 steps (16 full passes) run 16 slots per tile."""
+    verdict, ran = lbac.batch_schedule_check([(nx, 40)], [48], 40, 4, seed=1)
+    assert verdict == 0 and ran == 16 * tiles
+
+
 def test_rejects_bad_sizes():
     with pytest.raises(lbac.LbacError):
         lbac.batch_schedule_check([(16, 16)], [3], 4, 1)  # strip below the minimum
