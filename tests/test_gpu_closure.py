@@ -155,7 +155,7 @@ def test_closure_is_deterministic_across_launches_and_graphs(gpu_lib, nx, ny):
     # multi-step launches at 224 columns)
     for launch, graph in (((256, 16, 0), 0), ((128, 7, 2), 0), ((64, 33, 1), 0), ((256, 64, 0), 8), ((128, 16, 3), 0),
                           ((256, 32, 3), 6), ((64, 16, 4), 0), ((224, 40, 4), 0), ((160, 9, 4), 0), ((192, 13, 4), 6),
-                          ((224, 8, 3), 0), ((128, 200, 4), 0)):
+                          ((224, 8, 3), 0), ((128, 200, 4), 0), ((240, 24, 4), 0), ((240, 11, 3), 6)):
         sim = gpu_lib.Simulation({**case, "precision": "f32"}, phi0)
         sim.set_launch(*launch)
         if graph:
