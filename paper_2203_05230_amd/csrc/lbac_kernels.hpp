@@ -496,6 +496,7 @@ struct Io<float, ST_BF16> : IoShifted<__hip_bfloat16> {
 struct IoCoherent {
     static constexpr bool kShifted = false;
     static constexpr int kSc1 = 16;  // cache-policy operand: sc1 (device scope)
+    static constexpr int kNt = 2;    // cache-policy operand: nt (non-temporal)
     __amdgpu_buffer_rsrc_t sr, dr;
     uint32_t pb[9];  // byte offset of the plane read and written for population q
     // the bases and the stride pass through readfirstlane: they are uniform,
@@ -520,10 +521,14 @@ struct IoCoherent {
         for (int q = 0; q < 9; ++q)
             v[q] = __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(sr, (int)b, (int)pb[q], kSc1));
     }
+    // device-scope stores with the non-temporal hint (the hint leaves the
+    // scope alone: the stored rows are not read again in the pass, and the L2
+    // keeps the rows and halo columns other items read)
     __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float /*phi*/) const {
         const uint32_t b = on ? off * 4u : kDropOffset;
 #pragma unroll
-        for (int q = 0; q < 9; ++q) __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), dr, (int)b, (int)pb[q], kSc1);
+        for (int q = 0; q < 9; ++q)
+            __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v[q]), dr, (int)b, (int)pb[q], kSc1 | kNt);
     }
 };
 
@@ -560,15 +565,16 @@ struct IoCoherentShifted {
             v[q] = __builtin_fmaf(wq<float>(q), ph, h2f<H>(__builtin_bit_cast(H, g)));
         }
     }
-    // stores g_i = v_i - w_i phi and phi* = phi when `on`
+    // stores g_i = v_i - w_i phi and phi* = phi when `on` (device scope,
+    // non-temporal, as IoCoherent)
     __device__ __forceinline__ void store_nt(bool on, uint32_t off, const float (&v)[9], float phi) const {
         const uint32_t b2 = on ? off * 2u : kDropOffset, b4 = on ? off * 4u : kDropOffset;
 #pragma unroll
         for (int q = 1; q < 9; ++q)
             __builtin_amdgcn_raw_buffer_store_b16(
                 __builtin_bit_cast(unsigned short, f2h<H>(__builtin_fmaf(-wq<float>(q), phi, v[q]))), dg, (int)b2,
-                (int)pb[q], kSc1);
-        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(phi), dp, (int)b4, 0, kSc1);
+                (int)pb[q], kSc1 | IoCoherent::kNt);
+        __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(phi), dp, (int)b4, 0, kSc1 | IoCoherent::kNt);
     }
 };
 
